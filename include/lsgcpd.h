@@ -1,0 +1,215 @@
+/*
+ * lsgcpd.h -- C ABI of the MI355X (gfx950) LSG-CPD library.
+ *
+ * LSG-CPD (Liu, Wu, Chirikjian, ICCV 2021) registers a source cloud X (N x 3)
+ * to a target cloud Y (M x 3) by EM on a Gaussian mixture built on the target:
+ * one component per target point with inverse covariance
+ * sigma^-2 (alpha_m n_m n_m^T + I) (Sec. 3.1, Eq. 2), alpha_m set from the local
+ * surface variation (Eq. 3), plus a uniform outlier component (Eq. 1).
+ *
+ * Conventions shared by every call:
+ *  - Arrays named X, Y, normals, kappa, alpha, pi, w, P, colstats are DEVICE
+ *    pointers owned by the caller (hipMalloc'd or torch CUDA tensors), row-major
+ *    and contiguous.  Point clouds are float32 [n][3].  Structs (poses,
+ *    parameters, results, reports) are HOST memory owned by the caller.
+ *  - The library owns only the workspace inside an lsgcpd_ctx; it grows on
+ *    demand, is reused across calls and is released by lsgcpd_ctx_destroy.
+ *    No caller pointer is retained after a call returns.
+ *  - Every call returns an lsgcpd_status; nothing throws across the ABI.  On
+ *    a non-OK status the outputs are unspecified and lsgcpd_last_error(ctx)
+ *    holds a message.  Invalid arguments are rejected before any GPU work.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  lsgcpd_normals is
+ *    asynchronous on it; lsgcpd_estep and lsgcpd_register synchronise it before
+ *    filling their host outputs.
+ *  - A context is not thread-safe: use one context per host thread.
+ *  - The pose g = (R, t) maps the source into the target frame,
+ *    g(x) = R x + t, with R row-major.
+ */
+#ifndef LSGCPD_H
+#define LSGCPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSGCPD_ABI_VERSION 1
+
+typedef struct lsgcpd_ctx lsgcpd_ctx;
+typedef void *lsgcpd_stream;  /* a hipStream_t */
+
+typedef enum {
+  LSGCPD_OK = 0,
+  LSGCPD_E_INVALID = 1,     /* bad argument (NULL pointer, size, range)      */
+  LSGCPD_E_HIP = 2,         /* a HIP runtime call failed (no device, launch) */
+  LSGCPD_E_NOMEM = 3,       /* workspace allocation failed                   */
+  LSGCPD_E_NUMERIC = 4,     /* non-finite variance or pose                   */
+  LSGCPD_E_UNSUPPORTED = 5  /* size or option this build does not handle     */
+} lsgcpd_status;
+
+/* Flags for lsgcpd_estep / lsgcpd_params.flags */
+#define LSGCPD_EXACT_NORMALIZER 1u  /* multiply each component by sqrt(1+alpha_m),
+                                       the determinant factor of Eq. 2 that the
+                                       printed E step (Eq. 9-10) leaves out */
+#define LSGCPD_ACCUM_VALU 2u        /* accumulate on the vector ALU instead of
+                                       the FP64 matrix cores (same results to
+                                       rounding; for comparison only)          */
+
+typedef struct {
+  double R[9]; /* row-major rotation */
+  double t[3];
+} lsgcpd_pose;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` (it becomes current on this host
+ * thread).  Returns LSGCPD_E_HIP if the device cannot be opened. */
+lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out);
+/* Frees the workspace and the context.  NULL is a no-op. */
+void lsgcpd_ctx_destroy(lsgcpd_ctx *ctx);
+/* Message for the last failed call on ctx ("" if none).  Owned by ctx. */
+const char *lsgcpd_last_error(const lsgcpd_ctx *ctx);
+/* Static name of a status code. */
+const char *lsgcpd_status_string(lsgcpd_status s);
+int lsgcpd_abi_version(void);
+
+/* ---- target geometry (Sec. 3.1, Eq. 3) --------------------------------- */
+
+/* Surface normal n_m, surface variation kappa_m and penalty alpha_m of every
+ * target point.  The neighbourhood of y_m is its k nearest points of Y by
+ * Euclidean distance (itself included, ties to the lower index, distances
+ * compared in float32); its covariance about the neighbourhood mean (weight
+ * 1/k) is eigen-decomposed in FP64: n_m = unit eigenvector of the smallest
+ * eigenvalue (sign arbitrary), kappa_m = smallest eigenvalue / trace (in
+ * [0, 1/3]; 1/3 and n = e_z for a zero trace), and
+ * alpha_m = alpha_max (1 - e^{lambda(3 - 1/kappa)}) / (1 + e^{lambda(3 - 1/kappa)})
+ * (alpha_max at kappa = 0, never negative).
+ * Y: M x 3 float32.  Outputs: normals M x 3, kappa M (may be NULL), alpha M,
+ * all float32.  Requires 1 <= k <= min(M, 32), alpha_max >= 0, lambda > 0.
+ * Asynchronous on `stream`. */
+lsgcpd_status lsgcpd_normals(lsgcpd_ctx *ctx, const float *Y, int64_t M, int32_t k,
+                             double alpha_max, double lambda, float *normals,
+                             float *kappa, float *alpha, lsgcpd_stream stream);
+
+/* ---- one E step (Sec. 3.1 Eq. 5, Sec. 3.4 Eq. 9) ------------------------ */
+
+/* Sufficient statistics of the posterior.  With x~_n = (x_n, 1),
+ * M_m = I + alpha_m n_m n_m^T, and per source n
+ *   p_n = sum_m P_mn,  W_n = sum_m P_mn alpha_m n_m n_m^T,
+ *   B_n = sum_m P_mn M_m y_m,  C_n = sum_m P_mn y_m^T M_m y_m,
+ * the array `stats` holds, in this order (FP64):
+ *   [0..9]    S0 = sum_n p_n x~ x~^T         upper triangle of the 4x4, rows
+ *                                             (00 01 02 03 11 12 13 22 23 33)
+ *   [10..69]  S1[ab] = sum_n W_n[a][b] x~ x~^T for ab = 00 01 02 11 12 22,
+ *                                             10 values each, same order
+ *   [70..81]  S2 = sum_n B_n x~^T            3x4 row-major
+ *   [82]      S3 = sum_n C_n
+ *   [83]      sum_n log(sum_m K_mn + gamma)
+ *   [84]      sum_n gamma / (sum_m K_mn + gamma)     (expected outliers)
+ *   [85]      sum_n log w_n
+ * For G = [R | t] (3x4) the M-step objective is the quadratic
+ *   sum_mn P_mn d_mn(G) = sum_ab G_a^T (delta_ab S0 + S1[ab]) G_b
+ *                          - 2 <S2, G> + S3,
+ * d_mn(G) = (G x~_n - y_m)^T M_m (G x~_n - y_m). */
+#define LSGCPD_NSTATS 86
+
+typedef struct {
+  double sigma2, gamma, V;   /* values used; gamma = (2 pi sigma2)^{3/2} / V   */
+  double sumP;               /* N_P = sum_mn P_mn                              */
+  double outlier_mass;       /* sum_n gamma / (sum_m K_mn + gamma)            */
+  double nll;                /* Eq. 4 at the given pose                        */
+  double pd;                 /* sum_mn P_mn d_mn at the given pose             */
+  double stats[LSGCPD_NSTATS];
+  double grad[6];            /* Eq. 11 at the given pose (right derivatives of
+                                sum P d / sigma2, basis: rotations about x, y,
+                                z, then translations along x, y, z)            */
+  double hess[36];           /* (H + H^T)/2 of Eq. 12, row-major               */
+  lsgcpd_pose pose_next;     /* M step (Sec. 3.5) from the given pose          */
+  double sigma2_next;        /* sigma^2 after that M step                      */
+  int32_t newton_iters;
+  int32_t gn_fallbacks;
+} lsgcpd_estep_out;
+
+/* One E step at pose g and variance sigma2, plus the M step it implies.
+ *   X: N x 3, Y: M x 3, normals: M x 3 (unit), alpha: M (>= 0), float32.
+ *   pi: M priors (NULL => 1/M), w: N outlier weights in (0,1) (NULL => w0).
+ *   V > 0 working volume (<= 0 => target box volume, edges floored at 1e-3 of
+ *   its diagonal).  flags: LSGCPD_EXACT_NORMALIZER, LSGCPD_ACCUM_VALU.
+ *   Posterior P_mn = K_mn / (sum_m K_mn + gamma), K_mn = (1-w_n)/w_n pi_m
+ *   exp(-d_mn / (2 sigma2)) with d_mn = |g(x_n) - y_m|^2 + alpha_m (n_m .
+ *   (g(x_n) - y_m))^2 (Eq. 9-10).  The M x N matrix is never formed unless
+ *   `P` is non-NULL (testing aid: float32 M x N, row m = component).
+ *   colstats: NULL or N x 16 FP64 per-source values
+ *   [sum_m K_mn/rho_n, sum_m K_mn, p_n, W_n (00 01 02 11 12 22), B_n (3), C_n,
+ *    log(sum_m K_mn + gamma), gamma/(sum_m K_mn + gamma), 0]
+ *   with rho_n = (1 - w_n)/w_n.
+ * Requires M, N >= 1, 0 < w0 < 1 when w is NULL, finite sigma2 > 0, R a
+ * rotation (|R^T R - I| <= 1e-6).  Synchronises `stream`. */
+lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
+                           const float *normals, const float *alpha, int64_t M,
+                           const float *pi, const float *w, double w0, double V,
+                           const lsgcpd_pose *g, double sigma2, uint32_t flags,
+                           lsgcpd_estep_out *out, float *P, double *colstats,
+                           lsgcpd_stream stream);
+
+/* ---- full registration (Sec. 3) ----------------------------------------- */
+
+typedef struct {
+  int32_t k;             /* neighbourhood size for the normals (<= 32)       */
+  double alpha_max;      /* Eq. 3 upper bound                                 */
+  double lambda;         /* Eq. 3 sensitivity                                 */
+  double w0;             /* uniform outlier weight, 0 < w0 < 1                */
+  double V;              /* working volume; <= 0 => target box volume         */
+  int32_t max_iter;      /* EM iterations                                      */
+  double tol;            /* > 0: stop once |L_i - L_{i-1}| <= tol |L_i|       */
+  double sigma2_init;    /* <= 0 => sum_mn |g0(x_n) - y_m|^2 / (3 M N)        */
+  int32_t newton_max;    /* Newton steps per M step (>= 1)                     */
+  uint32_t flags;        /* LSGCPD_EXACT_NORMALIZER, LSGCPD_ACCUM_VALU         */
+} lsgcpd_params;
+
+typedef struct {
+  int32_t iters;         /* M steps taken                                      */
+  int32_t converged;     /* 1 if the tol criterion stopped EM                  */
+  int32_t gn_fallbacks;  /* M-step Newton steps that used the Gauss-Newton term */
+  double sigma2;         /* final sigma^2                                      */
+  double nll_first, nll_last;
+  double V;
+} lsgcpd_report;
+
+/* Fills p with the defaults used by the examples: k=10, alpha_max=30,
+ * lambda=0.2, w0=0.1, V=0, max_iter=50, tol=0, sigma2_init=0, newton_max=20. */
+void lsgcpd_params_default(lsgcpd_params *p);
+
+/* Registers X (N x 3) to Y (M x 3): normals from Y (lsgcpd_normals), then EM
+ * from `init` (NULL => identity).  `out` receives the final pose.  nll_trace:
+ * NULL or a host array of max_iter doubles receiving Eq. 4 at each E step
+ * (entries after the last E step are left untouched).  Synchronises
+ * `stream`. */
+lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
+                              int64_t M, const lsgcpd_params *p, const lsgcpd_pose *init,
+                              lsgcpd_pose *out, lsgcpd_report *report, double *nll_trace,
+                              lsgcpd_stream stream);
+
+/* ---- kernel timing (benchmarks) ----------------------------------------- */
+
+/* Event-based timing of the E step inside lsgcpd_estep / lsgcpd_register.
+ * While enabled, every E step records HIP events on the call's stream around
+ * (a) the pair kernel (exponents + feature accumulation) and (b) the whole
+ * E step (pair kernel + per-source finalisation + block reduction).  Elapsed
+ * times are summed when the call synchronises.  Off by default. */
+typedef struct {
+  int64_t launches;      /* E steps timed                                   */
+  int64_t pairs;         /* sum of M * N over those E steps                 */
+  double pair_kernel_ms; /* total time of (a)                               */
+  double estep_ms;       /* total time of (b)                               */
+} lsgcpd_profile;
+
+lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on);
+/* Copies the totals into *out (may be NULL) and, if reset != 0, zeroes them. */
+lsgcpd_status lsgcpd_profile_read(lsgcpd_ctx *ctx, lsgcpd_profile *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSGCPD_H */

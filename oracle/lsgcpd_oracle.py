@@ -94,7 +94,7 @@ def local_geometry(Y, nbr):
     lam, vec = np.linalg.eigh(C)                   # ascending eigenvalues
     tr = np.trace(C, axis1=1, axis2=2)
     n = vec[:, :, 0].copy()
-    kappa = np.empty(Y.shape[0])
+    kappa = np.empty(nbr.shape[0])
     deg = tr <= 0.0
     kappa[~deg] = lam[~deg, 0] / tr[~deg]
     kappa[deg] = 1.0 / 3.0
@@ -404,6 +404,29 @@ def pd_of(cols, X, R, t):
     Xg = _f64(X) @ _f64(R).T + _f64(t)
     return float(np.sum(np.einsum("ni,nij,nj->n", Xg, cols.A, Xg)
                         - 2.0 * np.einsum("ni,ni->n", Xg, cols.B) + cols.C))
+
+
+def lifted_stats(cols, X, nll_terms=None):
+    """The 86 sufficient statistics the GPU library reports for one E step,
+    written from their definitions (x~_n = (x_n, 1), p, W = A - p I, B, C the
+    per-source aggregates of Columns):
+      S0 = sum_n p_n x~ x~^T, S1[ab] = sum_n W_n[a,b] x~ x~^T (ab = 00 01 02 11
+      12 22), S2 = sum_n B_n x~^T, S3 = sum_n C_n, then the three NLL terms.
+    Upper-triangle order of a 4x4: 00 01 02 03 11 12 13 22 23 33."""
+    X = _f64(X)
+    xt = np.hstack([X, np.ones((X.shape[0], 1))])
+    iu = [(i, j) for i in range(4) for j in range(i, 4)]
+    xx = np.stack([xt[:, i] * xt[:, j] for (i, j) in iu], axis=1)     # (N, 10)
+    W = cols.A - cols.p[:, None, None] * np.eye(3)[None]
+    out = np.zeros(86)
+    out[0:10] = cols.p @ xx
+    for k, (a, b) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        out[10 + 10 * k:20 + 10 * k] = W[:, a, b] @ xx
+    out[70:82] = (cols.B.T @ xt).reshape(12)
+    out[82] = float(np.sum(cols.C))
+    if nll_terms is not None:
+        out[83:86] = nll_terms
+    return out
 
 
 @dataclass

@@ -1,0 +1,311 @@
+"""Python binding of liblsgcpd, the MI355X (gfx950) LSG-CPD library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+liblsgcpd.so (include/lsgcpd.h).  Arrays are torch CUDA (HIP) float32 tensors;
+torch provides device memory and the current stream, nothing else.  The module
+raises if the shared library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsgcpd.so")
+
+OK, E_INVALID, E_HIP, E_NOMEM, E_NUMERIC, E_UNSUPPORTED = range(6)
+EXACT_NORMALIZER = 1
+ACCUM_VALU = 2
+NSTATS = 86
+
+SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
+           "lsgcpd_ctx_destroy", "lsgcpd_last_error", "lsgcpd_params_default",
+           "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_profile_enable",
+           "lsgcpd_profile_read")
+
+
+class Pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class EstepOut(C.Structure):
+    _fields_ = [("sigma2", C.c_double), ("gamma", C.c_double), ("V", C.c_double),
+                ("sumP", C.c_double), ("outlier_mass", C.c_double), ("nll", C.c_double),
+                ("pd", C.c_double), ("stats", C.c_double * NSTATS), ("grad", C.c_double * 6),
+                ("hess", C.c_double * 36), ("pose_next", Pose), ("sigma2_next", C.c_double),
+                ("newton_iters", C.c_int32), ("gn_fallbacks", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("alpha_max", C.c_double), ("lambda_", C.c_double),
+                ("w0", C.c_double), ("V", C.c_double), ("max_iter", C.c_int32),
+                ("tol", C.c_double), ("sigma2_init", C.c_double), ("newton_max", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("gn_fallbacks", C.c_int32),
+                ("sigma2", C.c_double), ("nll_first", C.c_double), ("nll_last", C.c_double),
+                ("V", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("pairs", C.c_int64), ("pair_kernel_ms", C.c_double),
+                ("estep_ms", C.c_double)]
+
+
+class LsgcpdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_STATUS = {OK: "LSGCPD_OK", E_INVALID: "LSGCPD_E_INVALID", E_HIP: "LSGCPD_E_HIP",
+           E_NOMEM: "LSGCPD_E_NOMEM", E_NUMERIC: "LSGCPD_E_NUMERIC",
+           E_UNSUPPORTED: "LSGCPD_E_UNSUPPORTED"}
+
+_lib = None
+_ctx = {}
+
+
+def load_library(path=LIB_PATH):
+    """Loads liblsgcpd.so and declares its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2103_15039_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    vp, i64, i32, u32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_double
+    lib.lsgcpd_abi_version.restype = C.c_int
+    lib.lsgcpd_status_string.restype = C.c_char_p
+    lib.lsgcpd_status_string.argtypes = [C.c_int]
+    lib.lsgcpd_ctx_create.restype = C.c_int
+    lib.lsgcpd_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.lsgcpd_ctx_destroy.restype = None
+    lib.lsgcpd_ctx_destroy.argtypes = [vp]
+    lib.lsgcpd_last_error.restype = C.c_char_p
+    lib.lsgcpd_last_error.argtypes = [vp]
+    lib.lsgcpd_params_default.restype = None
+    lib.lsgcpd_params_default.argtypes = [C.POINTER(Params)]
+    lib.lsgcpd_normals.restype = C.c_int
+    lib.lsgcpd_normals.argtypes = [vp, vp, i64, i32, d, d, vp, vp, vp, vp]
+    lib.lsgcpd_estep.restype = C.c_int
+    lib.lsgcpd_estep.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, d, d, C.POINTER(Pose), d,
+                                 u32, C.POINTER(EstepOut), vp, vp, vp]
+    lib.lsgcpd_register.restype = C.c_int
+    lib.lsgcpd_register.argtypes = [vp, vp, i64, vp, i64, C.POINTER(Params), C.POINTER(Pose),
+                                    C.POINTER(Pose), C.POINTER(Report), vp, vp]
+    lib.lsgcpd_profile_enable.restype = C.c_int
+    lib.lsgcpd_profile_enable.argtypes = [vp, C.c_int]
+    lib.lsgcpd_profile_read.restype = C.c_int
+    lib.lsgcpd_profile_read.argtypes = [vp, C.POINTER(Profile), C.c_int]
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def context(device=0):
+    """The library context of a HIP device (created on first use)."""
+    lib = load_library()
+    if device not in _ctx:
+        h = C.c_void_p()
+        st = lib.lsgcpd_ctx_create(int(device), C.byref(h))
+        if st != OK:
+            raise LsgcpdError(st, f"cannot open HIP device {device}")
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _check(st, ctx):
+    if st != OK:
+        raise LsgcpdError(st, load_library().lsgcpd_last_error(ctx).decode())
+
+
+def _dev_tensor(a, shape_tail=None, name="array", device=None):
+    torch = _torch()
+    if not isinstance(a, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if not a.is_cuda:
+        raise ValueError(f"{name} must be on a HIP device")
+    if a.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not a.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(a.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape (n, {', '.join(map(str, shape_tail))})")
+    if device is not None and a.device.index != device:
+        raise ValueError(f"{name} is on another device")
+    return a
+
+
+def _ptr(a):
+    return C.c_void_p(a.data_ptr()) if a is not None else C.c_void_p(0)
+
+
+def _stream(device):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _pose(R, t):
+    p = Pose()
+    R = np.asarray(R, dtype=np.float64).reshape(9)
+    t = np.asarray(t, dtype=np.float64).reshape(3)
+    for i in range(9):
+        p.R[i] = R[i]
+    for i in range(3):
+        p.t[i] = t[i]
+    return p
+
+
+def _pose_np(p):
+    return np.array(p.R[:], dtype=np.float64).reshape(3, 3), np.array(p.t[:], dtype=np.float64)
+
+
+def normals(Y, k=10, alpha_max=30.0, lam=0.2, with_kappa=True):
+    """Normals, surface variation and penalty alpha of every target point
+    (lsgcpd_normals).  Returns (normals (M,3), kappa (M,) or None, alpha (M,))."""
+    torch = _torch()
+    Y = _dev_tensor(Y, (3,), "Y")
+    dev = Y.device.index
+    M = Y.shape[0]
+    n = torch.empty((M, 3), dtype=torch.float32, device=Y.device)
+    kap = torch.empty((M,), dtype=torch.float32, device=Y.device) if with_kappa else None
+    al = torch.empty((M,), dtype=torch.float32, device=Y.device)
+    ctx = context(dev)
+    st = load_library().lsgcpd_normals(ctx, _ptr(Y), M, int(k), float(alpha_max), float(lam),
+                                       _ptr(n), _ptr(kap), _ptr(al), _stream(dev))
+    _check(st, ctx)
+    return n, kap, al
+
+
+@dataclass
+class EStepResult:
+    sigma2: float
+    gamma: float
+    V: float
+    sumP: float
+    outlier_mass: float
+    nll: float
+    pd: float
+    stats: np.ndarray
+    grad: np.ndarray
+    hess: np.ndarray
+    R_next: np.ndarray
+    t_next: np.ndarray
+    sigma2_next: float
+    newton_iters: int
+    gn_fallbacks: int
+    P: object = None          # torch (M, N) float32 if requested
+    colstats: object = None   # torch (N, 16) float64 if requested
+
+
+def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=False,
+          valu=False, dump_P=False, colstats=False):
+    """One E step and the M step it implies (lsgcpd_estep)."""
+    torch = _torch()
+    X = _dev_tensor(X, (3,), "X")
+    dev = X.device.index
+    Y = _dev_tensor(Y, (3,), "Y", dev)
+    nrm = _dev_tensor(nrm, (3,), "normals", dev)
+    alpha = _dev_tensor(alpha, None, "alpha", dev)
+    N, M = X.shape[0], Y.shape[0]
+    if nrm.shape[0] != M or alpha.numel() != M:
+        raise ValueError("normals and alpha must have one row per target point")
+    if pi is not None:
+        pi = _dev_tensor(pi, None, "pi", dev)
+        if pi.numel() != M:
+            raise ValueError("pi must have M entries")
+    if w is not None:
+        w = _dev_tensor(w, None, "w", dev)
+        if w.numel() != N:
+            raise ValueError("w must have N entries")
+    P = torch.empty((M, N), dtype=torch.float32, device=X.device) if dump_P else None
+    cs = torch.empty((N, 16), dtype=torch.float64, device=X.device) if colstats else None
+    flags = (EXACT_NORMALIZER if exact else 0) | (ACCUM_VALU if valu else 0)
+    out = EstepOut()
+    pose = _pose(R, t)
+    ctx = context(dev)
+    st = load_library().lsgcpd_estep(ctx, _ptr(X), N, _ptr(Y), _ptr(nrm), _ptr(alpha), M,
+                                     _ptr(pi), _ptr(w), float(w0), float(V), C.byref(pose),
+                                     float(sigma2), flags, C.byref(out), _ptr(P), _ptr(cs),
+                                     _stream(dev))
+    _check(st, ctx)
+    Rn, tn = _pose_np(out.pose_next)
+    return EStepResult(sigma2=out.sigma2, gamma=out.gamma, V=out.V, sumP=out.sumP,
+                       outlier_mass=out.outlier_mass, nll=out.nll, pd=out.pd,
+                       stats=np.array(out.stats[:]), grad=np.array(out.grad[:]),
+                       hess=np.array(out.hess[:]).reshape(6, 6), R_next=Rn, t_next=tn,
+                       sigma2_next=out.sigma2_next, newton_iters=out.newton_iters,
+                       gn_fallbacks=out.gn_fallbacks, P=P, colstats=cs)
+
+
+@dataclass
+class RegistrationResult:
+    R: np.ndarray
+    t: np.ndarray
+    sigma2: float
+    iters: int
+    converged: bool
+    gn_fallbacks: int
+    nll: np.ndarray
+    V: float
+
+
+def default_params():
+    p = Params()
+    load_library().lsgcpd_params_default(C.byref(p))
+    return p
+
+
+def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
+             sigma2_init=0.0, newton_max=20, exact=False, valu=False, R0=None, t0=None):
+    """Full LSG-CPD registration of X onto Y (lsgcpd_register)."""
+    X = _dev_tensor(X, (3,), "X")
+    dev = X.device.index
+    Y = _dev_tensor(Y, (3,), "Y", dev)
+    p = Params(k=int(k), alpha_max=float(alpha_max), lambda_=float(lam), w0=float(w0),
+               V=float(V), max_iter=int(max_iter), tol=float(tol),
+               sigma2_init=float(sigma2_init), newton_max=int(newton_max),
+               flags=(EXACT_NORMALIZER if exact else 0) | (ACCUM_VALU if valu else 0))
+    init = None
+    if R0 is not None or t0 is not None:
+        init = _pose(np.eye(3) if R0 is None else R0, np.zeros(3) if t0 is None else t0)
+    out = Pose()
+    rep = Report()
+    trace = (C.c_double * max(int(max_iter), 1))()
+    ctx = context(dev)
+    st = load_library().lsgcpd_register(ctx, _ptr(X), X.shape[0], _ptr(Y), Y.shape[0],
+                                        C.byref(p), C.byref(init) if init is not None else None,
+                                        C.byref(out), C.byref(rep), C.cast(trace, C.c_void_p),
+                                        _stream(dev))
+    _check(st, ctx)
+    R, t = _pose_np(out)
+    filled = rep.iters + rep.converged
+    return RegistrationResult(R=R, t=t, sigma2=rep.sigma2, iters=rep.iters,
+                              converged=bool(rep.converged), gn_fallbacks=rep.gn_fallbacks,
+                              nll=np.array(trace[:filled]), V=rep.V)
+
+
+def profile_enable(on=True, device=0):
+    """Turns event timing of the E-step kernels on or off (lsgcpd_profile_enable)."""
+    ctx = context(device)
+    _check(load_library().lsgcpd_profile_enable(ctx, 1 if on else 0), ctx)
+
+
+def profile_read(reset=True, device=0):
+    """Totals since the last reset: dict(launches, pairs, pair_kernel_ms, estep_ms)."""
+    ctx = context(device)
+    p = Profile()
+    _check(load_library().lsgcpd_profile_read(ctx, C.byref(p), 1 if reset else 0), ctx)
+    return {"launches": p.launches, "pairs": p.pairs, "pair_kernel_ms": p.pair_kernel_ms,
+            "estep_ms": p.estep_ms}

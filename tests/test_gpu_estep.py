@@ -1,0 +1,184 @@
+"""GPU parity of the E step (lsgcpd_estep) against the FP64 oracle.
+
+Tolerances (spec bar and the error model of the float32 exponent):
+  * posteriors: |P - P_ref| <= 1e-5 P_ref + 1e-10, element by element;
+  * per-source sums and the 86 statistics: |d| <= 2e-6 * (sum of |terms|);
+  * M step from identical E-step inputs: rotation <= 1e-4 deg,
+    translation <= 1e-6 * box diagonal, sigma^2 relative 1e-5.
+Inputs: seeded synthetic clouds (datagen); normals and alpha come from the
+oracle or from seeded random draws, never from the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import lsgcpd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2103_15039_amd")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _inputs(M, N, seed, oracle_normals=True, angle=30.0):
+    p = datagen.range_scanner_pair(trial=seed, M=M, N=N, angle_deg=angle)
+    Y32, X32 = p.Y, p.X
+    if oracle_normals and M >= 3:
+        n, _, a = O.normals(Y32, min(10, M), 30.0, 0.2)
+    else:
+        rng = np.random.default_rng(seed + 100)
+        n = datagen.random_unit_normals(rng, M).astype(np.float64)
+        a = rng.uniform(0.0, 30.0, size=M)
+    return X32, Y32, n.astype(np.float32), a.astype(np.float32), p
+
+
+def _near_pose(p, seed, ang=0.02, tr=0.01):
+    rng = np.random.default_rng(seed + 7)
+    R = datagen.random_rotation(rng, ang) @ p.R_gt
+    t = p.t_gt + rng.uniform(-tr, tr, size=3)
+    return R, t
+
+
+def _stat_scale(cols, X):
+    absc = O.Columns(p=np.abs(cols.p), A=np.abs(cols.A), B=np.abs(cols.B), C=np.abs(cols.C),
+                     b=cols.b, c=cols.c)
+    # |W| from |A| - |p| on the diagonal is not |A - p I|; recompute exactly
+    W = cols.A - cols.p[:, None, None] * np.eye(3)[None]
+    absc.A = np.abs(W) + np.abs(cols.p)[:, None, None] * np.eye(3)[None]
+    return O.lifted_stats(absc, np.abs(X))
+
+
+def _pair_floor(X, Y, nrm, alpha):
+    """Per-statistic sum over all pairs of |feature| |x~ x~^T|: the P-floor
+    of 1e-10 per pair bounds the statistic error by 1e-10 times this."""
+    M = len(Y)
+    n = nrm.astype(np.float64)
+    a = alpha.astype(np.float64)
+    Wabs = np.abs(a[:, None, None] * n[:, :, None] * n[:, None, :]).sum(axis=0)
+    My = Y + a[:, None] * np.sum(Y * n, axis=1)[:, None] * n
+    C = np.sum(Y * My, axis=1)
+    ones = O.Columns(p=np.full(len(X), float(M)),
+                     A=np.broadcast_to(Wabs + M * np.eye(3), (len(X), 3, 3)).copy(),
+                     B=np.broadcast_to(np.abs(My).sum(axis=0), (len(X), 3)).copy(),
+                     C=np.full(len(X), np.abs(C).sum()), b=None, c=None)
+    return O.lifted_stats(ones, np.abs(X))
+
+
+def _check_estep(X32, Y32, n32, a32, R, t, s2, w0=0.1, V=None, pi=None, w=None, exact=False,
+                 valu=False, check_P=True):
+    X = X32.astype(np.float64)
+    Y = Y32.astype(np.float64)
+    es = O.estep(X, Y, n32.astype(np.float64), a32.astype(np.float64), R, t, s2, w0=w0,
+                 V=V, pi=None if pi is None else pi.astype(np.float64),
+                 w=None if w is None else w.astype(np.float64), exact_normalizer=exact)
+    cols = O.columns(es.P, X, Y, n32.astype(np.float64), a32.astype(np.float64), R, t)
+    ww = np.full(len(X), w0) if w is None else w.astype(np.float64)
+    nll_terms = [np.sum(np.log(es.Ksum + es.gamma)), np.sum(es.gamma / (es.Ksum + es.gamma)),
+                 np.sum(np.log(ww))]
+    ref_stats = O.lifted_stats(cols, X, nll_terms)
+    g = L.estep(dev(X32), dev(Y32), dev(n32), dev(a32), R, t, s2, w0=w0,
+                V=0.0 if V is None else V, pi=None if pi is None else dev(pi),
+                w=None if w is None else dev(w), exact=exact, valu=valu, dump_P=check_P,
+                colstats=True)
+    assert g.V == pytest.approx(es.V, rel=1e-14)
+    assert g.gamma == pytest.approx(es.gamma, rel=1e-13)
+    if check_P:
+        P = g.P.double().cpu().numpy()
+        err = np.abs(P - es.P)
+        bound = 1e-5 * es.P + 1e-10
+        worst = np.unravel_index(np.argmax(err - bound), err.shape)
+        assert np.all(err <= bound), (f"P mismatch at {worst}: gpu {P[worst]:.9g} "
+                                      f"oracle {es.P[worst]:.9g}")
+    cs = g.colstats.cpu().numpy()
+    # a normaliser error d moves every P of the column by d / (Ksum + gamma)
+    assert np.all(np.abs(cs[:, 1] - es.Ksum) <= 1e-5 * (es.Ksum + es.gamma))
+    np.testing.assert_allclose(cs[:, 2], cols.p, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(cs[:, 13], np.log(es.Ksum + es.gamma), rtol=0, atol=2e-6)
+    # column identity: components + outlier = 1 for every source
+    np.testing.assert_allclose(cs[:, 2] + cs[:, 14], 1.0, rtol=0, atol=1e-12)
+    scale = _stat_scale(cols, X)
+    scale[83:] = np.abs(ref_stats[83:]) + len(X)
+    floor = _pair_floor(X, Y, n32, a32)
+    d = np.abs(g.stats - ref_stats)
+    bad = np.nonzero(d > 2e-6 * scale + 1e-10 * floor)[0]
+    assert bad.size == 0, f"stats {bad[:8]}: gpu {g.stats[bad[:4]]} ref {ref_stats[bad[:4]]}"
+    assert g.nll == pytest.approx(es.nll, rel=1e-6, abs=1e-6 * len(X))
+    assert g.sumP + g.outlier_mass == pytest.approx(len(X), rel=1e-12)
+    return g, es, cols
+
+
+@pytest.mark.parametrize("valu", [False, True], ids=["mfma", "valu"])
+@pytest.mark.parametrize("M,N", [(1, 1), (5, 3), (37, 53), (300, 517), (1000, 2500)])
+def test_estep_parity(M, N, valu):
+    X32, Y32, n32, a32, p = _inputs(M, N, seed=M + N)
+    R, t = _near_pose(p, M)
+    for s2 in (2e-4, 0.02):
+        g, es, cols = _check_estep(X32, Y32, n32, a32, R, t, s2, valu=valu)
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_estep_weights_priors_exact(exact):
+    X32, Y32, n32, a32, p = _inputs(400, 350, seed=3)
+    rng = np.random.default_rng(5)
+    pi = rng.uniform(0.5, 1.5, size=400).astype(np.float32)
+    pi /= pi.sum()
+    w = rng.uniform(0.02, 0.9, size=350).astype(np.float32)
+    R, t = _near_pose(p, 9)
+    _check_estep(X32, Y32, n32, a32, R, t, 1e-3, pi=pi, w=w, exact=exact, V=3.5)
+
+
+def test_estep_mstep_outputs():
+    X32, Y32, n32, a32, p = _inputs(800, 700, seed=11)
+    R, t = _near_pose(p, 2, ang=0.05, tr=0.03)
+    s2 = 5e-4
+    g, es, cols = _check_estep(X32, Y32, n32, a32, R, t, s2, check_P=False)
+    X = X32.astype(np.float64)
+    gr, H = O.grad_hess(cols, X, R, t, s2)
+    Hs = 0.5 * (H + H.T)
+    np.testing.assert_allclose(g.grad, gr, rtol=0, atol=2e-5 * np.abs(gr).max())
+    np.testing.assert_allclose(g.hess, Hs, rtol=0, atol=2e-5 * np.abs(Hs).max())
+    ms = O.mstep(cols, X, R, t, s2, sigma2_floor=1e-12 * O.bbox_diag(Y32) ** 2)
+    assert O.rotation_error_deg(g.R_next, ms.R) < 1e-4
+    assert O.translation_error(g.t_next, ms.t) < 1e-6 * O.bbox_diag(Y32)
+    assert g.sigma2_next == pytest.approx(ms.sigma2, rel=1e-5)
+    assert g.pd == pytest.approx(float(np.sum(cols.c)), rel=2e-6)
+
+
+def test_estep_far_offset_coordinates():
+    """Clouds 1e3 away from the origin: the split hi/lo residual keeps the
+    posterior within the bound."""
+    X32, Y32, n32, a32, p = _inputs(300, 300, seed=21)
+    off = np.array([1000.0, -700.0, 300.0])
+    Y32o = (Y32.astype(np.float64) + off).astype(np.float32)
+    X32o = (X32.astype(np.float64) + off).astype(np.float32)
+    R, t = _near_pose(p, 4)
+    t = t + off - R @ off
+    _check_estep(X32o, Y32o, n32, a32, R, t, 2e-4)
+
+
+def test_estep_deterministic():
+    X32, Y32, n32, a32, p = _inputs(1500, 3000, seed=31)
+    R, t = _near_pose(p, 5)
+    a = L.estep(dev(X32), dev(Y32), dev(n32), dev(a32), R, t, 1e-3, colstats=True)
+    b = L.estep(dev(X32), dev(Y32), dev(n32), dev(a32), R, t, 1e-3, colstats=True)
+    assert np.array_equal(a.stats, b.stats)
+    assert torch.equal(a.colstats, b.colstats)
+
+
+def test_estep_invalid_arguments():
+    X32, Y32, n32, a32, p = _inputs(20, 20, seed=1, oracle_normals=False)
+    args = (dev(X32), dev(Y32), dev(n32), dev(a32))
+    for kw in ({"w0": 0.0}, {"w0": 1.0}, {"sigma2": 0.0}, {"sigma2": float("nan")}):
+        s2 = kw.pop("sigma2", 1e-3)
+        with pytest.raises(L.LsgcpdError) as ei:
+            L.estep(*args, np.eye(3), np.zeros(3), s2, **kw)
+        assert ei.value.status == L.E_INVALID
+    with pytest.raises(L.LsgcpdError) as ei:
+        L.estep(*args, 2.0 * np.eye(3), np.zeros(3), 1e-3)
+    assert ei.value.status == L.E_INVALID
