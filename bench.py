@@ -36,11 +36,28 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--valu", action="store_true", help="VALU accumulation back end")
+    ap.add_argument("--backend", default="scalar", choices=["scalar", "lds", "mfma"],
+                    help="pair-kernel back end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pair-kernel launch")
+    ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_kernel(mib):
+    """A plain elementwise copy (read MIB MiB, write MIB MiB), three launches,
+    for scaling the HBM byte counters of a profiler run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel_bytes_read": n * 4, "copy_kernel_bytes_written": n * 4,
+                      "launches": 3}), flush=True)
 
 
 def cpu_baseline(p, nrm, alpha):
@@ -65,6 +82,9 @@ def cpu_baseline(p, nrm, alpha):
 
 def main():
     a = parse()
+    if a.copy_kernel:
+        copy_kernel(a.copy_kernel)
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the "
               "multi-GPU layout is a design note, not an implemented path", file=sys.stderr)
@@ -78,7 +98,7 @@ def main():
     M, N = len(p.Y), len(p.X)
     X = torch.from_numpy(p.X).cuda()
     Y = torch.from_numpy(p.Y).cuda()
-    kw = dict(k=20, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, valu=a.valu)
+    kw = dict(k=20, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, backend=a.backend)
     torch.cuda.synchronize()
     for _ in range(a.warmup):
         L.register(X, Y, **kw)
@@ -117,7 +137,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rgbd_20000x20000", "M": M, "N": N, "em_iters": EM_ITERS,
                    "knn": 20, "alpha_max": 30.0, "lambda": 0.2, "w0": 0.1,
-                   "accumulation": "valu_fp64" if a.valu else "mfma_fp64"},
+                   "pair_kernel": a.backend},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic},
         "estep": {"pair_kernel_ms": k_ms, "estep_ms": e_ms,

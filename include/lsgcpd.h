@@ -52,9 +52,11 @@ typedef enum {
 #define LSGCPD_EXACT_NORMALIZER 1u  /* multiply each component by sqrt(1+alpha_m),
                                        the determinant factor of Eq. 2 that the
                                        printed E step (Eq. 9-10) leaves out */
-#define LSGCPD_ACCUM_VALU 2u        /* accumulate on the vector ALU instead of
-                                       the FP64 matrix cores (same results to
-                                       rounding; for comparison only)          */
+#define LSGCPD_PAIRS_LDS 2u         /* pair kernel stages target records in LDS
+                                       instead of reading them through the
+                                       scalar cache (comparison only)           */
+#define LSGCPD_PAIRS_MFMA 4u        /* pair kernel accumulates on the FP64
+                                       matrix cores (comparison only)           */
 
 typedef struct {
   double R[9]; /* row-major rotation */
@@ -135,7 +137,7 @@ typedef struct {
  *   X: N x 3, Y: M x 3, normals: M x 3 (unit), alpha: M (>= 0), float32.
  *   pi: M priors (NULL => 1/M), w: N outlier weights in (0,1) (NULL => w0).
  *   V > 0 working volume (<= 0 => target box volume, edges floored at 1e-3 of
- *   its diagonal).  flags: LSGCPD_EXACT_NORMALIZER, LSGCPD_ACCUM_VALU.
+ *   its diagonal).  flags: LSGCPD_EXACT_NORMALIZER, LSGCPD_PAIRS_LDS or LSGCPD_PAIRS_MFMA.
  *   Posterior P_mn = K_mn / (sum_m K_mn + gamma), K_mn = (1-w_n)/w_n pi_m
  *   exp(-d_mn / (2 sigma2)) with d_mn = |g(x_n) - y_m|^2 + alpha_m (n_m .
  *   (g(x_n) - y_m))^2 (Eq. 9-10).  The M x N matrix is never formed unless
@@ -165,7 +167,7 @@ typedef struct {
   double tol;            /* > 0: stop once |L_i - L_{i-1}| <= tol |L_i|       */
   double sigma2_init;    /* <= 0 => sum_mn |g0(x_n) - y_m|^2 / (3 M N)        */
   int32_t newton_max;    /* Newton steps per M step (>= 1)                     */
-  uint32_t flags;        /* LSGCPD_EXACT_NORMALIZER, LSGCPD_ACCUM_VALU         */
+  uint32_t flags;        /* as for lsgcpd_estep                                 */
 } lsgcpd_params;
 
 typedef struct {

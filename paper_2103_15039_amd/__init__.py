@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "liblsgcpd.so")
 
 OK, E_INVALID, E_HIP, E_NOMEM, E_NUMERIC, E_UNSUPPORTED = range(6)
 EXACT_NORMALIZER = 1
-ACCUM_VALU = 2
+PAIRS_LDS = 2
+PAIRS_MFMA = 4
+_BACKENDS = {"scalar": 0, "lds": PAIRS_LDS, "mfma": PAIRS_MFMA}
 NSTATS = 86
 
 SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
@@ -210,7 +212,7 @@ class EStepResult:
 
 
 def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=False,
-          valu=False, dump_P=False, colstats=False):
+          backend="scalar", dump_P=False, colstats=False):
     """One E step and the M step it implies (lsgcpd_estep)."""
     torch = _torch()
     X = _dev_tensor(X, (3,), "X")
@@ -231,7 +233,7 @@ def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=
             raise ValueError("w must have N entries")
     P = torch.empty((M, N), dtype=torch.float32, device=X.device) if dump_P else None
     cs = torch.empty((N, 16), dtype=torch.float64, device=X.device) if colstats else None
-    flags = (EXACT_NORMALIZER if exact else 0) | (ACCUM_VALU if valu else 0)
+    flags = (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend]
     out = EstepOut()
     pose = _pose(R, t)
     ctx = context(dev)
@@ -268,7 +270,7 @@ def default_params():
 
 
 def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
-             sigma2_init=0.0, newton_max=20, exact=False, valu=False, R0=None, t0=None):
+             sigma2_init=0.0, newton_max=20, exact=False, backend="scalar", R0=None, t0=None):
     """Full LSG-CPD registration of X onto Y (lsgcpd_register)."""
     X = _dev_tensor(X, (3,), "X")
     dev = X.device.index
@@ -276,7 +278,7 @@ def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, to
     p = Params(k=int(k), alpha_max=float(alpha_max), lambda_=float(lam), w0=float(w0),
                V=float(V), max_iter=int(max_iter), tol=float(tol),
                sigma2_init=float(sigma2_init), newton_max=int(newton_max),
-               flags=(EXACT_NORMALIZER if exact else 0) | (ACCUM_VALU if valu else 0))
+               flags=(EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend])
     init = None
     if R0 is not None or t0 is not None:
         init = _pose(np.eye(3) if R0 is None else R0, np.zeros(3) if t0 is None else t0)

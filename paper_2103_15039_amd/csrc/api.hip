@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -29,7 +30,7 @@ struct Buf {
 struct lsgcpd_ctx {
   int device = 0;
   std::string err;
-  Buf knn, geo, feat, partial, blockstats, colS, mom_part, mom, nrm, kap, alp, trace;
+  Buf knn, rec, partial, blockstats, colS, mom_part, mom, nrm, kap, alp, trace;
   DevState *dstate = nullptr;  // device
   DevState *hstate = nullptr;  // pinned host staging
   // E-step timing: 3 events per E step (start, after pair kernel, end)
@@ -87,6 +88,28 @@ lsgcpd_status ensure(lsgcpd_ctx *ctx, Buf &b, size_t bytes) {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+constexpr uint32_t kKnownFlags = LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA;
+
+// Launch shape of the pair kernel: sources per lane (2 or 4) and target parts
+// per block (1, 2 or 4).  Defaults are the fastest measured on MI355X for the
+// 20k x 20k and 100k x 50k workloads; LSGCPD_PAIR_SOURCES / LSGCPD_PAIR_PARTS
+// override them for tuning sweeps.
+int pair_sources() {
+  const char *e = getenv("LSGCPD_PAIR_SOURCES");
+  return (e && atoi(e) == 2) ? 2 : 4;
+}
+
+int pair_parts() {
+  const char *e = getenv("LSGCPD_PAIR_PARTS");
+  return e ? atoi(e) : 4;
+}
+
+int backend_of(uint32_t flags) {
+  if (flags & LSGCPD_PAIRS_MFMA) return lsg::kBackendMfma;
+  if (flags & LSGCPD_PAIRS_LDS) return lsg::kBackendLds;
+  return lsg::kBackendScalar;
+}
+
 lsgcpd_status check_pose(lsgcpd_ctx *ctx, const lsgcpd_pose *g) {
   for (int i = 0; i < 9; ++i)
     if (!isfinite(g->R[i])) return fail(ctx, LSGCPD_E_INVALID, "pose R is not finite");
@@ -134,15 +157,14 @@ void fill_state(DevState *s, const lsgcpd_pose *g, double sigma2, double V, doub
 lsgcpd_status setup(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
                     const float *normals, const float *alpha, const float *pi, int64_t M,
                     uint32_t flags, int v_auto, int s2_auto, hipStream_t st) {
-  ENSURE(geo, (size_t)M * 2 * sizeof(float4));
-  ENSURE(feat, (size_t)M * lsg::kFeat * sizeof(double));
+  ENSURE(rec, (size_t)M * sizeof(lsg::TRec));
   const int nb = lsg::moments_blocks(N > M ? N : M);
   ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
   ENSURE(mom, 32 * sizeof(double));
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
   HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, pi, M,
                                   (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0,
-                                  (float4 *)ctx->geo.p, (double *)ctx->feat.p, st));
+                                  (lsg::TRec *)ctx->rec.p, st));
   double *ymom = (double *)ctx->mom.p;
   double *xmom = ymom + 16;
   HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(M),
@@ -195,8 +217,8 @@ lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::EstepPlan &pl, const float *
                         hipStream_t st) {
   lsgcpd_status s = prof_record(ctx, st);
   if (s != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep(pl, X, N, (const float4 *)ctx->geo.p, (const double *)ctx->feat.p, M,
-                           ctx->dstate, (double *)ctx->partial.p, st));
+  HIPCHK(lsg::launch_estep(pl, X, N, (const lsg::TRec *)ctx->rec.p, M, ctx->dstate,
+                           (double *)ctx->partial.p, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_finalize(pl, X, N, w, ctx->dstate, (const double *)ctx->partial.p,
                               (double *)ctx->blockstats.p, (double *)ctx->colS.p, colstats, st));
@@ -261,7 +283,7 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
 LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  Buf *bufs[] = {&c->knn, &c->geo,  &c->feat, &c->partial, &c->blockstats, &c->colS,
+  Buf *bufs[] = {&c->knn, &c->rec, &c->partial, &c->blockstats, &c->colS,
                  &c->mom_part, &c->mom, &c->nrm, &c->kap, &c->alp, &c->trace};
   for (Buf *b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -321,19 +343,20 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   if (!w && !(w0 > 0.0 && w0 < 1.0)) return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
   if (!finite_pos(sigma2)) return fail(ctx, LSGCPD_E_INVALID, "sigma2 must be finite and > 0");
   if (!isfinite(V)) return fail(ctx, LSGCPD_E_INVALID, "V must be finite");
-  if (flags & ~(uint32_t)(LSGCPD_EXACT_NORMALIZER | LSGCPD_ACCUM_VALU))
-    return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", flags);
+  if (flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", flags);
+  if ((flags & LSGCPD_PAIRS_LDS) && (flags & LSGCPD_PAIRS_MFMA))
+    return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
   RETURN_IF(check_pose(ctx, g));
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
-  const lsg::EstepPlan pl = lsg::estep_plan(N, M, (flags & LSGCPD_ACCUM_VALU) ? 0 : 1);
+  const lsg::EstepPlan pl = lsg::estep_plan(N, M, backend_of(flags), pair_sources(), pair_parts());
   RETURN_IF(ensure_estep(ctx, pl, N));
   fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 20, 1);
   RETURN_IF(setup(ctx, X, N, Y, normals, alpha, pi, M, flags, V > 0.0 ? 0 : 1, 0, st));
   RETURN_IF(prof_reserve(ctx, 1));
   RETURN_IF(run_estep(ctx, pl, X, N, M, w, colstats, nullptr, 0, st));
   if (P)
-    HIPCHK(lsg::launch_dump_P(X, N, (const float4 *)ctx->geo.p, M, w, ctx->dstate,
+    HIPCHK(lsg::launch_dump_P(X, N, (const lsg::TRec *)ctx->rec.p, M, w, ctx->dstate,
                               (const double *)ctx->colS.p, P, st));
   HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, sizeof(DevState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -379,8 +402,9 @@ LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N
     return fail(ctx, LSGCPD_E_INVALID, "max_iter = %d out of range", p->max_iter);
   if (p->newton_max < 1 || p->newton_max > 1000)
     return fail(ctx, LSGCPD_E_INVALID, "newton_max = %d out of range", p->newton_max);
-  if (p->flags & ~(uint32_t)(LSGCPD_EXACT_NORMALIZER | LSGCPD_ACCUM_VALU))
-    return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", p->flags);
+  if ((p->flags & LSGCPD_PAIRS_LDS) && (p->flags & LSGCPD_PAIRS_MFMA))
+    return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
   if (init) RETURN_IF(check_pose(ctx, init));
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
@@ -394,7 +418,7 @@ LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N
   HIPCHK(lsg::launch_normals(Y, M, p->k, p->alpha_max, p->lambda, (float *)ctx->nrm.p,
                              (float *)ctx->kap.p, (float *)ctx->alp.p, ctx->knn.p, ns, st));
 
-  const lsg::EstepPlan pl = lsg::estep_plan(N, M, (p->flags & LSGCPD_ACCUM_VALU) ? 0 : 1);
+  const lsg::EstepPlan pl = lsg::estep_plan(N, M, backend_of(p->flags), pair_sources(), pair_parts());
   RETURN_IF(ensure_estep(ctx, pl, N));
   ENSURE(trace, (size_t)(p->max_iter > 0 ? p->max_iter : 1) * sizeof(double));
   const int s2_auto = p->sigma2_init > 0.0 ? 0 : 1;

@@ -6,8 +6,14 @@
 // (qb, split) streams its chunk through LDS in tiles and every thread keeps the
 // k best (distance, index) pairs of one query in registers.  Distances are
 // float32 ((dx*dx + dy*dy) + dz*dz), no contraction, so that the neighbour set
-// is decided exactly as the float32 definition says; ties go to the lower
-// index because pairs are ordered lexicographically by (distance, index).
+// is decided exactly as the float32 definition says; pairs are ordered by the
+// 64-bit key (distance bits, index), i.e. by distance with ties to the lower
+// index.  Before the scan each query takes, as an upper bound tau0 of its k-th
+// distance, the k-th smallest distance to its 2k+1 index neighbours; only keys
+// <= (tau0, any index) can belong to the answer, so the list starts filled
+// with (tau0, +inf) sentinels.  On clouds stored in scan or image order (index
+// neighbours are spatial neighbours) this removes almost all list updates;
+// the result is exact for any order.
 // Pass 2 (knn_merge_pca): one thread per query merges the nsplit partial
 // lists, forms the neighbourhood covariance about its mean in FP64 and
 // diagonalises it by cyclic Jacobi rotations.
@@ -21,10 +27,7 @@ namespace {
 
 constexpr int kKnnBlock = 256;
 constexpr int kKnnTile = 256;
-
-__device__ __forceinline__ bool lex_less(float d1, int i1, float d2, int i2) {
-  return d1 < d2 || (d1 == d2 && i1 < i2);
-}
+constexpr uint32_t kNoIndex = 0xffffffffu;
 
 __device__ __forceinline__ float dist2_f32(float ax, float ay, float az, float bx, float by,
                                            float bz) {
@@ -35,79 +38,89 @@ __device__ __forceinline__ float dist2_f32(float ax, float ay, float az, float b
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// The KM best (distance, index) pairs seen so far, kept sorted in registers
-// (all indices compile-time constants, so nothing spills to scratch).  The
-// caller uses the first k <= KM entries; wd/wi is the k-th best pair, the
-// threshold a new candidate must beat.
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t i) {
+  return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)i;
+}
+__device__ __forceinline__ float key_dist(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ uint32_t key_index(uint64_t k) { return (uint32_t)k; }
+
+// The KM smallest keys seen so far, sorted, in registers (all indices are
+// compile-time constants, so nothing spills).  The caller uses the first
+// k <= KM entries; `worst` is the k-th key, the bound a new key must beat.
 template <int KM>
 struct TopK {
-  float d[KM];
-  int i[KM];
-  float wd;
-  int wi;
+  uint64_t key[KM];
+  uint64_t worst;
   int k;
 
-  __device__ __forceinline__ void init(int k_) {
+  __device__ __forceinline__ void init(int k_, uint64_t fill) {
     k = k_;
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      d[j] = INFINITY;
-      i[j] = 0x7fffffff;
-    }
-    wd = INFINITY;
-    wi = 0x7fffffff;
+    for (int j = 0; j < KM; ++j) key[j] = fill;
+    worst = fill;
   }
 
-  // insertion by one bubbling pass: the candidate moves past every larger
-  // pair, the last pair drops out
-  __device__ __forceinline__ void insert(float dn, int in) {
-    float cd = dn;
-    int ci = in;
+  // one bubbling pass: the new key moves past every smaller key
+  __device__ __forceinline__ void insert(uint64_t kn) {
+    uint64_t c = kn;
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
-      const bool lt = lex_less(cd, ci, d[j], i[j]);
-      const float td = d[j];
-      const int ti = i[j];
-      d[j] = lt ? cd : td;
-      i[j] = lt ? ci : ti;
-      cd = lt ? td : cd;
-      ci = lt ? ti : ci;
+      const uint64_t o = key[j];
+      const bool lt = c < o;
+      key[j] = lt ? c : o;
+      c = lt ? o : c;
     }
-    float th = d[0];
-    int thi = i[0];
+    uint64_t w = key[0];
 #pragma unroll
-    for (int j = 1; j < KM; ++j) {
-      const bool at = j == k - 1;
-      th = at ? d[j] : th;
-      thi = at ? i[j] : thi;
-    }
-    wd = th;
-    wi = thi;
+    for (int j = 1; j < KM; ++j) w = (j == k - 1) ? key[j] : w;
+    worst = w;
   }
 
-  __device__ __forceinline__ void offer(float dn, int in) {
-    if (lex_less(dn, in, wd, wi)) insert(dn, in);
+  __device__ __forceinline__ void offer(uint64_t kn) {
+    if (kn < worst) insert(kn);
   }
 };
+
+// tau0: k-th smallest distance from query q to its 2k+1 index neighbours.
+template <int KM>
+__device__ float index_window_bound(const float *__restrict__ Y, int M, int k, int q, float qx,
+                                    float qy, float qz) {
+  TopK<KM> t;
+  t.init(k, ~(uint64_t)0);
+  int lo = q - k, hi = q + k;
+  if (lo < 0) {
+    hi -= lo;
+    lo = 0;
+  }
+  if (hi > M - 1) {
+    lo -= hi - (M - 1);
+    hi = M - 1;
+    if (lo < 0) lo = 0;
+  }
+  for (int j = lo; j <= hi; ++j)
+    t.offer(make_key(dist2_f32(qx, qy, qz, Y[3 * j], Y[3 * j + 1], Y[3 * j + 2]), (uint32_t)j));
+  return key_dist(t.worst);
+}
 
 template <int KM>
 __global__ __launch_bounds__(kKnnBlock) void knn_partial(const float *__restrict__ Y, int M,
                                                          int k, int chunk,
-                                                         float *__restrict__ outd,
-                                                         int *__restrict__ outi) {
+                                                         uint64_t *__restrict__ out) {
   const int split = blockIdx.y;
   const int q = blockIdx.x * kKnnBlock + threadIdx.x;
   const int j0 = split * chunk;
   const int j1 = min(M, j0 + chunk);
   float qx = 0.f, qy = 0.f, qz = 0.f;
+  float tau = 0.f;
   if (q < M) {
     qx = Y[3 * q];
     qy = Y[3 * q + 1];
     qz = Y[3 * q + 2];
+    tau = index_window_bound<KM>(Y, M, k, q, qx, qy, qz);
   }
   __shared__ float4 tile[kKnnTile];
   TopK<KM> top;
-  top.init(k);
+  top.init(k, make_key(tau, kNoIndex));
   for (int jt = j0; jt < j1; jt += kKnnTile) {
     const int cnt = min(kKnnTile, j1 - jt);
     if (threadIdx.x < cnt) {
@@ -118,20 +131,15 @@ __global__ __launch_bounds__(kKnnBlock) void knn_partial(const float *__restrict
     for (int jj = 0; jj < cnt; ++jj) {
       const float4 p = tile[jj];
       const float d = dist2_f32(qx, qy, qz, p.x, p.y, p.z);
-      // indices increase along the scan, so (d, j) < worst <=> d < worst.d
-      if (d < top.wd) top.insert(d, jt + jj);
+      // cheap float test first; the exact key order decides inside
+      if (d <= key_dist(top.worst)) top.offer(make_key(d, (uint32_t)(jt + jj)));
     }
     __syncthreads();
   }
   if (q < M) {
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        const size_t o = ((size_t)split * k + j) * M + q;
-        outd[o] = top.d[j];
-        outi[o] = top.i[j];
-      }
-    }
+    for (int j = 0; j < KM; ++j)
+      if (j < k) out[((size_t)split * k + j) * M + q] = top.key[j];
   }
 }
 
@@ -177,8 +185,8 @@ __device__ void jacobi3(double a[3][3], double v[3][3]) {
 
 template <int KM>
 __global__ __launch_bounds__(256) void knn_merge_pca(const float *__restrict__ Y, int M, int k,
-                                                     int nsplit, const float *__restrict__ ind,
-                                                     const int *__restrict__ ini,
+                                                     int nsplit,
+                                                     const uint64_t *__restrict__ keys,
                                                      double alpha_max, double lambda,
                                                      float *__restrict__ normals,
                                                      float *__restrict__ kappa,
@@ -186,26 +194,27 @@ __global__ __launch_bounds__(256) void knn_merge_pca(const float *__restrict__ Y
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= M) return;
   TopK<KM> top;
-  top.init(k);
+  top.init(k, ~(uint64_t)0);
   for (int s = 0; s < nsplit; ++s)
     for (int j = 0; j < k; ++j) {
-      const size_t o = ((size_t)s * k + j) * M + q;
-      const int idx = ini[o];
-      if (idx >= 0 && idx < M) top.offer(ind[o], idx);
+      const uint64_t kk = keys[((size_t)s * k + j) * M + q];
+      if (key_index(kk) < (uint32_t)M) top.offer(kk);
     }
-  // fewer than k valid candidates only happens with non-finite input
-  // coordinates; such slots fall back to the query point itself
+  // every slot holds a valid index unless the inputs were not finite; such
+  // slots fall back to the query point itself
+  int idx[KM];
 #pragma unroll
-  for (int j = 0; j < KM; ++j)
-    if (top.i[j] < 0 || top.i[j] >= M) top.i[j] = q;
+  for (int j = 0; j < KM; ++j) {
+    const uint32_t i = key_index(top.key[j]);
+    idx[j] = i < (uint32_t)M ? (int)i : q;
+  }
   double mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
   for (int j = 0; j < KM; ++j) {
     if (j < k) {
-      const int idx = top.i[j];
-      mx += (double)Y[3 * idx];
-      my += (double)Y[3 * idx + 1];
-      mz += (double)Y[3 * idx + 2];
+      mx += (double)Y[3 * idx[j]];
+      my += (double)Y[3 * idx[j] + 1];
+      mz += (double)Y[3 * idx[j] + 2];
     }
   }
   const double invk = 1.0 / (double)k;
@@ -216,10 +225,9 @@ __global__ __launch_bounds__(256) void knn_merge_pca(const float *__restrict__ Y
 #pragma unroll
   for (int j = 0; j < KM; ++j) {
     if (j < k) {
-      const int idx = top.i[j];
-      const double dx = (double)Y[3 * idx] - mx;
-      const double dy = (double)Y[3 * idx + 1] - my;
-      const double dz = (double)Y[3 * idx + 2] - mz;
+      const double dx = (double)Y[3 * idx[j]] - mx;
+      const double dy = (double)Y[3 * idx[j] + 1] - my;
+      const double dz = (double)Y[3 * idx[j] + 2] - mz;
       c00 += dx * dx;
       c01 += dx * dy;
       c02 += dx * dz;
@@ -275,7 +283,7 @@ int knn_choose_splits(int64_t M) {
 }
 
 size_t knn_workspace_bytes(int64_t M, int nsplit) {
-  return (size_t)nsplit * 32 * (size_t)M * (sizeof(float) + sizeof(int));
+  return (size_t)nsplit * 32 * (size_t)M * sizeof(uint64_t);
 }
 
 hipError_t launch_normals(const float *Y, int64_t M, int k, double alpha_max, double lambda,
@@ -283,19 +291,20 @@ hipError_t launch_normals(const float *Y, int64_t M, int k, double alpha_max, do
                           hipStream_t st) {
   const int Mi = (int)M;
   const int chunk = (int)((M + nsplit - 1) / nsplit);
-  float *ind = (float *)work;
-  int *ini = (int *)((char *)work + (size_t)nsplit * k * M * sizeof(float));
+  uint64_t *keys = (uint64_t *)work;
   dim3 g1((unsigned)((M + kKnnBlock - 1) / kKnnBlock), (unsigned)nsplit);
   dim3 g2((unsigned)((M + 255) / 256));
-  if (k <= 16) {
-    hipLaunchKernelGGL(knn_partial<16>, g1, dim3(kKnnBlock), 0, st, Y, Mi, k, chunk, ind, ini);
-    hipLaunchKernelGGL(knn_merge_pca<16>, g2, dim3(256), 0, st, Y, Mi, k, nsplit, ind, ini,
-                       alpha_max, lambda, normals, kappa, alpha);
-  } else {
-    hipLaunchKernelGGL(knn_partial<32>, g1, dim3(kKnnBlock), 0, st, Y, Mi, k, chunk, ind, ini);
-    hipLaunchKernelGGL(knn_merge_pca<32>, g2, dim3(256), 0, st, Y, Mi, k, nsplit, ind, ini,
-                       alpha_max, lambda, normals, kappa, alpha);
-  }
+#define LSG_KNN(KM_)                                                                         \
+  do {                                                                                       \
+    hipLaunchKernelGGL(knn_partial<KM_>, g1, dim3(kKnnBlock), 0, st, Y, Mi, k, chunk, keys); \
+    hipLaunchKernelGGL(knn_merge_pca<KM_>, g2, dim3(256), 0, st, Y, Mi, k, nsplit, keys,     \
+                       alpha_max, lambda, normals, kappa, alpha);                            \
+  } while (0)
+  if (k <= 8) LSG_KNN(8);
+  else if (k <= 16) LSG_KNN(16);
+  else if (k <= 20) LSG_KNN(20);
+  else LSG_KNN(32);
+#undef LSG_KNN
   return hipGetLastError();
 }
 

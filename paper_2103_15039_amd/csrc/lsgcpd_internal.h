@@ -7,17 +7,21 @@
 
 namespace lsg {
 
-// Per-target record read by the E-step kernels.
-//   geo[2m]   = (y_x, y_y, y_z, l_m)   l_m = log2(pi_m [* sqrt(1 + alpha_m)])
-//   geo[2m+1] = (a_x, a_y, a_z, 0)     a = sqrt(alpha_m) n_m
-//   feat[16m + c], c = 0..15 (FP64): accumulation features f_m
-//     0: 1
-//     1..6: alpha n n^T   (00 01 02 11 12 22)
-//     7..9: y + alpha s n  (s = y . n), i.e. M_m y_m
-//     10: |y|^2 + alpha s^2,              i.e. y_m^T M_m y_m
-//     11..15: 0
-constexpr int kFeat = 16;
-constexpr int kFeatUsed = 11;
+// Per-target record read by the E-step kernels (FP64, 144 bytes):
+//   y     target point
+//   a     sqrt(alpha_m) n_m
+//   l     log2(pi_m [* sqrt(1 + alpha_m)])
+//   f     accumulation features 1..10 (feature 0 is the constant 1):
+//         alpha n n^T (00 01 02 11 12 22), M_m y_m, y_m^T M_m y_m
+struct TRec {
+  double y[3];
+  double a[3];
+  double l;
+  double f[10];
+  double pad;
+};
+constexpr int kRecDoubles = 18;
+constexpr int kFeatUsed = 11;   // feature 0 (= 1) and f[0..9]
 constexpr int kStats = 86;
 constexpr int kColStats = 16;
 
@@ -76,28 +80,33 @@ hipError_t launch_init_state(DevState *s, const double *ymom, const double *xmom
 
 // Target records.
 hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
-                               const float *pi, int64_t M, int exact, float4 *geo, double *feat,
-                               hipStream_t st);
+                               const float *pi, int64_t M, int exact, TRec *rec, hipStream_t st);
 
 // E step: fused exponent + accumulation over target chunks, then per-source
 // finalisation + lift to the 86 statistics, then the deterministic reduction.
+constexpr int kBackendScalar = 0;  // target records via the scalar cache (default)
+constexpr int kBackendLds = 1;     // target records staged in LDS
+constexpr int kBackendMfma = 2;    // FP64 matrix-core accumulation
+constexpr int kPairS = 2;          // sources per lane in the VALU back ends
+
 struct EstepPlan {
-  int mfma;        // 1: FP64 matrix-core accumulation, 0: VALU accumulation
+  int backend;
+  int srcs_per_lane;  // sources per lane of the VALU back ends (2 or 4)
+  int parts;          // target sub-ranges per block of the scalar back end (1, 2, 4)
   int nsplit;      // target chunks
   int64_t mchunk;  // targets per chunk (multiple of the tile)
   int nsrc_blocks; // source blocks of the accumulation kernel
   int nfin_blocks; // blocks of the finalisation kernel
 };
-EstepPlan estep_plan(int64_t N, int64_t M, int mfma);
+EstepPlan estep_plan(int64_t N, int64_t M, int backend, int srcs_per_lane, int parts);
 size_t estep_partial_bytes(const EstepPlan &pl, int64_t N);
 
-hipError_t launch_estep(const EstepPlan &pl, const float *X, int64_t N, const float4 *geo,
-                        const double *feat, int64_t M, const DevState *s, double *partial,
-                        hipStream_t st);
+hipError_t launch_estep(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
+                        int64_t M, const DevState *s, double *partial, hipStream_t st);
 hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const float *w,
                            const DevState *s, const double *partial, double *blockstats,
                            double *colS, double *colstats, hipStream_t st);
-hipError_t launch_dump_P(const float *X, int64_t N, const float4 *geo, int64_t M, const float *w,
+hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, const float *w,
                          const DevState *s, const double *colS, float *P, hipStream_t st);
 
 // Reduce the block statistics and run the M step.  mode 0: derive only

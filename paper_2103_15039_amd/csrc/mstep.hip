@@ -11,7 +11,8 @@
 // sigma^2).  If Hs is not positive definite the Gauss-Newton part is used;
 // steps are halved until D does not grow beyond a rounding allowance.  After
 // the pose, sigma^2 = D(G_new) / (3 N_P) (Sec. 3.5, last paragraph).
-// The solve is a few thousand FP64 operations; one thread does it.
+// The block's threads share the 12 x 12 products; thread 0 does the 6 x 6
+// Cholesky solve and the exponential map.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -22,73 +23,9 @@ namespace {
 
 constexpr double kTwoPi = 6.283185307179586477;
 
-struct Quad {
-  double H[12][12];
-  double b[12];
-  double c;
-};
-
-__device__ void build_quad(const double *S, Quad &q) {
-  // upper-triangle order (00 01 02 03 11 12 13 22 23 33)
-  double S0[4][4], S1[6][4][4];
-  auto unpack = [](const double *u, double M4[4][4]) {
-    int o = 0;
-    for (int i = 0; i < 4; ++i)
-      for (int j = i; j < 4; ++j) {
-        M4[i][j] = u[o];
-        M4[j][i] = u[o];
-        ++o;
-      }
-  };
-  unpack(S, S0);
-  for (int ab = 0; ab < 6; ++ab) unpack(S + 10 + 10 * ab, S1[ab]);
-  const int pair[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-  for (int a = 0; a < 3; ++a)
-    for (int bb = 0; bb < 3; ++bb)
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j)
-          q.H[4 * a + i][4 * bb + j] = (a == bb ? S0[i][j] : 0.0) + S1[pair[a][bb]][i][j];
-  for (int i = 0; i < 12; ++i) q.b[i] = S[70 + i];
-  q.c = S[82];
-}
-
-__device__ double quad_eval(const Quad &q, const double G[4][4]) {
-  double g[12];
-  for (int a = 0; a < 3; ++a)
-    for (int j = 0; j < 4; ++j) g[4 * a + j] = G[a][j];
-  double s = q.c;
-  for (int r = 0; r < 12; ++r) {
-    double hr = 0.0;
-    for (int c = 0; c < 12; ++c) hr = fma(q.H[r][c], g[c], hr);
-    s = fma(g[r], hr - 2.0 * q.b[r], s);
-  }
-  return s;
-}
-
-// se(3) basis: E_0..E_2 rotations about x, y, z; E_3..E_5 translations.
-__device__ void basis(int i, double E[4][4]) {
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) E[r][c] = 0.0;
-  if (i < 3) {
-    const int a = (i + 1) % 3, b = (i + 2) % 3;  // [e_i]_x: E[b][a] = 1, E[a][b] = -1
-    E[b][a] = 1.0;
-    E[a][b] = -1.0;
-  } else {
-    E[i - 3][3] = 1.0;
-  }
-}
-
-__device__ void mat4_mul(const double A[4][4], const double B[4][4], double C[4][4]) {
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) {
-      double s = 0.0;
-      for (int k = 0; k < 4; ++k) s = fma(A[r][k], B[k][c], s);
-      C[r][c] = s;
-    }
-}
-
-// exp of the twist xi = (omega, v): Rodrigues rotation and left Jacobian.
-__device__ void se3_exp(const double xi[6], double T[4][4]) {
+// SE(3) exponential of the twist xi = (omega, v): Rodrigues rotation and the
+// left Jacobian of SO(3) for the translation.
+__device__ void se3_exp(const double xi[6], double Rx[3][3], double tx[3]) {
   const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
   const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
   const double th = sqrt(th2);
@@ -114,12 +51,21 @@ __device__ void se3_exp(const double xi[6], double T[4][4]) {
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
       const double I = r == c ? 1.0 : 0.0;
-      T[r][c] = I + A * W[r][c] + B * W2[r][c];
+      Rx[r][c] = I + A * W[r][c] + B * W2[r][c];
       Vm[r][c] = I + B * W[r][c] + C * W2[r][c];
     }
-  for (int r = 0; r < 3; ++r) T[r][3] = Vm[r][0] * xi[3] + Vm[r][1] * xi[4] + Vm[r][2] * xi[5];
-  T[3][0] = T[3][1] = T[3][2] = 0.0;
-  T[3][3] = 1.0;
+  for (int r = 0; r < 3; ++r) tx[r] = Vm[r][0] * xi[3] + Vm[r][1] * xi[4] + Vm[r][2] * xi[5];
+}
+
+// g_out = vec(G exp(xi^)) for g = vec(G), G = [R | t] (3 x 4 row-major)
+__device__ void compose(const double *g, const double xi[6], double *gout) {
+  double Rx[3][3], tx[3];
+  se3_exp(xi, Rx, tx);
+  for (int a = 0; a < 3; ++a) {
+    const double *G = g + 4 * a;
+    for (int c = 0; c < 3; ++c) gout[4 * a + c] = G[0] * Rx[0][c] + G[1] * Rx[1][c] + G[2] * Rx[2][c];
+    gout[4 * a + 3] = G[0] * tx[0] + G[1] * tx[1] + G[2] * tx[2] + G[3];
+  }
 }
 
 // Cholesky solve of the 6x6 system A x = -g; false if A is not positive definite.
@@ -152,160 +98,261 @@ __device__ bool chol_solve6(const double A[6][6], const double g[6], double x[6]
   return true;
 }
 
-// Gradient (Eq. 11) and symmetrised Hessian (Eq. 12) at G, and the
-// Gauss-Newton part of the Hessian, all divided by sigma^2.
-__device__ void derivatives(const Quad &q, const double G[4][4], double inv_s2, double grad[6],
-                            double Hs[6][6], double Hgn[6][6]) {
-  double g[12];
-  for (int a = 0; a < 3; ++a)
-    for (int j = 0; j < 4; ++j) g[4 * a + j] = G[a][j];
-  double v[12];
-  for (int r = 0; r < 12; ++r) {
-    double s = -q.b[r];
-    for (int c = 0; c < 12; ++c) s = fma(q.H[r][c], g[c], s);
-    v[r] = s;
-  }
-  double J[6][12], HJ[6][12];
-  for (int i = 0; i < 6; ++i) {
-    double E[4][4], GE[4][4];
-    basis(i, E);
-    mat4_mul(G, E, GE);
-    for (int a = 0; a < 3; ++a)
-      for (int j = 0; j < 4; ++j) J[i][4 * a + j] = GE[a][j];
-  }
-  for (int i = 0; i < 6; ++i)
-    for (int r = 0; r < 12; ++r) {
-      double s = 0.0;
-      for (int c = 0; c < 12; ++c) s = fma(q.H[r][c], J[i][c], s);
-      HJ[i][r] = s;
-    }
-  for (int i = 0; i < 6; ++i) {
+// Shared state of the block-parallel M step.
+struct MSh {
+  double H[12][12];   // H[4a+i][4b+j] = delta_ab S0[i][j] + S1[ab][i][j]
+  double b[12];       // vec(S2)
+  double c;           // S3
+  double g[12];       // vec(G), the current pose
+  double gn[12];      // trial pose
+  double J[6][12];    // vec(G E_i) of the six generators
+  double HJ[6][12];
+  double Hg[12];
+  double GN[6][6];
+  double xi[6];
+  double cur, val, step;
+  int go;             // 1 while Newton continues
+  int accept;
+};
+
+__device__ __forceinline__ int pair_index(int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;  // (00 01 02 11 12 22)
+  return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+}
+
+// upper-triangle position of (i, j) in the 4x4 packing (00 01 02 03 11 12 13 22 23 33)
+__device__ __forceinline__ int tri4(int i, int j) {
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  const int base[4] = {0, 4, 7, 9};
+  return base[lo] + hi - lo;
+}
+
+// D(vec) = v^T H v - 2 b^T v + c with the block's threads: rows in parallel.
+__device__ double block_quad(MSh &m, const double *v, double *rowbuf) {
+  const int tid = threadIdx.x;
+  if (tid < 12) {
     double s = 0.0;
-    for (int r = 0; r < 12; ++r) s = fma(v[r], J[i][r], s);
-    grad[i] = 2.0 * s * inv_s2;
+    for (int k = 0; k < 12; ++k) s = fma(m.H[tid][k], v[k], s);
+    rowbuf[tid] = v[tid] * (s - 2.0 * m.b[tid]);
   }
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) {
-      double s = 0.0;
-      for (int r = 0; r < 12; ++r) s = fma(J[i][r], HJ[j][r], s);
-      double Ei[4][4], Ej[4][4], EiEj[4][4], EjEi[4][4], K[4][4], GK[4][4];
-      basis(i, Ei);
-      basis(j, Ej);
-      mat4_mul(Ei, Ej, EiEj);
-      mat4_mul(Ej, Ei, EjEi);
-      for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) K[r][c] = 0.5 * (EiEj[r][c] + EjEi[r][c]);
-      mat4_mul(G, K, GK);
-      double t2 = 0.0;
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 4; ++c) t2 = fma(v[4 * a + c], GK[a][c], t2);
-      Hgn[i][j] = Hgn[j][i] = 2.0 * s * inv_s2;
-      Hs[i][j] = Hs[j][i] = 2.0 * (s + t2) * inv_s2;
-    }
+  __syncthreads();
+  double tot = m.c;
+  for (int r = 0; r < 12; ++r) tot += rowbuf[r];
+  __syncthreads();
+  return tot;
 }
 
 __global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ blockstats, int nblk,
                                                     int N, DevState *__restrict__ s,
                                                     double *__restrict__ trace, int mode) {
   if (s->done) return;
+  // block statistics are stat-major (row i holds the nblk partials of
+  // statistic i); thread (i, h) sums half h of row i with four independent
+  // running sums, and the halves are added in a fixed order, so the result is
+  // reproducible bit for bit
   __shared__ double S[kStats];
-  for (int i = threadIdx.x; i < kStats; i += blockDim.x) {
-    double a = 0.0;
-    for (int b = 0; b < nblk; ++b) a += blockstats[(size_t)b * kStats + i];
-    S[i] = a;
+  __shared__ double half[2][kStats];
+  __shared__ MSh m;
+  __shared__ double rowbuf[12];
+  const int tid = threadIdx.x;
+  if (tid < 2 * kStats) {
+    const int i = tid >> 1, h = tid & 1;
+    const double *row = blockstats + (size_t)i * nblk;
+    const int b0 = h ? nblk / 2 : 0, b1 = h ? nblk : nblk / 2;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = b0;
+    for (; b + 4 <= b1; b += 4) {
+      a0 += row[b];
+      a1 += row[b + 1];
+      a2 += row[b + 2];
+      a3 += row[b + 3];
+    }
+    for (; b < b1; ++b) a0 += row[b];
+    half[h][i] = (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (tid < kStats) S[tid] = half[0][tid] + half[1][tid];
+  __syncthreads();
+  // the quadratic and the pose
+  for (int e = tid; e < 144; e += blockDim.x) {
+    const int r = e / 12, cc = e % 12;
+    const int a = r >> 2, i = r & 3, bb = cc >> 2, k = cc & 3;
+    double v = S[10 + 10 * pair_index(a, bb) + tri4(i, k)];
+    if (a == bb) v += S[tri4(i, k)];
+    m.H[r][cc] = v;
+  }
+  if (tid < 12) {
+    m.b[tid] = S[70 + tid];
+    const int a = tid >> 2, j = tid & 3;
+    m.g[tid] = j < 3 ? s->R[3 * a + j] : s->t[a];
+  }
+  if (tid == 0) m.c = S[82];
+  __syncthreads();
 
   const double sigma2 = s->sigma2;
-  const double gam = pow(kTwoPi * sigma2, 1.5) / s->V;
+  const double inv_s2 = 1.0 / sigma2;
   const double Np = S[9];
   const double nll = -(S[85] + S[83] - 1.5 * (double)N * log(kTwoPi * sigma2));
-  for (int i = 0; i < kStats; ++i) s->stats[i] = S[i];
-  s->gamma = gam;
-  s->nll = nll;
-
-  Quad q;
-  build_quad(S, q);
-  double G[4][4];
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c) G[r][c] = s->R[3 * r + c];
-    G[r][3] = s->t[r];
-  }
-  G[3][0] = G[3][1] = G[3][2] = 0.0;
-  G[3][3] = 1.0;
-  double cur = quad_eval(q, G);
-  s->pd = cur;
-
-  if (mode == 1) {
-    const int it = s->iter;
-    if (trace) trace[it] = nll;
-    if (s->tol > 0.0 && it > 0 && fabs(nll - s->nll_prev) <= s->tol * fabs(nll)) {
-      s->done = 1;
-      s->converged = 1;
-      return;
+  double cur = block_quad(m, m.g, rowbuf);
+  if (tid == 0) {
+    for (int i = 0; i < kStats; ++i) s->stats[i] = S[i];
+    s->gamma = pow(kTwoPi * sigma2, 1.5) / s->V;
+    s->nll = nll;
+    s->pd = cur;
+    m.cur = cur;
+    m.go = Np > 0.0 ? 1 : 0;
+    if (mode == 1) {
+      const int it = s->iter;
+      if (trace) trace[it] = nll;
+      if (s->tol > 0.0 && it > 0 && fabs(nll - s->nll_prev) <= s->tol * fabs(nll)) {
+        s->done = 1;
+        s->converged = 1;
+        m.go = -1;
+      } else {
+        s->nll_prev = nll;
+      }
     }
-    s->nll_prev = nll;
+    if (mode == 0 && Np <= 0.0) {
+      for (int i = 0; i < 6; ++i) s->grad[i] = 0.0;
+      for (int i = 0; i < 36; ++i) s->hess[i] = 0.0;
+    }
   }
+  __syncthreads();
+  if (m.go < 0) return;  // EM stopped by the tolerance (uniform)
 
-  const double inv_s2 = 1.0 / sigma2;
   int iters = 0, gnf = 0;
-  double grad[6], Hs[6][6], Hgn[6][6];
-  if (Np > 0.0) {
-    for (int itn = 0; itn < s->newton_max; ++itn) {
-      ++iters;
-      derivatives(q, G, inv_s2, grad, Hs, Hgn);
+  for (int itn = 0; itn < s->newton_max && m.go == 1; ++itn) {
+    ++iters;
+    // generators J_i = vec(G E_i): rotation i -> [R [e_i]x | 0], translation i -> [0 | R e_i]
+    if (tid < 72) {
+      const int i = tid / 12, r = tid % 12, a = r >> 2, c = r & 3;
+      double v = 0.0;
+      if (i < 3) {
+        const int u = (i + 1) % 3, w = (i + 2) % 3;  // [e_i]x: (w, u) = 1, (u, w) = -1
+        if (c == u) v = m.g[4 * a + w];
+        else if (c == w) v = -m.g[4 * a + u];
+      } else if (c == 3) {
+        v = m.g[4 * a + (i - 3)];
+      }
+      m.J[i][r] = v;
+    }
+    __syncthreads();
+    if (tid < 72) {
+      const int i = tid / 12, r = tid % 12;
+      double acc = 0.0;
+      for (int k = 0; k < 12; ++k) acc = fma(m.H[r][k], m.J[i][k], acc);
+      m.HJ[i][r] = acc;
+    } else if (tid >= 96 && tid < 108) {
+      const int r = tid - 96;
+      double acc = 0.0;
+      for (int k = 0; k < 12; ++k) acc = fma(m.H[r][k], m.g[k], acc);
+      m.Hg[r] = acc;
+    }
+    __syncthreads();
+    if (tid < 36) {
+      const int i = tid / 6, j = tid % 6;
+      double acc = 0.0;
+      for (int r = 0; r < 12; ++r) acc = fma(m.J[i][r], m.HJ[j][r], acc);
+      m.GN[i][j] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // V = H g - b;  Q = R^T V[:, 0:3],  w = R^T V[:, 3]
+      double V[12], Q[3][3], w[3];
+      for (int r = 0; r < 12; ++r) V[r] = m.Hg[r] - m.b[r];
+      for (int l = 0; l < 3; ++l) {
+        for (int k = 0; k < 3; ++k)
+          Q[l][k] = m.g[l] * V[k] + m.g[4 + l] * V[4 + k] + m.g[8 + l] * V[8 + k];
+        w[l] = m.g[l] * V[3] + m.g[4 + l] * V[7] + m.g[8 + l] * V[11];
+      }
+      double grad[6], Hs[6][6], Hg[6][6];
+      grad[0] = 2.0 * (Q[2][1] - Q[1][2]) * inv_s2;
+      grad[1] = 2.0 * (Q[0][2] - Q[2][0]) * inv_s2;
+      grad[2] = 2.0 * (Q[1][0] - Q[0][1]) * inv_s2;
+      for (int i = 0; i < 3; ++i) grad[3 + i] = 2.0 * w[i] * inv_s2;
+      // second-order term 2 <V, G (E_i E_j + E_j E_i)/2>:
+      //   rot-rot Q_ij + Q_ji - 2 delta_ij tr Q,  rot i / trans j  w . (e_i x e_j)
+      const double trQ = Q[0][0] + Q[1][1] + Q[2][2];
+      for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+          double t2 = 0.0;
+          if (i < 3 && j < 3) {
+            t2 = Q[i][j] + Q[j][i] - (i == j ? 2.0 * trQ : 0.0);
+          } else if ((i < 3) != (j < 3)) {
+            const int ir = i < 3 ? i : j, jt = (i < 3 ? j : i) - 3;
+            if (ir != jt) {
+              const int k = 3 - ir - jt;
+              t2 = ((jt - ir + 3) % 3 == 1 ? 1.0 : -1.0) * w[k];
+            }
+          }
+          const double gn = 0.5 * (m.GN[i][j] + m.GN[j][i]);
+          Hg[i][j] = 2.0 * gn * inv_s2;
+          Hs[i][j] = (2.0 * gn + t2) * inv_s2;
+        }
       if (itn == 0 && mode == 0) {
         for (int i = 0; i < 6; ++i) s->grad[i] = grad[i];
         for (int i = 0; i < 6; ++i)
           for (int j = 0; j < 6; ++j) s->hess[6 * i + j] = Hs[i][j];
       }
       double xi[6];
-      if (!chol_solve6(Hs, grad, xi)) {
+      bool ok = chol_solve6(Hs, grad, xi);
+      if (!ok) {
         ++gnf;
-        if (!chol_solve6(Hgn, grad, xi)) {
+        ok = chol_solve6(Hg, grad, xi);
+        if (!ok) {
           double mx = 0.0;
-          for (int i = 0; i < 6; ++i) mx = fmax(mx, Hgn[i][i]);
-          for (int i = 0; i < 6; ++i) Hgn[i][i] += 1e-10 * mx + 1e-300;
-          if (!chol_solve6(Hgn, grad, xi)) break;
+          for (int i = 0; i < 6; ++i) mx = fmax(mx, Hg[i][i]);
+          for (int i = 0; i < 6; ++i) Hg[i][i] += 1e-10 * mx + 1e-300;
+          ok = chol_solve6(Hg, grad, xi);
         }
       }
-      double step = 1.0;
-      bool ok = false;
-      double Gn[4][4], val = cur;
-      for (int h = 0; h < 31; ++h) {
-        double xs[6], T[4][4];
-        for (int i = 0; i < 6; ++i) xs[i] = step * xi[i];
-        se3_exp(xs, T);
-        mat4_mul(G, T, Gn);
-        val = quad_eval(q, Gn);
-        if (val <= cur + 1e-12 * fabs(cur)) {
-          ok = true;
-          break;
-        }
-        step *= 0.5;
-      }
-      if (!ok) break;
-      for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) G[r][c] = Gn[r][c];
-      cur = val;
-      double mxs = 0.0;
-      for (int i = 0; i < 6; ++i) mxs = fmax(mxs, fabs(step * xi[i]));
-      if (mxs < 1e-12) break;
+      for (int i = 0; i < 6; ++i) m.xi[i] = ok ? xi[i] : 0.0;
+      m.go = ok ? 1 : 0;
+      m.step = 1.0;
+      m.accept = 0;
     }
-  } else if (mode == 0) {
-    for (int i = 0; i < 6; ++i) s->grad[i] = 0.0;
-    for (int i = 0; i < 36; ++i) s->hess[i] = 0.0;
+    __syncthreads();
+    if (m.go != 1) break;
+    // halve the step until D does not grow beyond a rounding allowance
+    for (int h = 0; h < 31; ++h) {
+      if (tid == 0) {
+        double xs[6];
+        for (int i = 0; i < 6; ++i) xs[i] = m.step * m.xi[i];
+        compose(m.g, xs, m.gn);
+      }
+      __syncthreads();
+      const double val = block_quad(m, m.gn, rowbuf);
+      if (tid == 0) {
+        m.val = val;
+        if (val <= m.cur + 1e-12 * fabs(m.cur)) m.accept = 1;
+        else m.step *= 0.5;
+      }
+      __syncthreads();
+      if (m.accept) break;
+    }
+    if (tid == 0) {
+      if (!m.accept) {
+        m.go = 0;
+      } else {
+        double mxs = 0.0;
+        for (int i = 0; i < 6; ++i) mxs = fmax(mxs, fabs(m.step * m.xi[i]));
+        for (int r = 0; r < 12; ++r) m.g[r] = m.gn[r];
+        m.cur = m.val;
+        if (mxs < 1e-12) m.go = 0;
+      }
+    }
+    __syncthreads();
   }
-  double s2n = Np > 0.0 ? fmax(cur / (3.0 * Np), s->sigma2_floor) : sigma2;
+  if (tid != 0) return;
+  cur = m.cur;
+  const double s2n = Np > 0.0 ? fmax(cur / (3.0 * Np), s->sigma2_floor) : sigma2;
   bool finite = isfinite(s2n);
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 4; ++c) finite = finite && isfinite(G[r][c]);
+  for (int r = 0; r < 12; ++r) finite = finite && isfinite(m.g[r]);
   s->newton_iters = iters;
   s->gn_fallbacks += gnf;
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c) s->R_next[3 * r + c] = G[r][c];
-    s->t_next[r] = G[r][3];
+  for (int a = 0; a < 3; ++a) {
+    for (int c = 0; c < 3; ++c) s->R_next[3 * a + c] = m.g[4 * a + c];
+    s->t_next[a] = m.g[4 * a + 3];
   }
   s->sigma2_next = s2n;
   if (mode == 1) {
@@ -314,9 +361,9 @@ __global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ b
       s->done = 1;
       return;
     }
-    for (int r = 0; r < 3; ++r) {
-      for (int c = 0; c < 3; ++c) s->R[3 * r + c] = G[r][c];
-      s->t[r] = G[r][3];
+    for (int a = 0; a < 3; ++a) {
+      for (int c = 0; c < 3; ++c) s->R[3 * a + c] = m.g[4 * a + c];
+      s->t[a] = m.g[4 * a + 3];
     }
     s->sigma2 = s2n;
     s->iter += 1;

@@ -71,7 +71,7 @@ def _pair_floor(X, Y, nrm, alpha):
 
 
 def _check_estep(X32, Y32, n32, a32, R, t, s2, w0=0.1, V=None, pi=None, w=None, exact=False,
-                 valu=False, check_P=True):
+                 backend="scalar", check_P=True):
     X = X32.astype(np.float64)
     Y = Y32.astype(np.float64)
     es = O.estep(X, Y, n32.astype(np.float64), a32.astype(np.float64), R, t, s2, w0=w0,
@@ -84,7 +84,7 @@ def _check_estep(X32, Y32, n32, a32, R, t, s2, w0=0.1, V=None, pi=None, w=None, 
     ref_stats = O.lifted_stats(cols, X, nll_terms)
     g = L.estep(dev(X32), dev(Y32), dev(n32), dev(a32), R, t, s2, w0=w0,
                 V=0.0 if V is None else V, pi=None if pi is None else dev(pi),
-                w=None if w is None else dev(w), exact=exact, valu=valu, dump_P=check_P,
+                w=None if w is None else dev(w), exact=exact, backend=backend, dump_P=check_P,
                 colstats=True)
     assert g.V == pytest.approx(es.V, rel=1e-14)
     assert g.gamma == pytest.approx(es.gamma, rel=1e-13)
@@ -113,13 +113,13 @@ def _check_estep(X32, Y32, n32, a32, R, t, s2, w0=0.1, V=None, pi=None, w=None, 
     return g, es, cols
 
 
-@pytest.mark.parametrize("valu", [False, True], ids=["mfma", "valu"])
+@pytest.mark.parametrize("backend", ["scalar", "lds", "mfma"])
 @pytest.mark.parametrize("M,N", [(1, 1), (5, 3), (37, 53), (300, 517), (1000, 2500)])
-def test_estep_parity(M, N, valu):
+def test_estep_parity(M, N, backend):
     X32, Y32, n32, a32, p = _inputs(M, N, seed=M + N)
     R, t = _near_pose(p, M)
     for s2 in (2e-4, 0.02):
-        g, es, cols = _check_estep(X32, Y32, n32, a32, R, t, s2, valu=valu)
+        g, es, cols = _check_estep(X32, Y32, n32, a32, R, t, s2, backend=backend)
 
 
 @pytest.mark.parametrize("exact", [False, True])

@@ -84,14 +84,15 @@ def test_register_small_variants(trial):
     _reg_pair(p, 10, 30, exact=(trial == 2))
 
 
-def test_register_tol_stop_and_valu_backend():
+def test_register_tol_stop_and_backends():
     p = datagen.range_scanner_pair(trial=3, M=500, N=500)
     g = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7)
     o = O.register(p.X, p.Y, k=10, max_iter=60, tol=1e-7)
     assert g.converged and g.iters == o.iters < 60
-    v = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7, valu=True)
-    assert v.iters == g.iters
-    assert O.rotation_error_deg(v.R, g.R) < 1e-5
+    for backend in ("lds", "mfma"):
+        v = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7, backend=backend)
+        assert v.iters == g.iters
+        assert O.rotation_error_deg(v.R, g.R) < 1e-5
 
 
 def test_register_nll_monotone_and_recovery():
