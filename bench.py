@@ -38,12 +38,31 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--backend", default="scalar", choices=["scalar", "lds", "mfma"],
                     help="pair-kernel back end")
+    ap.add_argument("--workload", default="rgbd_20000x20000",
+                    choices=["rgbd_20000x20000", "lidar_100000x50000", "range_scanner_2000x2000"],
+                    help="synthetic pair (the default is the benchmark's workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with measured HBM bytes per pair-kernel launch")
+                    help="JSON file with measured HBM bytes per pair-kernel launch "
+                         "(default: profiles/estep_pairs_<workload>_traffic.json)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def measured_traffic(path):
+    """HBM bytes per pair-kernel launch from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def copy_kernel(mib):
@@ -94,11 +113,12 @@ def main():
     import datagen
     import paper_2103_15039_amd as L
 
-    p = datagen.rgbd_pair(trial=0)
+    p = datagen.WORKLOADS[a.workload](trial=0)
     M, N = len(p.Y), len(p.X)
+    knn = 10 if a.workload.startswith("range") else 20
     X = torch.from_numpy(p.X).cuda()
     Y = torch.from_numpy(p.Y).cuda()
-    kw = dict(k=20, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, backend=a.backend)
+    kw = dict(k=knn, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, backend=a.backend)
     torch.cuda.synchronize()
     for _ in range(a.warmup):
         L.register(X, Y, **kw)
@@ -118,9 +138,8 @@ def main():
     k_ms = prof["pair_kernel_ms"] / max(prof["launches"], 1)
     e_ms = prof["estep_ms"] / max(prof["launches"], 1)
     achieved = FLOPS_PER_PAIR * M * N / (k_ms * 1e-3)
-    traffic = None
-    if a.traffic and os.path.exists(a.traffic):
-        traffic = json.load(open(a.traffic)).get("bytes_per_launch")
+    traffic = measured_traffic(a.traffic or os.path.join(
+        ROOT, "profiles", f"estep_pairs_{a.workload}_traffic.json"))
     rot_err = float(np.degrees(np.arccos(np.clip((np.trace(p.R_gt.T @ r.R) - 1) / 2, -1, 1))))
     out = {
         "metric": "E-step pair-evals/s",
@@ -135,8 +154,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "rgbd_20000x20000", "M": M, "N": N, "em_iters": EM_ITERS,
-                   "knn": 20, "alpha_max": 30.0, "lambda": 0.2, "w0": 0.1,
+        "config": {"workload": a.workload, "M": M, "N": N, "em_iters": EM_ITERS,
+                   "knn": knn, "alpha_max": 30.0, "lambda": 0.2, "w0": 0.1,
                    "pair_kernel": a.backend},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic},

@@ -1,0 +1,121 @@
+"""GPU parity at the workloads' full sizes (20,000 x 20,000 RGBD-like and
+100,000 x 50,000 LiDAR-like), in the launch configuration the benchmark uses.
+
+* one E step: every statistic against the C form of the oracle over all
+  M x N pairs; per-source sums of a random sample of sources against the
+  dense NumPy oracle; the column identity for every source;
+* registration: the 20k pair for 25 EM iterations and the 100k x 50k pair for
+  3 iterations against the oracle driven by the C E step (rotation <= 1e-3
+  deg, translation <= 1e-5 * box diagonal, NLL per iteration 1e-6).
+Normals for the E-step checks are seeded random unit vectors and penalties
+(an E step does not care where they come from); registrations compute their
+own normals on each side.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import c_oracle as CO
+from oracle import lsgcpd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2103_15039_amd")
+
+_PAIRS = {}
+
+
+def pair(name):
+    if name not in _PAIRS:
+        _PAIRS[name] = {"rgbd": datagen.rgbd_pair, "lidar": datagen.lidar_pair}[name]()
+    return _PAIRS[name]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _c_oracle():
+    CO.build()
+
+
+def _geometry(M, seed):
+    rng = np.random.default_rng(seed)
+    n = rng.normal(size=(M, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return n.astype(np.float32), rng.uniform(0.0, 30.0, size=M).astype(np.float32)
+
+
+def _abs_scale(cols, X):
+    W = cols.A - cols.p[:, None, None] * np.eye(3)[None]
+    ab = O.Columns(p=np.abs(cols.p), A=np.abs(W) + np.abs(cols.p)[:, None, None] * np.eye(3)[None],
+                   B=np.abs(cols.B), C=np.abs(cols.C), b=None, c=None)
+    return O.lifted_stats(ab, np.abs(X))
+
+
+@pytest.mark.parametrize("name,s2", [("rgbd", 2e-3), ("rgbd", 0.05), ("lidar", 5e-3),
+                                     ("lidar", 0.2)])
+def test_estep_full_size(name, s2):
+    p = pair(name)
+    M, N = len(p.Y), len(p.X)
+    n32, a32 = _geometry(M, 1)
+    rng = np.random.default_rng(2)
+    R = datagen.random_rotation(rng, 0.01) @ p.R_gt
+    t = p.t_gt + rng.uniform(-0.02, 0.02, size=3)
+    V = O.working_volume(p.Y)
+    g = L.estep(dev(p.X), dev(p.Y), dev(n32), dev(a32), R, t, s2, w0=0.1, colstats=True)
+    assert g.V == pytest.approx(V, rel=1e-14)
+    cs = g.colstats.cpu().numpy()
+    # every column: components + outlier = 1
+    np.testing.assert_allclose(cs[:, 2] + cs[:, 14], 1.0, rtol=0, atol=1e-12)
+    assert g.sumP + g.outlier_mass == pytest.approx(N, rel=1e-12)
+    # sampled columns against the dense oracle
+    smp = np.sort(rng.choice(N, size=48, replace=False))
+    es = O.estep(p.X[smp], p.Y, n32, a32, R, t, s2, w0=0.1, V=V)
+    cols = O.columns(es.P, p.X[smp], p.Y, n32, a32, R, t)
+    assert np.all(np.abs(cs[smp, 1] - es.Ksum) <= 1e-5 * (es.Ksum + es.gamma))
+    np.testing.assert_allclose(cs[smp, 2], cols.p, rtol=1e-5, atol=1e-12)
+    W = cols.A - cols.p[:, None, None] * np.eye(3)[None]
+    iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    Wref = np.stack([W[:, a, b] for a, b in iu], axis=1)
+    np.testing.assert_allclose(cs[smp, 3:9], Wref, rtol=1e-5,
+                               atol=1e-5 * np.abs(Wref).max() + 1e-12)
+    np.testing.assert_allclose(cs[smp, 9:12], cols.B, rtol=1e-5,
+                               atol=1e-5 * np.abs(cols.B).max() + 1e-12)
+    np.testing.assert_allclose(cs[smp, 12], cols.C, rtol=1e-5, atol=1e-12)
+    # every statistic against the C oracle over all pairs
+    cc, ks = CO.estep_columns(p.X, p.Y, n32, a32, R, t, s2, w0=0.1, V=V)
+    gamma = (2 * np.pi * s2) ** 1.5 / V
+    ref = O.lifted_stats(cc, p.X, [np.sum(np.log(ks + gamma)), np.sum(gamma / (ks + gamma)),
+                                   N * np.log(0.1)])
+    scale = _abs_scale(cc, p.X.astype(np.float64))
+    scale[83:] = np.abs(ref[83:]) + N
+    d = np.abs(g.stats - ref)
+    bad = np.nonzero(d > 2e-6 * scale + 1e-300)[0]
+    assert bad.size == 0, f"stats {bad[:8]}: gpu {g.stats[bad[:4]]} ref {ref[bad[:4]]}"
+
+
+def _oracle_normals(Y, k):
+    nbr = CO.knn_indices(Y, k)
+    n, kappa, _, _ = O.local_geometry(Y, nbr)
+    return n, O.penalty_alpha(kappa, 30.0, 0.2)
+
+
+@pytest.mark.parametrize("name,iters", [("rgbd", 25), ("lidar", 3)])
+def test_register_full_size(name, iters):
+    p = pair(name)
+    k = 20
+    g = L.register(dev(p.X), dev(p.Y), k=k, max_iter=iters)
+    n, a = _oracle_normals(p.Y, k)
+    V = O.working_volume(p.Y)
+    s20 = CO.sigma2_init(p.X, p.Y, np.eye(3), np.zeros(3))
+    o = O.register(p.X, p.Y, max_iter=iters, target_normals=n, target_alpha=a, V=V,
+                   sigma2_0=s20, estep_columns=CO.register_columns_fn(p.X, p.Y, n, a, 0.1, V))
+    diag = O.bbox_diag(p.Y)
+    assert g.iters == o.iters == iters
+    assert O.rotation_error_deg(g.R, o.R) <= 1e-3
+    assert O.translation_error(g.t, o.t) <= 1e-5 * diag
+    np.testing.assert_allclose(g.nll, o.nll, rtol=1e-6)
+    assert g.sigma2 == pytest.approx(o.sigma2, rel=1e-4)
