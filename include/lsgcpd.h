@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LSGCPD_ABI_VERSION 1
+#define LSGCPD_ABI_VERSION 2
 
 typedef struct lsgcpd_ctx lsgcpd_ctx;
 typedef void *lsgcpd_stream;  /* a hipStream_t */
@@ -57,6 +57,15 @@ typedef enum {
                                        scalar cache (comparison only)           */
 #define LSGCPD_PAIRS_MFMA 4u        /* pair kernel accumulates on the FP64
                                        matrix cores (comparison only)           */
+#define LSGCPD_DENSE 8u             /* evaluate every pair.  By default the
+                                       pair kernel drops (source group, target
+                                       tile) blocks whose bounding boxes prove
+                                       that every exponential is an exact zero
+                                       in float32, and lsgcpd_register first
+                                       puts both clouds in spatial order; the
+                                       dropped terms are exact zeros, so the
+                                       results differ only in the rounding order
+                                       of the sums */
 
 typedef struct {
   double R[9]; /* row-major rotation */
@@ -201,10 +210,12 @@ lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const 
  * E step (pair kernel + per-source finalisation + block reduction).  Elapsed
  * times are summed when the call synchronises.  Off by default. */
 typedef struct {
-  int64_t launches;      /* E steps timed                                   */
-  int64_t pairs;         /* sum of M * N over those E steps                 */
-  double pair_kernel_ms; /* total time of (a)                               */
-  double estep_ms;       /* total time of (b)                               */
+  int64_t launches;        /* E steps timed                                 */
+  int64_t pairs;           /* sum of M * N over those E steps               */
+  double pair_kernel_ms;   /* total time of (a)                             */
+  double estep_ms;         /* total time of (b)                             */
+  int64_t evaluated_pairs; /* pairs (a) evaluated after dropping the blocks
+                              of exact zeros (<= pairs)                     */
 } lsgcpd_profile;
 
 lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on);

@@ -20,7 +20,8 @@ OK, E_INVALID, E_HIP, E_NOMEM, E_NUMERIC, E_UNSUPPORTED = range(6)
 EXACT_NORMALIZER = 1
 PAIRS_LDS = 2
 PAIRS_MFMA = 4
-_BACKENDS = {"scalar": 0, "lds": PAIRS_LDS, "mfma": PAIRS_MFMA}
+DENSE = 8
+_BACKENDS = {"scalar": 0, "lds": PAIRS_LDS, "mfma": PAIRS_MFMA, "dense": DENSE}
 NSTATS = 86
 
 SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
@@ -56,7 +57,7 @@ class Report(C.Structure):
 
 class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("pairs", C.c_int64), ("pair_kernel_ms", C.c_double),
-                ("estep_ms", C.c_double)]
+                ("estep_ms", C.c_double), ("evaluated_pairs", C.c_int64)]
 
 
 class LsgcpdError(RuntimeError):
@@ -305,9 +306,10 @@ def profile_enable(on=True, device=0):
 
 
 def profile_read(reset=True, device=0):
-    """Totals since the last reset: dict(launches, pairs, pair_kernel_ms, estep_ms)."""
+    """Totals since the last reset: dict(launches, pairs, pair_kernel_ms, estep_ms,
+    evaluated_pairs)."""
     ctx = context(device)
     p = Profile()
     _check(load_library().lsgcpd_profile_read(ctx, C.byref(p), 1 if reset else 0), ctx)
     return {"launches": p.launches, "pairs": p.pairs, "pair_kernel_ms": p.pair_kernel_ms,
-            "estep_ms": p.estep_ms}
+            "estep_ms": p.estep_ms, "evaluated_pairs": p.evaluated_pairs}

@@ -30,7 +30,8 @@ struct Buf {
 struct lsgcpd_ctx {
   int device = 0;
   std::string err;
-  Buf knn, rec, partial, blockstats, colS, mom_part, mom, nrm, kap, alp, trace;
+  Buf knn, rec, pts, boxes, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
+      trace, order, xperm, yperm;
   DevState *dstate = nullptr;  // device
   DevState *hstate = nullptr;  // pinned host staging
   // E-step timing: 3 events per E step (start, after pair kernel, end)
@@ -38,7 +39,7 @@ struct lsgcpd_ctx {
   std::vector<hipEvent_t> events;
   int ev_used = 0;
   int64_t prof_pairs_pending = 0;
-  lsgcpd_profile totals = {0, 0, 0.0, 0.0};
+  lsgcpd_profile totals = {0, 0, 0.0, 0.0, 0};
 };
 
 namespace {
@@ -88,20 +89,16 @@ lsgcpd_status ensure(lsgcpd_ctx *ctx, Buf &b, size_t bytes) {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
-constexpr uint32_t kKnownFlags = LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA;
+constexpr uint32_t kKnownFlags =
+    LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA | LSGCPD_DENSE;
 
-// Launch shape of the pair kernel: sources per lane (2 or 4) and target parts
-// per block (1, 2 or 4).  Defaults are the fastest measured on MI355X for the
-// 20k x 20k and 100k x 50k workloads; LSGCPD_PAIR_SOURCES / LSGCPD_PAIR_PARTS
-// override them for tuning sweeps.
-int pair_sources() {
-  const char *e = getenv("LSGCPD_PAIR_SOURCES");
-  return (e && atoi(e) == 2) ? 2 : 4;
-}
-
-int pair_parts() {
-  const char *e = getenv("LSGCPD_PAIR_PARTS");
-  return e ? atoi(e) : 4;
+// About this many work items per E step for the scalar back end (the
+// fastest measured on MI355X for the 20k x 20k and 100k x 50k workloads);
+// LSGCPD_WORK_ITEMS overrides it for tuning sweeps.
+int work_items() {
+  const char *e = getenv("LSGCPD_WORK_ITEMS");
+  const int v = e ? atoi(e) : 0;
+  return v >= 64 && v <= (1 << 20) ? v : 8192;
 }
 
 int backend_of(uint32_t flags) {
@@ -153,18 +150,23 @@ void fill_state(DevState *s, const lsgcpd_pose *g, double sigma2, double V, doub
   s->max_iter = max_iter;
 }
 
-// Target records + moments of Y, X at the state's pose + init_state.
+// Target records (record i describes target yperm[i], or target i if yperm is
+// null) and their tile boxes + moments of Y, X at the state's pose + init_state.
 lsgcpd_status setup(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
-                    const float *normals, const float *alpha, const float *pi, int64_t M,
-                    uint32_t flags, int v_auto, int s2_auto, hipStream_t st) {
-  ENSURE(rec, (size_t)M * sizeof(lsg::TRec));
+                    const float *normals, const float *alpha, const float *pi,
+                    const uint32_t *yperm, int64_t M, uint32_t flags, int v_auto, int s2_auto,
+                    hipStream_t st) {
+  ENSURE(rec, (size_t)(M + 1) * sizeof(lsg::TRec));  // + sentinel
+  ENSURE(pts, (size_t)M * sizeof(lsg::TPt));
+  ENSURE(boxes, (size_t)((M + lsg::kCullTile - 1) / lsg::kCullTile) * sizeof(lsg::TBox));
   const int nb = lsg::moments_blocks(N > M ? N : M);
   ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
-  ENSURE(mom, 32 * sizeof(double));
+  ENSURE(mom, 48 * sizeof(double));
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
-  HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, pi, M,
+  HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, pi, yperm, M,
                                   (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0,
-                                  (lsg::TRec *)ctx->rec.p, st));
+                                  (lsg::TRec *)ctx->rec.p, (lsg::TPt *)ctx->pts.p,
+                                  (lsg::TBox *)ctx->boxes.p, st));
   double *ymom = (double *)ctx->mom.p;
   double *xmom = ymom + 16;
   HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(M),
@@ -194,9 +196,11 @@ lsgcpd_status prof_record(lsgcpd_ctx *ctx, hipStream_t st) {
   return LSGCPD_OK;
 }
 
-// After the stream has been synchronised: fold the recorded events into the totals.
-lsgcpd_status prof_collect(lsgcpd_ctx *ctx) {
+// After the stream has been synchronised: fold the recorded events and the
+// pairs the pair kernel evaluated into the totals.
+lsgcpd_status prof_collect(lsgcpd_ctx *ctx, int64_t evaluated) {
   if (!ctx->prof) return LSGCPD_OK;
+  ctx->totals.evaluated_pairs += evaluated;
   for (int i = 0; i + 3 <= ctx->ev_used; i += 3) {
     float a = 0.f, b = 0.f;
     HIPCHK(hipEventElapsedTime(&a, ctx->events[i], ctx->events[i + 1]));
@@ -217,19 +221,22 @@ lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::EstepPlan &pl, const float *
                         hipStream_t st) {
   lsgcpd_status s = prof_record(ctx, st);
   if (s != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep(pl, X, N, (const lsg::TRec *)ctx->rec.p, M, ctx->dstate,
-                           (double *)ctx->partial.p, st));
+  HIPCHK(lsg::launch_estep(pl, X, N, (const lsg::TRec *)ctx->rec.p,
+                           (const lsg::TPt *)ctx->pts.p, (const lsg::TBox *)ctx->boxes.p, M,
+                           ctx->dstate, ctx->plan.p, (double *)ctx->partial.p, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_finalize(pl, X, N, w, ctx->dstate, (const double *)ctx->partial.p,
-                              (double *)ctx->blockstats.p, (double *)ctx->colS.p, colstats, st));
+  HIPCHK(lsg::launch_finalize(pl, X, N, w, ctx->dstate, ctx->plan.p,
+                              (const double *)ctx->partial.p, (double *)ctx->blockstats.p,
+                              (double *)ctx->colS.p, colstats, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   if (ctx->prof) ctx->prof_pairs_pending += M * N;
   HIPCHK(lsg::launch_reduce_mstep((double *)ctx->blockstats.p, pl.nfin_blocks, N, ctx->dstate,
-                                  trace, mode, st));
+                                  trace, lsg::estep_plan_counter(pl, ctx->plan.p), mode, st));
   return LSGCPD_OK;
 }
 
 lsgcpd_status ensure_estep(lsgcpd_ctx *ctx, const lsg::EstepPlan &pl, int64_t N) {
+  ENSURE(plan, lsg::estep_plan_bytes(pl));
   ENSURE(partial, lsg::estep_partial_bytes(pl, N));
   ENSURE(blockstats, (size_t)pl.nfin_blocks * lsg::kStats * sizeof(double));
   ENSURE(colS, (size_t)N * sizeof(double));
@@ -283,8 +290,9 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
 LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  Buf *bufs[] = {&c->knn, &c->rec, &c->partial, &c->blockstats, &c->colS,
-                 &c->mom_part, &c->mom, &c->nrm, &c->kap, &c->alp, &c->trace};
+  Buf *bufs[] = {&c->knn,  &c->rec,      &c->pts, &c->boxes, &c->plan,  &c->partial,
+                 &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm, &c->kap,
+                 &c->alp,  &c->trace,    &c->order, &c->xperm, &c->yperm};
   for (Buf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
@@ -349,10 +357,12 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   RETURN_IF(check_pose(ctx, g));
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
-  const lsg::EstepPlan pl = lsg::estep_plan(N, M, backend_of(flags), pair_sources(), pair_parts());
+  const lsg::EstepPlan pl =
+      lsg::estep_plan(N, M, backend_of(flags), (flags & LSGCPD_DENSE) ? 0 : 1, work_items());
   RETURN_IF(ensure_estep(ctx, pl, N));
   fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 20, 1);
-  RETURN_IF(setup(ctx, X, N, Y, normals, alpha, pi, M, flags, V > 0.0 ? 0 : 1, 0, st));
+  RETURN_IF(
+      setup(ctx, X, N, Y, normals, alpha, pi, nullptr, M, flags, V > 0.0 ? 0 : 1, 0, st));
   RETURN_IF(prof_reserve(ctx, 1));
   RETURN_IF(run_estep(ctx, pl, X, N, M, w, colstats, nullptr, 0, st));
   if (P)
@@ -360,7 +370,8 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
                               (const double *)ctx->colS.p, P, st));
   HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, sizeof(DevState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  RETURN_IF(prof_collect(ctx));
+  RETURN_IF(prof_collect(
+      ctx, pl.backend == lsg::kBackendScalar ? ctx->hstate->evaluated_pairs : M * N));
   const DevState &s = *ctx->hstate;
   out->sigma2 = s.sigma2;
   out->gamma = s.gamma;
@@ -418,20 +429,48 @@ LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N
   HIPCHK(lsg::launch_normals(Y, M, p->k, p->alpha_max, p->lambda, (float *)ctx->nrm.p,
                              (float *)ctx->kap.p, (float *)ctx->alp.p, ctx->knn.p, ns, st));
 
-  const lsg::EstepPlan pl = lsg::estep_plan(N, M, backend_of(p->flags), pair_sources(), pair_parts());
+  const lsg::EstepPlan pl =
+      lsg::estep_plan(N, M, backend_of(p->flags), (p->flags & LSGCPD_DENSE) ? 0 : 1, work_items());
   RETURN_IF(ensure_estep(ctx, pl, N));
+  // With tile culling both clouds are put in spatial (Morton) order once, so
+  // that a wave's sources and a tile's targets are neighbours.  Every
+  // statistic is a sum over all sources and all targets, so the order changes
+  // only the rounding of the sums.
+  const uint32_t *yperm = nullptr;
+  if (pl.backend == lsg::kBackendScalar && pl.cull && N > 256) {
+    const int nb = lsg::moments_blocks(N > M ? N : M);
+    ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
+    ENSURE(mom, 48 * sizeof(double));
+    const size_t wb = lsg::morton_workspace_bytes(N > M ? N : M);
+    ENSURE(order, wb);
+    ENSURE(xperm, (size_t)N * 3 * sizeof(float));
+    ENSURE(yperm, (size_t)M * sizeof(uint32_t));
+    double *xbox = (double *)ctx->mom.p + 32;
+    HIPCHK(lsg::launch_moments(X, N, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(N),
+                               xbox, st));
+    HIPCHK(lsg::launch_morton_order(X, N, xbox, ctx->order.p, ctx->order.cap,
+                                    (float *)ctx->xperm.p, nullptr, st));
+    X = (const float *)ctx->xperm.p;
+    HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(M),
+                               xbox, st));
+    HIPCHK(lsg::launch_morton_order(Y, M, xbox, ctx->order.p, ctx->order.cap, nullptr,
+                                    (uint32_t *)ctx->yperm.p, st));
+    yperm = (const uint32_t *)ctx->yperm.p;
+  }
   ENSURE(trace, (size_t)(p->max_iter > 0 ? p->max_iter : 1) * sizeof(double));
   const int s2_auto = p->sigma2_init > 0.0 ? 0 : 1;
   fill_state(ctx->hstate, init, s2_auto ? 1.0 : p->sigma2_init, p->V > 0.0 ? p->V : 0.0, p->w0,
              p->tol, p->newton_max, p->max_iter);
-  RETURN_IF(setup(ctx, X, N, Y, (const float *)ctx->nrm.p, (const float *)ctx->alp.p, nullptr, M,
-                  p->flags, p->V > 0.0 ? 0 : 1, s2_auto, st));
+  RETURN_IF(setup(ctx, X, N, Y, (const float *)ctx->nrm.p, (const float *)ctx->alp.p, nullptr,
+                  yperm, M, p->flags, p->V > 0.0 ? 0 : 1, s2_auto, st));
   RETURN_IF(prof_reserve(ctx, p->max_iter));
   for (int it = 0; it < p->max_iter; ++it)
     RETURN_IF(run_estep(ctx, pl, X, N, M, nullptr, nullptr, (double *)ctx->trace.p, 1, st));
   HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, sizeof(DevState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  RETURN_IF(prof_collect(ctx));
+  RETURN_IF(prof_collect(ctx, pl.backend == lsg::kBackendScalar
+                                  ? ctx->hstate->evaluated_pairs
+                                  : M * N * (ctx->hstate->iter + ctx->hstate->converged)));
   double first = ctx->hstate->nll;
   if (p->max_iter > 0 && ctx->hstate->iter + ctx->hstate->converged > 0) {
     HIPCHK(hipMemcpy(&first, ctx->trace.p, sizeof(double), hipMemcpyDeviceToHost));
@@ -468,6 +507,6 @@ LSG_API lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on) {
 LSG_API lsgcpd_status lsgcpd_profile_read(lsgcpd_ctx *ctx, lsgcpd_profile *out, int reset) {
   if (!ctx) return LSGCPD_E_INVALID;
   if (out) *out = ctx->totals;
-  if (reset) ctx->totals = lsgcpd_profile{0, 0, 0.0, 0.0};
+  if (reset) ctx->totals = lsgcpd_profile{0, 0, 0.0, 0.0, 0};
   return LSGCPD_OK;
 }

@@ -24,19 +24,21 @@
 // exact FP64 functions of the float32 inputs and all sums are FP64.
 //
 // Back ends (same pair arithmetic, different data movement):
-//  * estep_pairs_scalar<S> (default): all lanes of a wave take the same target
+//  * estep_pairs_items (default): all lanes of a wave take the same target
 //    at the same time, so the target record is wave-uniform and is read
 //    through the scalar data cache straight into SGPR operands; each lane keeps
-//    S sources in registers.
+//    4 sources in registers.  Target tiles that provably hold only exact-zero
+//    exponentials for a source group are dropped, and the rest is cut into
+//    balanced work items.
 //  * estep_pairs_lds<S>: the block stages tiles of target records in LDS and
 //    every wave reads them back with broadcast LDS loads.
 //  * estep_mfma: V_MFMA_F64_16X16X4 multiplies 16 (sources) x 4 (targets)
 //    exponentials by 4 x 16 features.  On gfx950 matrix and vector
 //    instructions of a SIMD do not execute concurrently and the FP64 matrix
 //    rate equals the FP64 vector rate, so this is kept only for comparison.
-// Target chunks (split-M) give enough blocks for small N; the per-chunk
-// partial sums are combined in a fixed order by estep_finalize, so results are
-// bitwise reproducible.
+// Work items (scalar) or target chunks (LDS, MFMA) give enough blocks for
+// small N; their partial sums are combined in a fixed order by estep_finalize,
+// so results are bitwise reproducible.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -78,11 +80,12 @@ __device__ __forceinline__ Src load_src(const float *__restrict__ X, int n, int 
   return o;
 }
 
-// e = K_mn / rho_n of one pair; negsc = -sqrt(c).  Every operation is written
-// out so that every kernel (and the P dump) produces the same value.
-__device__ __forceinline__ double pair_exp(const Src &s, double y0, double y1, double y2,
-                                           double a0, double a1, double a2, double l,
-                                           double negsc) {
+// Exponent z = log2(e_mn) = l_m - c d_mn of one pair; negsc = -sqrt(c).
+// Every operation is written out so that every kernel (and the P dump)
+// produces the same value.
+__device__ __forceinline__ double pair_z(const Src &s, double y0, double y1, double y2,
+                                         double a0, double a1, double a2, double l,
+                                         double negsc) {
   const double r0 = fma(negsc, y0, s.x0);
   const double r1 = fma(negsc, y1, s.x1);
   const double r2 = fma(negsc, y2, s.x2);
@@ -92,14 +95,27 @@ __device__ __forceinline__ double pair_exp(const Src &s, double y0, double y1, d
   double p = a0 * r0;
   p = fma(a1, r1, p);
   p = fma(a2, r2, p);
-  const double z = fma(-p, p, q);
+  return fma(-p, p, q);
+}
+
+// e = K_mn / rho_n = 2^z, the only float32 step
+__device__ __forceinline__ double exp2_of(double z) {
   return (double)__builtin_amdgcn_exp2f((float)z);
 }
 
-__device__ __forceinline__ double rec_exp(const Src &s, const TRec &t, double negsc) {
-  return pair_exp(s, t.y[0], t.y[1], t.y[2], t.a[0], t.a[1], t.a[2], t.l, negsc);
+__device__ __forceinline__ double rec_z(const Src &s, const TRec &t, double negsc) {
+  return pair_z(s, t.y[0], t.y[1], t.y[2], t.a[0], t.a[1], t.a[2], t.l, negsc);
 }
 
+__device__ __forceinline__ double rec_exp(const Src &s, const TRec &t, double negsc) {
+  return exp2_of(rec_z(s, t, negsc));
+}
+
+// Below this exponent the float32 exp2 is exactly +0 (2^-160 is far below the
+// smallest denormal, 2^-149), so such pairs add exact zeros to every sum.
+constexpr double kZeroExponent = -160.0;
+
+// Adds one target's contribution to the S sources of this lane.
 template <int S>
 __device__ __forceinline__ void accumulate(const Src (&x)[S], const TRec &t, double negsc,
                                            double (&acc)[S][kFeatUsed]) {
@@ -112,80 +128,287 @@ __device__ __forceinline__ void accumulate(const Src (&x)[S], const TRec &t, dou
   }
 }
 
+// Exact culling.  For sources whose scaled positions lie in the box
+// [blo, bhi] and targets whose positions lie in [lo, hi] with log-priors
+// <= lmax, every pair has |r|^2 >= d2 = sum_a gap_a^2 (gap_a = distance between
+// the two intervals on axis a after scaling the targets by sqrt(c)), and since
+// the plane term is non-negative, z = l - |r|^2 - p^2 <= lmax - d2.  If that
+// bound is below kZeroExponent every such exponential is an exact zero and
+// the pairs can be skipped without changing any sum by a single bit.  A
+// single target is the box lo = hi = y_m, lmax = l_m.
+__device__ __forceinline__ bool box_live(const double *lo, const double *hi, double lmax,
+                                         const double (&blo)[3], const double (&bhi)[3],
+                                         double sc) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double g = fmax(0.0, fmax(sc * lo[a] - bhi[a], blo[a] - sc * hi[a]));
+    d2 = fma(g, g, d2);
+  }
+  return lmax - d2 >= kZeroExponent;
+}
+
 // ------------------------------------------------------- pair kernel (VALU)
-// Scalar-cache back end.  The block's four waves form 4/Q source groups of Q
-// waves; a group owns 64*S sources (S per lane) and its Q waves split the
-// block's target chunk into Q parts.  Waves of different groups read the same
-// records at about the same time (scalar-cache reuse 4/Q); the Q partial sums
-// of a group are added through LDS in a fixed order, so a block writes one
-// partial per source (Q times fewer partials than one per wave).
-template <int S, int Q>
-__global__ __launch_bounds__(kBlock) void estep_pairs_scalar(const float *__restrict__ X, int N,
-                                                             const TRec *__restrict__ rec,
-                                                             int64_t M,
-                                                             const DevState *__restrict__ st,
-                                                             int64_t mchunk, int nsplit,
-                                                             double *__restrict__ partial) {
+// Scalar-cache back end with exact tile culling and balanced work items.
+//
+// Sources form groups of kGroup = 256 consecutive points (4 per lane of a
+// wave); targets form tiles of kCullTile = 64 consecutive records.  Once per
+// E step
+//  * cull_groups (one block per group) takes the group's bounding box in
+//    scaled coordinates and lists, in increasing order, the tiles that
+//    box_live cannot rule out (with culling off: every tile);
+//  * cull_items (one block) cuts every group's list into items of L tiles,
+//    with L chosen so that there are at most about `target` items in all, and
+//    writes the item -> group map;
+//  * estep_pairs_items runs one block per item: the 4 waves hold the same 256
+//    sources and take every 4th tile of the item.  Per tile, one lane per
+//    target tests the target against the group box, and the wave walks the
+//    set bits of the resulting 64-bit mask.  The 4 waves' sums are added
+//    through LDS in a fixed order and the block writes one partial per source
+//    and feature.
+// Groups near much of the target cloud get many items and isolated ones few,
+// so the blocks carry about equal work whatever the culling removes.  All
+// counts are integers and every sum runs in a fixed order, so results are
+// bitwise reproducible.
+constexpr int kGroup = 256;
+
+// Scaled-coordinate bounding box of each source group (kept for the pair
+// kernel), then the live tiles in increasing order.
+__global__ __launch_bounds__(kBlock) void cull_groups(const float *__restrict__ X, int N,
+                                                      const DevState *__restrict__ st,
+                                                      const TBox *__restrict__ boxes,
+                                                      int ntiles, int *__restrict__ counts,
+                                                      double *__restrict__ gbox,
+                                                      int *__restrict__ list) {
   if (st->done) return;
-  constexpr int G = 4 / Q;  // source groups per block
-  const int split = blockIdx.x % nsplit;
-  const int sb = blockIdx.x / nsplit;
+  const int g = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double R[9], t[3];
+  for (int i = 0; i < 9; ++i) R[i] = st->R[i];
+  for (int i = 0; i < 3; ++i) t[i] = st->t[i];
+  const double sc = sqrt_c_of(st);
+  const int n = g * kGroup + threadIdx.x;
+  const Src x = load_src(X, n, N, R, t, sc);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (n < N) {
+    lo[0] = hi[0] = x.x0;
+    lo[1] = hi[1] = x.x1;
+    lo[2] = hi[2] = x.x2;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fmin(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmax(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+  __shared__ double bx[4][6];
+  __shared__ int wc[4];
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) {
+      bx[wave][a] = lo[a];
+      bx[wave][3 + a] = hi[a];
+    }
+  __syncthreads();
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = fmin(fmin(bx[0][a], bx[1][a]), fmin(bx[2][a], bx[3][a]));
+    hi[a] = fmax(fmax(bx[0][3 + a], bx[1][3 + a]), fmax(bx[2][3 + a], bx[3][3 + a]));
+  }
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) {
+      gbox[g * 8 + a] = lo[a];
+      gbox[g * 8 + 3 + a] = hi[a];
+    }
+  int *out = list + (int64_t)g * ntiles;
+  int base = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
+    const int ti = t0 + threadIdx.x;
+    const bool live =
+        ti < ntiles && box_live(boxes[ti].lo, boxes[ti].hi, boxes[ti].lmax, lo, hi, sc);
+    const uint64_t bal = __ballot(live);
+    if (lane == 0) wc[wave] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wave; ++w) off += wc[w];
+    if (live) out[off + __popcll(bal & ((1ull << lane) - 1ull))] = ti;
+    base += wc[0] + wc[1] + wc[2] + wc[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[g] = base;
+}
+
+// Items: L tiles each (L a multiple of 4, at least 4), about `target` in all.
+// Without culling every group lists all tiles and no per-group pass runs.
+// Also clears the counter of evaluated pairs for the pair kernel.
+template <bool CULL>
+__global__ __launch_bounds__(kBlock) void cull_items(const DevState *__restrict__ st,
+                                                     const int *__restrict__ counts,
+                                                     int ngroups, int ntiles, int target,
+                                                     int cap, CullHdr *__restrict__ hdr,
+                                                     int *__restrict__ off,
+                                                     int *__restrict__ map,
+                                                     unsigned long long *__restrict__ evcount) {
+  if (st->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ int64_t red[4];
+  __shared__ int scan[kBlock];
+  int64_t tiles = 0;
+  if (CULL) {
+    for (int g = threadIdx.x; g < ngroups; g += kBlock) tiles += counts[g];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tiles += __shfl_xor(tiles, o, 64);
+    if (lane == 0) red[wave] = tiles;
+    __syncthreads();
+    tiles = red[0] + red[1] + red[2] + red[3];
+  } else {
+    tiles = (int64_t)ngroups * ntiles;
+  }
+  int64_t L = (tiles + target - 1) / target;
+  L = L < 4 ? 4 : (L + 3) / 4 * 4;
+  int run = 0;
+  for (int g0 = 0; g0 < ngroups; g0 += kBlock) {
+    const int g = g0 + threadIdx.x;
+    const int64_t cnt = g < ngroups ? (CULL ? counts[g] : ntiles) : 0;
+    const int v = (int)((cnt + L - 1) / L);
+    scan[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int add = threadIdx.x >= d ? scan[threadIdx.x - d] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const int first = run + scan[threadIdx.x] - v;
+    if (g < ngroups) {
+      off[g] = first;
+      for (int k = 0; k < v && first + k < cap; ++k) map[first + k] = g;
+    }
+    run += scan[kBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    off[ngroups] = run;
+    hdr->items = run < cap ? run : cap;
+    hdr->tiles_per_item = (int)L;
+    *evcount = 0ull;
+  }
+}
+
+template <bool CULL>
+// 4 waves per SIMD (at most 128 VGPRs) hide the scalar-load latency
+__global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
+    const float *__restrict__ X, int N, const TRec *__restrict__ rec,
+    const TPt *__restrict__ pts, int64_t M, const DevState *__restrict__ st,
+    const CullHdr *__restrict__ hdr, const int *__restrict__ counts,
+    const int *__restrict__ off, const int *__restrict__ map, const int *__restrict__ list,
+    const double *__restrict__ gbox, int ntiles, unsigned long long *__restrict__ evcount,
+    double *__restrict__ partial) {
+  constexpr int S = 4;
+  if (st->done) return;
+  const int item = blockIdx.x;
+  if (item >= hdr->items) return;
   // the wave index is wave-uniform; readfirstlane tells the compiler so, which
-  // keeps the target loop counter (and so the record loads) scalar
+  // keeps the tile loop (and so the record loads) scalar
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int grp = wave % G, part = wave / G;
-  const int64_t m0 = (int64_t)split * mchunk;
-  const int64_t m1 = m0 + mchunk < M ? m0 + mchunk : M;
-  const int64_t qc = (m1 - m0 + Q - 1) / Q;
-  const int64_t w0 = m0 + part * qc < m1 ? m0 + part * qc : m1;
-  const int64_t w1 = w0 + qc < m1 ? w0 + qc : m1;
+  const int g = map[item];
+  const int L = hdr->tiles_per_item;
+  const int k0 = (item - off[g]) * L;
+  const int cnt = CULL ? counts[g] : ntiles;
+  const int kn = cnt - k0 < L ? cnt - k0 : L;
+  const int *tl = list + (int64_t)g * ntiles + k0;
   double R[9], t[3];
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
   const double sc = sqrt_c_of(st);
   const double negsc = -sc;
   Src x[S];
-  int nidx[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    nidx[s] = (sb * G + grp) * 64 * S + s * 64 + lane;
-    x[s] = load_src(X, nidx[s], N, R, t, sc);
-  }
+  for (int s = 0; s < S; ++s) x[s] = load_src(X, g * kGroup + s * 64 + lane, N, R, t, sc);
   double acc[S][kFeatUsed];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int c = 0; c < kFeatUsed; ++c) acc[s][c] = 0.0;
-  for (int64_t m = w0; m < w1; ++m) accumulate<S>(x, rec[m], negsc, acc);
-  if constexpr (Q == 1) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (nidx[s] < N) {
-#pragma unroll
-        for (int c = 0; c < kFeatUsed; ++c)
-          partial[((size_t)split * kFeatUsed + c) * N + nidx[s]] = acc[s][c];
+  double blo[3], bhi[3];
+  if constexpr (CULL)
+    for (int a = 0; a < 3; ++a) {
+      blo[a] = gbox[g * 8 + a];
+      bhi[a] = gbox[g * 8 + 3 + a];
+    }
+  const int Mi = (int)M;  // M < 2^27: 32-bit scalar loop arithmetic
+  // the wave's tiles are j = wave, wave + 4, ...; their indices are fetched 64
+  // at a time, one per lane, and read back with readlane
+  const int nt = kn > wave ? (kn - wave + 3) / 4 : 0;
+  int tv = 0;
+  int done = 0;  // targets this wave evaluated
+  if constexpr (CULL) {
+    for (int q = 0; q < nt; ++q) {
+      if ((q & 63) == 0) {
+        const int jl = wave + 4 * (q + lane);
+        tv = jl < kn ? tl[jl] : 0;
       }
+      const int ti = __builtin_amdgcn_readlane(tv, q & 63);
+      const int n1 = Mi - ti * kCullTile < kCullTile ? Mi - ti * kCullTile : kCullTile;
+      // the tile's targets that the group box cannot rule out: one lane per
+      // target tests it, the ballot is the (wave-uniform) mask
+      bool on = false;
+      if (lane < n1) {
+        const TPt &p = pts[(int64_t)ti * kCullTile + lane];
+        on = box_live(p.y, p.y, p.l, blo, bhi, sc);
+      }
+      uint64_t mk = __ballot(on);
+      done += __popcll(mk);
+      const TRec *tr = rec + (int64_t)ti * kCullTile;
+      // an empty mask visits the sentinel record rec[M] (exponent -inf, all
+      // features 0), which adds exact zeros; so the walk over the set bits is
+      // a do-while and one set of accumulators flows through it
+      if (mk == 0) {
+        mk = 1;
+        tr = rec + M;
+      }
+      do {
+        accumulate<S>(x, tr[__builtin_ctzll(mk)], negsc, acc);
+        mk &= mk - 1;
+      } while (mk);
     }
   } else {
-    __shared__ double red[4 - G][kFeatUsed][64];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (part > 0)
-#pragma unroll
-        for (int c = 0; c < kFeatUsed; ++c) red[wave - G][c][lane] = acc[s][c];
-      __syncthreads();
-      if (part == 0 && nidx[s] < N) {
-#pragma unroll
-        for (int c = 0; c < kFeatUsed; ++c) {
-          double v = acc[s][c];
-#pragma unroll
-          for (int p = 1; p < Q; ++p) v += red[p * G + grp - G][c][lane];
-          partial[((size_t)split * kFeatUsed + c) * N + nidx[s]] = v;
-        }
-      }
-      __syncthreads();
+    for (int q = 0; q < nt; ++q) {
+      if ((q & 63) == 0) tv = k0 + wave + 4 * (q + lane);
+      const int ti = __builtin_amdgcn_readlane(tv, q & 63);
+      const TRec *tr = rec + (int64_t)ti * kCullTile;
+      const int n1 = Mi - ti * kCullTile < kCullTile ? Mi - ti * kCullTile : kCullTile;
+      done += n1;
+      int m = 0;
+      // a tile is never empty; a do-while keeps one set of accumulators
+      do {
+        accumulate<S>(x, tr[m], negsc, acc);
+      } while (++m < n1);
     }
+  }
+  __shared__ int wdone[4];
+  if (lane == 0) wdone[wave] = done;
+  __shared__ double red[3][kFeatUsed][64];
+  double *dst = partial + (size_t)item * kFeatUsed * kGroup;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    if (wave > 0)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) red[wave - 1][c][lane] = acc[s][c];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c)
+        dst[c * kGroup + s * 64 + lane] =
+            ((acc[s][c] + red[0][c][lane]) + red[1][c][lane]) + red[2][c][lane];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const unsigned long long nv =
+        (unsigned long long)(N - g * kGroup < kGroup ? N - g * kGroup : kGroup);
+    atomicAdd(evcount,
+              nv * (unsigned long long)(wdone[0] + wdone[1] + wdone[2] + wdone[3]));
   }
 }
 
@@ -305,10 +528,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kFinBlock = 64;
 
+// ITEMS: partials per work item ([item][feature][256], the items of source
+// group g are off[g] .. off[g+1]-1); otherwise per target chunk
+// ([chunk][feature][N]).
+template <bool ITEMS>
 __global__ __launch_bounds__(kFinBlock) void estep_finalize(
     const float *__restrict__ X, int N, const float *__restrict__ w,
     const DevState *__restrict__ st, const double *__restrict__ partial, int nsplit,
-    double *__restrict__ blockstats, double *__restrict__ colS, double *__restrict__ colstats) {
+    const int *__restrict__ off, double *__restrict__ blockstats, double *__restrict__ colS,
+    double *__restrict__ colstats) {
   if (st->done) return;
   const int n = blockIdx.x * kFinBlock + threadIdx.x;
   double p = 0.0, W[6] = {0, 0, 0, 0, 0, 0}, B[3] = {0, 0, 0}, C = 0.0, lg = 0.0, outl = 0.0,
@@ -318,9 +546,33 @@ __global__ __launch_bounds__(kFinBlock) void estep_finalize(
     double T[kFeatUsed];
 #pragma unroll
     for (int c = 0; c < kFeatUsed; ++c) T[c] = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp)
+    if (ITEMS) {
+      // items in increasing order; the loads of 4 items are issued together
+      const int g = n / kGroup, j = n % kGroup;
+      const int i1 = off[g + 1];
+      int it = off[g];
+      for (; it + 4 <= i1; it += 4) {
+        double v[4][kFeatUsed];
 #pragma unroll
-      for (int c = 0; c < kFeatUsed; ++c) T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < kFeatUsed; ++c)
+            v[u][c] = partial[((size_t)(it + u) * kFeatUsed + c) * kGroup + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < kFeatUsed; ++c) T[c] += v[u][c];
+      }
+      for (; it < i1; ++it)
+#pragma unroll
+        for (int c = 0; c < kFeatUsed; ++c)
+          T[c] += partial[((size_t)it * kFeatUsed + c) * kGroup + j];
+    } else {
+      for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+        for (int c = 0; c < kFeatUsed; ++c)
+          T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
+    }
     const double wn = w ? (double)w[n] : st->w0;
     const double rho = (1.0 - wn) / wn;
     const double gam = gamma_of(st);
@@ -413,9 +665,11 @@ __global__ void dump_P(const float *__restrict__ X, int N, const TRec *__restric
 // ----------------------------------------------------------- target records
 __global__ void prep_targets(const float *__restrict__ Y, const float *__restrict__ nrm,
                              const float *__restrict__ alpha, const float *__restrict__ pi,
-                             int64_t M, int exact, TRec *__restrict__ rec) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
+                             const uint32_t *__restrict__ perm, int64_t M, int exact,
+                             TRec *__restrict__ rec, TPt *__restrict__ pts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int64_t m = perm ? (int64_t)perm[i] : i;  // record i describes target m
   const double y0 = Y[3 * m], y1 = Y[3 * m + 1], y2 = Y[3 * m + 2];
   const double n0 = nrm[3 * m], n1 = nrm[3 * m + 1], n2 = nrm[3 * m + 2];
   const double al = alpha[m];
@@ -443,7 +697,51 @@ __global__ void prep_targets(const float *__restrict__ Y, const float *__restric
   r.f[8] = y2 + al * s * n2;
   r.f[9] = y0 * y0 + y1 * y1 + y2 * y2 + al * s * s;
   r.pad = 0.0;
-  rec[m] = r;
+  rec[i] = r;
+  if (i == 0) {  // sentinel rec[M]: exponent -inf, no features
+    TRec z = {};
+    z.l = -INFINITY;
+    rec[M] = z;
+  }
+  TPt q;
+  for (int a = 0; a < 3; ++a) q.y[a] = r.y[a];
+  q.l = r.l;
+  pts[i] = q;
+}
+
+// Bounding box and largest log-prior of every tile of kCullTile records.
+// One wave per tile, one lane per target.
+__global__ void tile_boxes(const TPt *__restrict__ pts, int64_t M, TBox *__restrict__ box) {
+  const int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t ntiles = (M + kCullTile - 1) / kCullTile;
+  if (t >= ntiles) return;  // wave-uniform
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double lmax = -INFINITY;
+  const int64_t m = t * kCullTile + lane;
+  if (m < M) {
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = pts[m].y[a];
+    lmax = pts[m].l;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fmin(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmax(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+    lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
+  }
+  if (lane == 0) {
+    TBox b;
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = lo[a];
+      b.hi[a] = hi[a];
+    }
+    b.lmax = lmax;
+    b.pad = 0.0;
+    box[t] = b;
+  }
 }
 
 // ---------------------------------------------------------------- moments
@@ -511,17 +809,23 @@ __global__ void moments_final(const double *__restrict__ part, int nblk, double 
 
 // ----------------------------------------------------------------- launchers
 
-EstepPlan estep_plan(int64_t N, int64_t M, int backend, int srcs_per_lane, int parts) {
-  EstepPlan pl;
+EstepPlan estep_plan(int64_t N, int64_t M, int backend, int cull, int target_items) {
+  EstepPlan pl = {};
   pl.backend = backend;
-  pl.srcs_per_lane = backend == kBackendScalar && srcs_per_lane == 4 ? 4 : kPairS;
-  pl.parts = parts == 1 || parts == 4 ? parts : 2;
-  // sources per block: the scalar back end has 4/Q groups of 64*S sources,
-  // the LDS back end gives every thread its own S, MFMA 64 per wave
-  const int64_t per_block = backend == kBackendScalar
-                                ? (int64_t)(4 / pl.parts) * 64 * pl.srcs_per_lane
-                            : backend == kBackendLds ? (int64_t)kBlock * pl.srcs_per_lane
-                                                     : (int64_t)kBlock;
+  pl.nfin_blocks = (int)((N + kFinBlock - 1) / kFinBlock);
+  if (backend == kBackendScalar) {
+    pl.ngroups = (int)((N + kGroup - 1) / kGroup);
+    pl.ntiles = (int)((M + kCullTile - 1) / kCullTile);
+    // the live-tile lists take 4 bytes per (group, tile); beyond 2^28 of
+    // them (1 GiB) every pair is evaluated
+    pl.cull = cull && (int64_t)pl.ngroups * pl.ntiles <= ((int64_t)1 << 28);
+    pl.target_items = target_items >= 64 ? target_items : 8192;
+    // sum_g ceil(count_g / L) < tiles / L + ngroups <= target + ngroups
+    pl.cap_items = pl.target_items + pl.ngroups;
+    return pl;
+  }
+  // LDS and MFMA back ends: sources per block, target chunks (split-M)
+  const int64_t per_block = backend == kBackendLds ? (int64_t)kBlock * kPairS : (int64_t)kBlock;
   pl.nsrc_blocks = (int)((N + per_block - 1) / per_block);
   // about 1024 blocks (4096 waves) fill the 256 CUs; every split adds one
   // FP64 partial per source and feature, so no more splits than that
@@ -536,46 +840,105 @@ EstepPlan estep_plan(int64_t N, int64_t M, int backend, int srcs_per_lane, int p
   ns = (M + chunk - 1) / chunk;
   pl.nsplit = (int)ns;
   pl.mchunk = chunk;
-  pl.nfin_blocks = (int)((N + kFinBlock - 1) / kFinBlock);
   return pl;
 }
 
 size_t estep_partial_bytes(const EstepPlan &pl, int64_t N) {
+  if (pl.backend == kBackendScalar)
+    return (size_t)pl.cap_items * kFeatUsed * kGroup * sizeof(double);
   return (size_t)pl.nsplit * kFeatUsed * (size_t)N * sizeof(double);
 }
 
+// Work-item plan layout: CullHdr, evaluated-pair counter, counts[ngroups],
+// off[ngroups + 1], map[cap_items], gbox[ngroups][8], list[ngroups * ntiles].
+namespace {
+struct PlanPtrs {
+  CullHdr *hdr;
+  unsigned long long *evcount;
+  int *counts, *off, *map, *list;
+  double *gbox;
+};
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+PlanPtrs plan_ptrs(const EstepPlan &pl, void *ws) {
+  char *p = (char *)ws;
+  PlanPtrs q;
+  q.hdr = (CullHdr *)p;
+  p += align256(sizeof(CullHdr));
+  q.evcount = (unsigned long long *)p;
+  p += 256;
+  q.counts = (int *)p;
+  p += align256((size_t)pl.ngroups * sizeof(int));
+  q.off = (int *)p;
+  p += align256((size_t)(pl.ngroups + 1) * sizeof(int));
+  q.map = (int *)p;
+  p += align256((size_t)pl.cap_items * sizeof(int));
+  q.gbox = (double *)p;
+  p += align256((size_t)pl.ngroups * 8 * sizeof(double));
+  q.list = (int *)p;
+  return q;
+}
+}  // namespace
+
+size_t estep_plan_bytes(const EstepPlan &pl) {
+  if (pl.backend != kBackendScalar) return 256;
+  size_t b = align256(sizeof(CullHdr)) + 256 + align256((size_t)pl.ngroups * sizeof(int)) +
+             align256((size_t)(pl.ngroups + 1) * sizeof(int)) +
+             align256((size_t)pl.cap_items * sizeof(int)) +
+             align256((size_t)pl.ngroups * 8 * sizeof(double));
+  if (pl.cull) b += (size_t)pl.ngroups * pl.ntiles * sizeof(int);
+  return b;
+}
+
+unsigned long long *estep_plan_counter(const EstepPlan &pl, void *plan_ws) {
+  return pl.backend == kBackendScalar ? plan_ptrs(pl, plan_ws).evcount : nullptr;
+}
+
 hipError_t launch_estep(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
-                        int64_t M, const DevState *s, double *partial, hipStream_t st) {
+                        const TPt *pts, const TBox *boxes, int64_t M, DevState *s,
+                        void *plan_ws, double *partial, hipStream_t st) {
+  if (pl.backend == kBackendScalar) {
+    const PlanPtrs q = plan_ptrs(pl, plan_ws);
+    if (pl.cull) {
+      hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.ngroups), dim3(kBlock), 0, st, X, (int)N,
+                         s, boxes, pl.ntiles, q.counts, q.gbox, q.list);
+      hipLaunchKernelGGL(cull_items<true>, dim3(1), dim3(kBlock), 0, st, s, q.counts,
+                         pl.ngroups, pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off,
+                         q.map, q.evcount);
+      hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.cap_items), dim3(kBlock), 0,
+                         st, X, (int)N, rec, pts, M, s, q.hdr, q.counts, q.off, q.map, q.list,
+                         q.gbox, pl.ntiles, q.evcount, partial);
+    } else {
+      hipLaunchKernelGGL(cull_items<false>, dim3(1), dim3(kBlock), 0, st, s, q.counts,
+                         pl.ngroups, pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off,
+                         q.map, q.evcount);
+      hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.cap_items), dim3(kBlock), 0,
+                         st, X, (int)N, rec, pts, M, s, q.hdr, q.counts, q.off, q.map, q.list,
+                         q.gbox, pl.ntiles, q.evcount, partial);
+    }
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)(pl.nsrc_blocks * pl.nsplit));
   if (pl.backend == kBackendMfma)
     hipLaunchKernelGGL(estep_mfma, grid, dim3(kBlock), 0, st, X, (int)N, rec, M, s, pl.mchunk,
                        pl.nsplit, partial);
-  else if (pl.backend == kBackendLds)
+  else
     hipLaunchKernelGGL(estep_pairs_lds<kPairS>, grid, dim3(kBlock), 0, st, X, (int)N, rec, M, s,
                        pl.mchunk, pl.nsplit, partial);
-  else {
-#define LSG_PAIRS(S_, Q_)                                                                  \
-  hipLaunchKernelGGL((estep_pairs_scalar<S_, Q_>), grid, dim3(kBlock), 0, st, X, (int)N, rec, \
-                     M, s, pl.mchunk, pl.nsplit, partial)
-    if (pl.srcs_per_lane == 4) {
-      if (pl.parts == 1) LSG_PAIRS(4, 1);
-      else if (pl.parts == 2) LSG_PAIRS(4, 2);
-      else LSG_PAIRS(4, 4);
-    } else {
-      if (pl.parts == 1) LSG_PAIRS(2, 1);
-      else if (pl.parts == 2) LSG_PAIRS(2, 2);
-      else LSG_PAIRS(2, 4);
-    }
-#undef LSG_PAIRS
-  }
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const float *w,
-                           const DevState *s, const double *partial, double *blockstats,
-                           double *colS, double *colstats, hipStream_t st) {
-  hipLaunchKernelGGL(estep_finalize, dim3((unsigned)pl.nfin_blocks), dim3(kFinBlock), 0, st, X,
-                     (int)N, w, s, partial, pl.nsplit, blockstats, colS, colstats);
+                           const DevState *s, const void *plan_ws, const double *partial,
+                           double *blockstats, double *colS, double *colstats, hipStream_t st) {
+  if (pl.backend == kBackendScalar)
+    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.nfin_blocks), dim3(kFinBlock), 0,
+                       st, X, (int)N, w, s, partial, 0,
+                       (const int *)plan_ptrs(pl, (void *)plan_ws).off, blockstats, colS,
+                       colstats);
+  else
+    hipLaunchKernelGGL(estep_finalize<false>, dim3((unsigned)pl.nfin_blocks), dim3(kFinBlock), 0,
+                       st, X, (int)N, w, s, partial, pl.nsplit, (const int *)nullptr, blockstats,
+                       colS, colstats);
   return hipGetLastError();
 }
 
@@ -590,10 +953,13 @@ hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, 
 }
 
 hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
-                               const float *pi, int64_t M, int exact, TRec *rec,
-                               hipStream_t st) {
+                               const float *pi, const uint32_t *perm, int64_t M, int exact,
+                               TRec *rec, TPt *pts, TBox *boxes, hipStream_t st) {
   hipLaunchKernelGGL(prep_targets, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, Y,
-                     normals, alpha, pi, M, exact, rec);
+                     normals, alpha, pi, perm, M, exact, rec, pts);
+  const int64_t ntiles = (M + kCullTile - 1) / kCullTile;
+  hipLaunchKernelGGL(tile_boxes, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, pts, M,
+                     boxes);
   return hipGetLastError();
 }
 

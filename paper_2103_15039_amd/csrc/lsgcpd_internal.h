@@ -21,6 +21,22 @@ struct TRec {
   double pad;
 };
 constexpr int kRecDoubles = 18;
+
+// Bounding box of a tile of kCullTile consecutive target records and their
+// largest log-prior (for exact culling in the pair kernel).
+struct TBox {
+  double lo[3];
+  double hi[3];
+  double lmax;
+  double pad;
+};
+constexpr int kCullTile = 64;
+
+// Position and log-prior of a target record, packed for the culling tests.
+struct TPt {
+  double y[3];
+  double l;
+};
 constexpr int kFeatUsed = 11;   // feature 0 (= 1) and f[0..9]
 constexpr int kStats = 86;
 constexpr int kColStats = 16;
@@ -47,6 +63,7 @@ struct DevState {
   double pd;          // sum P d at the E-step pose
   double nll;         // Eq. 4 at the E-step pose
   double gamma;
+  int64_t evaluated_pairs;  // pairs the pair kernel evaluated (scalar back end)
   int32_t iter;       // M steps taken
   int32_t done;       // 1 once tol stopped EM (later kernels return at once)
   int32_t converged;
@@ -78,41 +95,74 @@ int moments_blocks(int64_t n);
 hipError_t launch_init_state(DevState *s, const double *ymom, const double *xmom, int64_t M,
                              int64_t N, int v_auto, int s2_auto, hipStream_t st);
 
-// Target records.
-hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
-                               const float *pi, int64_t M, int exact, TRec *rec, hipStream_t st);
+// Points sorted by a Morton code of their position (box = moments of the
+// cloud): writes the permuted cloud to `out` and/or the permutation (sorted
+// position -> original index) to `perm`; either may be null.
+size_t morton_workspace_bytes(int64_t n);
+hipError_t launch_morton_order(const float *P, int64_t n, const double *box, void *work,
+                               size_t work_bytes, float *out, uint32_t *perm, hipStream_t st);
 
-// E step: fused exponent + accumulation over target chunks, then per-source
-// finalisation + lift to the 86 statistics, then the deterministic reduction.
+// Target records.
+// Record i describes target perm[i] (perm may be null); rec[M] is a sentinel
+// whose exponent is -inf (rec holds M + 1 records); boxes gets one TBox per
+// tile of kCullTile records.
+hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
+                               const float *pi, const uint32_t *perm, int64_t M, int exact,
+                               TRec *rec, TPt *pts, TBox *boxes, hipStream_t st);
+
+// E step: fused exponent + accumulation (over live target tiles in balanced
+// work items, or over target chunks), then per-source finalisation + lift to
+// the 86 statistics, then the deterministic reduction.
 constexpr int kBackendScalar = 0;  // target records via the scalar cache (default)
 constexpr int kBackendLds = 1;     // target records staged in LDS
 constexpr int kBackendMfma = 2;    // FP64 matrix-core accumulation
-constexpr int kPairS = 2;          // sources per lane in the VALU back ends
+constexpr int kPairS = 2;          // sources per thread in the LDS back end
 
 struct EstepPlan {
   int backend;
-  int srcs_per_lane;  // sources per lane of the VALU back ends (2 or 4)
-  int parts;          // target sub-ranges per block of the scalar back end (1, 2, 4)
-  int nsplit;      // target chunks
-  int64_t mchunk;  // targets per chunk (multiple of the tile)
-  int nsrc_blocks; // source blocks of the accumulation kernel
-  int nfin_blocks; // blocks of the finalisation kernel
+  // scalar back end (work items over live tiles)
+  int cull;          // drop target tiles whose exponentials are all exact zeros
+  int ngroups;       // source groups of 256
+  int ntiles;        // target tiles of kCullTile records
+  int target_items;  // about this many work items per E step
+  int cap_items;     // upper bound on the work items (grid of the pair kernel)
+  // LDS and MFMA back ends (target chunks)
+  int nsplit;        // target chunks
+  int64_t mchunk;    // targets per chunk
+  int nsrc_blocks;   // source blocks of the accumulation kernel
+  int nfin_blocks;   // blocks of the finalisation kernel
 };
-EstepPlan estep_plan(int64_t N, int64_t M, int backend, int srcs_per_lane, int parts);
+
+// Written on the device by each E step of the scalar back end.
+struct CullHdr {
+  int items;           // work items of the pair kernel
+  int tiles_per_item;
+};
+
+EstepPlan estep_plan(int64_t N, int64_t M, int backend, int cull, int target_items);
 size_t estep_partial_bytes(const EstepPlan &pl, int64_t N);
 
+// Device workspace of the work-item plan, and the counter of evaluated pairs
+// inside it (scalar back end; null otherwise).
+size_t estep_plan_bytes(const EstepPlan &pl);
+unsigned long long *estep_plan_counter(const EstepPlan &pl, void *plan_ws);
+
 hipError_t launch_estep(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
-                        int64_t M, const DevState *s, double *partial, hipStream_t st);
+                        const TPt *pts, const TBox *boxes, int64_t M, DevState *s,
+                        void *plan_ws, double *partial, hipStream_t st);
 hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const float *w,
-                           const DevState *s, const double *partial, double *blockstats,
-                           double *colS, double *colstats, hipStream_t st);
+                           const DevState *s, const void *plan_ws, const double *partial,
+                           double *blockstats, double *colS, double *colstats, hipStream_t st);
 hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, const float *w,
                          const DevState *s, const double *colS, float *P, hipStream_t st);
 
 // Reduce the block statistics and run the M step.  mode 0: derive only
 // (gradient, Hessian, next pose into the *_next fields); mode 1: EM update of
 // the state (pose, sigma2, iteration, convergence).
+// evcount (may be null): pairs the pair kernel evaluated, added to
+// s->evaluated_pairs.
 hipError_t launch_reduce_mstep(double *blockstats, int nblk, int64_t N, DevState *s,
-                               double *nll_trace, int mode, hipStream_t st);
+                               double *nll_trace, const unsigned long long *evcount, int mode,
+                               hipStream_t st);
 
 }  // namespace lsg

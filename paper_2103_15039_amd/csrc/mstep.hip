@@ -144,8 +144,11 @@ __device__ double block_quad(MSh &m, const double *v, double *rowbuf) {
 
 __global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ blockstats, int nblk,
                                                     int N, DevState *__restrict__ s,
-                                                    double *__restrict__ trace, int mode) {
+                                                    double *__restrict__ trace,
+                                                    const unsigned long long *__restrict__ evcount,
+                                                    int mode) {
   if (s->done) return;
+  if (evcount && threadIdx.x == 0) s->evaluated_pairs += (int64_t)*evcount;
   // block statistics are stat-major (row i holds the nblk partials of
   // statistic i); thread (i, h) sums half h of row i with four independent
   // running sums, and the halves are added in a fixed order, so the result is
@@ -403,9 +406,10 @@ __global__ void init_state(DevState *__restrict__ s, const double *__restrict__ 
 }  // namespace
 
 hipError_t launch_reduce_mstep(double *blockstats, int nblk, int64_t N, DevState *s,
-                               double *nll_trace, int mode, hipStream_t st) {
+                               double *nll_trace, const unsigned long long *evcount, int mode,
+                               hipStream_t st) {
   hipLaunchKernelGGL(reduce_mstep, dim3(1), dim3(256), 0, st, blockstats, nblk, (int)N, s,
-                     nll_trace, mode);
+                     nll_trace, evcount, mode);
   return hipGetLastError();
 }
 

@@ -1,0 +1,92 @@
+// Spatial ordering of the source cloud for the E step.
+//
+// The pair kernel gives each wave 256 consecutive sources and walks the
+// targets in tiles of 64 records.  When a wave's sources and a tile's targets
+// are each close together in space, the bounding boxes prove that every
+// exponential between them is an exact zero and the wave skips the tile (see
+// estep.hip).  Sorting both clouds by a 30-bit Morton code of their position
+// (10 bits per axis inside the cloud's bounding box) makes consecutive points
+// spatial neighbours.  The sort is rocPRIM's stable radix sort, so the order
+// is deterministic.  Every E-step sum runs over all sources and all targets,
+// so the order changes only the rounding of the sums.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "lsgcpd_internal.h"
+
+namespace lsg {
+
+namespace {
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// box[4..6] = min, box[7..9] = max (moments layout)
+__global__ void morton_codes(const float *__restrict__ P, int n, const double *__restrict__ box,
+                             uint32_t *__restrict__ code, uint32_t *__restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double lo = box[4 + a], hi = box[7 + a];
+    const double u = hi > lo ? ((double)P[3 * i + a] - lo) / (hi - lo) : 0.0;
+    double q = u * 1023.0;
+    q = q < 0.0 ? 0.0 : (q > 1023.0 ? 1023.0 : q);  // also maps NaN to 0
+    c |= spread10((uint32_t)q) << a;
+  }
+  code[i] = c;
+  idx[i] = (uint32_t)i;
+}
+
+__global__ void gather3(const float *__restrict__ P, int n, const uint32_t *__restrict__ idx,
+                        float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t j = idx[i];
+  out[3 * i] = P[3 * j];
+  out[3 * i + 1] = P[3 * j + 1];
+  out[3 * i + 2] = P[3 * j + 2];
+}
+
+}  // namespace
+
+size_t morton_workspace_bytes(int64_t n) {
+  size_t tmp = 0;
+  uint32_t *nul = nullptr;
+  if (rocprim::radix_sort_pairs(nullptr, tmp, nul, nul, nul, nul, (unsigned)n, 0, 30) !=
+      hipSuccess)
+    tmp = 0;
+  // codes in/out + indices in/out + sort scratch
+  return 4 * (size_t)n * sizeof(uint32_t) + tmp + 256;
+}
+
+hipError_t launch_morton_order(const float *P, int64_t n, const double *box, void *work,
+                               size_t work_bytes, float *out, uint32_t *perm, hipStream_t st) {
+  uint32_t *code_in = (uint32_t *)work;
+  uint32_t *code_out = code_in + n;
+  uint32_t *idx_in = code_out + n;
+  uint32_t *idx_out = idx_in + n;
+  void *tmp = (void *)(idx_out + n);
+  size_t tmp_bytes = work_bytes - 4 * (size_t)n * sizeof(uint32_t);
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(morton_codes, dim3(blocks), dim3(256), 0, st, P, (int)n, box, code_in,
+                     idx_in);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, code_in, code_out, idx_in, idx_out, (unsigned)n,
+                                0, 30, st);
+  if (e != hipSuccess) return e;
+  if (out) hipLaunchKernelGGL(gather3, dim3(blocks), dim3(256), 0, st, P, (int)n, idx_out, out);
+  if (perm) {
+    e = hipMemcpyAsync(perm, idx_out, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lsg

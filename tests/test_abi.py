@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
                          text=True).stdout
     exported = set(re.findall(r" T (lsgcpd_\w+)", out))
     assert exported == set(names)
-    assert lib.lsgcpd_abi_version() == 1
+    assert lib.lsgcpd_abi_version() == 2
     assert lib.lsgcpd_status_string(3) == b"LSGCPD_E_NOMEM"
 
 
@@ -43,10 +43,11 @@ def test_header_compiles_and_layout_matches(cc, ext):
 #include <stdio.h>
 #include "lsgcpd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lsgcpd_pose), sizeof(lsgcpd_estep_out),
-         offsetof(lsgcpd_estep_out, stats), offsetof(lsgcpd_estep_out, newton_iters),
-         sizeof(lsgcpd_params), offsetof(lsgcpd_params, tol), sizeof(lsgcpd_report),
-         offsetof(lsgcpd_report, sigma2));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lsgcpd_pose),
+         sizeof(lsgcpd_estep_out), offsetof(lsgcpd_estep_out, stats),
+         offsetof(lsgcpd_estep_out, newton_iters), sizeof(lsgcpd_params),
+         offsetof(lsgcpd_params, tol), sizeof(lsgcpd_report), offsetof(lsgcpd_report, sigma2),
+         sizeof(lsgcpd_profile), offsetof(lsgcpd_profile, evaluated_pairs));
   return 0;
 }
 '''
@@ -59,7 +60,8 @@ int main(void) {
         got = list(map(int, subprocess.run([exe], capture_output=True, text=True).stdout.split()))
     want = [C.sizeof(L.Pose), C.sizeof(L.EstepOut), L.EstepOut.stats.offset,
             L.EstepOut.newton_iters.offset, C.sizeof(L.Params), L.Params.tol.offset,
-            C.sizeof(L.Report), L.Report.sigma2.offset]
+            C.sizeof(L.Report), L.Report.sigma2.offset, C.sizeof(L.Profile),
+            L.Profile.evaluated_pairs.offset]
     assert got == want
 
 

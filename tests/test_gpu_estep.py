@@ -171,6 +171,47 @@ def test_estep_deterministic():
     assert torch.equal(a.colstats, b.colstats)
 
 
+@pytest.mark.parametrize("s2", [1e-4, 2e-3, 0.5])
+@pytest.mark.parametrize("spatial", [False, True])
+def test_estep_culling_matches_dense(s2, spatial):
+    """Dropping (source group, target tile) blocks whose exponentials are all
+    exact zeros changes only the order of the sums.
+
+    With ``spatial`` both clouds are first sorted along x on the host, so that
+    groups and tiles are compact and culling removes most blocks at small
+    sigma^2 (the cut-off distance is about 15 sigma)."""
+    X32, Y32, n32, a32, p = _inputs(3000, 4100, seed=41)
+    if spatial:
+        ox, oy = np.argsort(X32[:, 0], kind="stable"), np.argsort(Y32[:, 0], kind="stable")
+        X32, Y32, n32, a32 = X32[ox], Y32[oy], n32[oy], a32[oy]
+    R, t = _near_pose(p, 6)
+    args = (dev(X32), dev(Y32), dev(n32), dev(a32), R, t, s2)
+    L.profile_enable(True)
+    try:
+        L.profile_read(reset=True)
+        a = L.estep(*args, colstats=True)
+        pa = L.profile_read(reset=True)
+        a2 = L.estep(*args, colstats=True)
+        L.profile_read(reset=True)
+        b = L.estep(*args, colstats=True, backend="dense")
+        pb = L.profile_read(reset=True)
+    finally:
+        L.profile_enable(False)
+    MN = len(X32) * len(Y32)
+    assert pb["evaluated_pairs"] == pb["pairs"] == MN
+    assert 0 < pa["evaluated_pairs"] <= MN
+    if spatial and s2 <= 1e-4:  # cut-off radius ~15 sigma = 0.15 on a ~1 m cloud
+        assert pa["evaluated_pairs"] < MN // 2
+    # culling is deterministic
+    assert np.array_equal(a.stats, a2.stats) and torch.equal(a.colstats, a2.colstats)
+    ca, cb = a.colstats.cpu().numpy(), b.colstats.cpu().numpy()
+    scale = np.abs(cb).max(axis=0, keepdims=True)
+    assert np.all(np.abs(ca - cb) <= 1e-12 * (np.abs(cb) + scale))
+    np.testing.assert_allclose(a.stats, b.stats, rtol=1e-11, atol=1e-13 * np.abs(b.stats).max())
+    assert np.abs(a.R_next - b.R_next).max() < 1e-10
+    np.testing.assert_allclose(a.sigma2_next, b.sigma2_next, rtol=1e-11)
+
+
 def test_estep_invalid_arguments():
     X32, Y32, n32, a32, p = _inputs(20, 20, seed=1, oracle_normals=False)
     args = (dev(X32), dev(Y32), dev(n32), dev(a32))

@@ -89,6 +89,11 @@ def test_register_tol_stop_and_backends():
     g = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7)
     o = O.register(p.X, p.Y, k=10, max_iter=60, tol=1e-7)
     assert g.converged and g.iters == o.iters < 60
+    # dense keeps the caller's source order; the default sorts sources
+    # spatially, which changes only the rounding of the sums
+    d = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7, backend="dense")
+    assert d.iters == g.iters and O.rotation_error_deg(d.R, g.R) < 1e-7
+    np.testing.assert_allclose(d.nll, g.nll, rtol=1e-12)
     for backend in ("lds", "mfma"):
         v = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7, backend=backend)
         assert v.iters == g.iters
