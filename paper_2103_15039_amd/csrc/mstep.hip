@@ -9,10 +9,13 @@
 // group: G <- G exp(xi^), xi = -Hs^{-1} grad, where grad and the symmetrised
 // Hessian Hs are the right derivatives of Eq. 11-12 (divided, as printed, by
 // sigma^2).  If Hs is not positive definite the Gauss-Newton part is used;
-// steps are halved until D does not grow beyond a rounding allowance.  After
+// steps are halved until D does not grow beyond a rounding allowance (the
+// change of D is evaluated as the exact difference of the quadratic).  After
 // the pose, sigma^2 = D(G_new) / (3 N_P) (Sec. 3.5, last paragraph).
-// The block's threads share the 12 x 12 products; thread 0 does the 6 x 6
-// Cholesky solve and the exponential map.
+// reduce_stats sums the block statistics with one block per statistic;
+// reduce_mstep runs the Newton iteration in one block, whose threads share
+// the 12 x 12 products while thread 0 does the 6 x 6 Cholesky solve and the
+// exponential map.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -142,39 +145,48 @@ __device__ double block_quad(MSh &m, const double *v, double *rowbuf) {
   return tot;
 }
 
-__global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ blockstats, int nblk,
-                                                    int N, DevState *__restrict__ s,
+// Sum of row i of the stat-major block statistics (one block per statistic,
+// so that the reads are spread over many CUs): thread t adds the partials
+// t, t + 256, ... in order, then a fixed tree adds the threads.  The result
+// does not depend on timing.
+__global__ __launch_bounds__(256) void reduce_stats(const double *__restrict__ blockstats,
+                                                     int nblk, DevState *__restrict__ s) {
+  if (s->done) return;
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const double *row = blockstats + (size_t)i * nblk;
+  double a = 0.0;
+  for (int c0 = 0; c0 < nblk; c0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int b = c0 + k * 256 + tid;
+      v[k] = b < nblk ? row[b] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a += v[k];
+  }
+  __shared__ double r[256];
+  r[tid] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) r[tid] += r[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) s->stats[i] = r[0];
+}
+
+// The M step from the 86 statistics in s->stats.
+__global__ __launch_bounds__(256) void reduce_mstep(int N, DevState *__restrict__ s,
                                                     double *__restrict__ trace,
                                                     const unsigned long long *__restrict__ evcount,
                                                     int mode) {
   if (s->done) return;
   if (evcount && threadIdx.x == 0) s->evaluated_pairs += (int64_t)*evcount;
-  // block statistics are stat-major (row i holds the nblk partials of
-  // statistic i); thread (i, h) sums half h of row i with four independent
-  // running sums, and the halves are added in a fixed order, so the result is
-  // reproducible bit for bit
   __shared__ double S[kStats];
-  __shared__ double half[2][kStats];
   __shared__ MSh m;
   __shared__ double rowbuf[12];
   const int tid = threadIdx.x;
-  if (tid < 2 * kStats) {
-    const int i = tid >> 1, h = tid & 1;
-    const double *row = blockstats + (size_t)i * nblk;
-    const int b0 = h ? nblk / 2 : 0, b1 = h ? nblk : nblk / 2;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = b0;
-    for (; b + 4 <= b1; b += 4) {
-      a0 += row[b];
-      a1 += row[b + 1];
-      a2 += row[b + 2];
-      a3 += row[b + 3];
-    }
-    for (; b < b1; ++b) a0 += row[b];
-    half[h][i] = (a0 + a1) + (a2 + a3);
-  }
-  __syncthreads();
-  if (tid < kStats) S[tid] = half[0][tid] + half[1][tid];
+  if (tid < kStats) S[tid] = s->stats[tid];
   __syncthreads();
   // the quadratic and the pose
   for (int e = tid; e < 144; e += blockDim.x) {
@@ -198,7 +210,6 @@ __global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ b
   const double nll = -(S[85] + S[83] - 1.5 * (double)N * log(kTwoPi * sigma2));
   double cur = block_quad(m, m.g, rowbuf);
   if (tid == 0) {
-    for (int i = 0; i < kStats; ++i) s->stats[i] = S[i];
     s->gamma = pow(kTwoPi * sigma2, 1.5) / s->V;
     s->nll = nll;
     s->pd = cur;
@@ -316,7 +327,10 @@ __global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ b
     }
     __syncthreads();
     if (m.go != 1) break;
-    // halve the step until D does not grow beyond a rounding allowance
+    // halve the step until D does not grow beyond a rounding allowance.  The
+    // change of D is computed as  dD = d^T (2 (H g - b) + H d),  d = g' - g,
+    // which is exact for the quadratic and free of the cancellation between
+    // the large terms of D itself
     for (int h = 0; h < 31; ++h) {
       if (tid == 0) {
         double xs[6];
@@ -324,11 +338,21 @@ __global__ __launch_bounds__(256) void reduce_mstep(const double *__restrict__ b
         compose(m.g, xs, m.gn);
       }
       __syncthreads();
-      const double val = block_quad(m, m.gn, rowbuf);
+      if (tid < 12) {
+        double hd = 0.0;
+        for (int k = 0; k < 12; ++k) hd = fma(m.H[tid][k], m.gn[k] - m.g[k], hd);
+        rowbuf[tid] = (m.gn[tid] - m.g[tid]) * (2.0 * (m.Hg[tid] - m.b[tid]) + hd);
+      }
+      __syncthreads();
       if (tid == 0) {
-        m.val = val;
-        if (val <= m.cur + 1e-12 * fabs(m.cur)) m.accept = 1;
-        else m.step *= 0.5;
+        double dD = 0.0;
+        for (int r = 0; r < 12; ++r) dD += rowbuf[r];
+        if (dD <= 1e-12 * fabs(m.cur)) {
+          m.accept = 1;
+          m.val = m.cur + dD;
+        } else {
+          m.step *= 0.5;
+        }
       }
       __syncthreads();
       if (m.accept) break;
@@ -408,8 +432,9 @@ __global__ void init_state(DevState *__restrict__ s, const double *__restrict__ 
 hipError_t launch_reduce_mstep(double *blockstats, int nblk, int64_t N, DevState *s,
                                double *nll_trace, const unsigned long long *evcount, int mode,
                                hipStream_t st) {
-  hipLaunchKernelGGL(reduce_mstep, dim3(1), dim3(256), 0, st, blockstats, nblk, (int)N, s,
-                     nll_trace, evcount, mode);
+  hipLaunchKernelGGL(reduce_stats, dim3(kStats), dim3(256), 0, st, blockstats, nblk, s);
+  hipLaunchKernelGGL(reduce_mstep, dim3(1), dim3(256), 0, st, (int)N, s, nll_trace, evcount,
+                     mode);
   return hipGetLastError();
 }
 
