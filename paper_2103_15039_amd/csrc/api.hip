@@ -31,7 +31,7 @@ struct lsgcpd_ctx {
   int device = 0;
   std::string err;
   Buf knn, rec, pts, boxes, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
-      trace, order, xperm, yperm;
+      trace, order, xperm, yperm, ys4;
   DevState *dstate = nullptr;  // device
   DevState *hstate = nullptr;  // pinned host staging
   // E-step timing: 3 events per E step (start, after pair kernel, end)
@@ -178,6 +178,30 @@ lsgcpd_status setup(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
   return LSGCPD_OK;
 }
 
+// Y in Morton order: ctx->ys4 (x, y, z, original index) and ctx->yperm.
+lsgcpd_status sort_targets(lsgcpd_ctx *ctx, const float *Y, int64_t M, hipStream_t st) {
+  const int nb = lsg::moments_blocks(M);
+  ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
+  ENSURE(mom, 48 * sizeof(double));
+  ENSURE(order, lsg::morton_workspace_bytes(M));
+  ENSURE(yperm, (size_t)M * sizeof(uint32_t));
+  ENSURE(ys4, (size_t)M * sizeof(float4));
+  double *box = (double *)ctx->mom.p + 32;
+  HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, nb, box, st));
+  HIPCHK(lsg::launch_morton_order(Y, M, box, ctx->order.p, ctx->order.cap, nullptr,
+                                  (float4 *)ctx->ys4.p, (uint32_t *)ctx->yperm.p, st));
+  return LSGCPD_OK;
+}
+
+lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int k, double alpha_max,
+                             double lambda, float *normals, float *kappa, float *alpha,
+                             hipStream_t st) {
+  ENSURE(knn, lsg::knn_workspace_bytes(M, k));
+  HIPCHK(lsg::launch_normals(Y, M, (const float4 *)ctx->ys4.p, (const uint32_t *)ctx->yperm.p, k,
+                             alpha_max, lambda, normals, kappa, alpha, ctx->knn.p, st));
+  return LSGCPD_OK;
+}
+
 // Makes room for `steps` more timed E steps (no-op unless profiling).
 lsgcpd_status prof_reserve(lsgcpd_ctx *ctx, int steps) {
   if (!ctx->prof) return LSGCPD_OK;
@@ -292,7 +316,7 @@ LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   (void)hipSetDevice(c->device);
   Buf *bufs[] = {&c->knn,  &c->rec,      &c->pts, &c->boxes, &c->plan,  &c->partial,
                  &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm, &c->kap,
-                 &c->alp,  &c->trace,    &c->order, &c->xperm, &c->yperm};
+                 &c->alp,  &c->trace,    &c->order, &c->xperm, &c->yperm, &c->ys4};
   for (Buf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
@@ -329,11 +353,9 @@ LSG_API lsgcpd_status lsgcpd_normals(lsgcpd_ctx *ctx, const float *Y, int64_t M,
     return fail(ctx, LSGCPD_E_INVALID, "alpha_max must be finite and >= 0");
   if (!finite_pos(lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
   RETURN_IF(set_device(ctx));
-  const int ns = lsg::knn_choose_splits(M);
-  ENSURE(knn, lsg::knn_workspace_bytes(M, ns));
-  HIPCHK(lsg::launch_normals(Y, M, k, alpha_max, lambda, normals, kappa, alpha, ctx->knn.p, ns,
-                             (hipStream_t)stream));
-  return LSGCPD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  RETURN_IF(sort_targets(ctx, Y, M, st));
+  return normals_sorted(ctx, Y, M, k, alpha_max, lambda, normals, kappa, alpha, st);
 }
 
 LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
@@ -420,41 +442,33 @@ LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
 
-  // target geometry
+  // target geometry: neighbours over Y in Morton order (the sort workspace is
+  // sized for both clouds up front, so it is not reallocated while in use)
+  ENSURE(order, lsg::morton_workspace_bytes(N > M ? N : M));
+  ENSURE(mom_part, (size_t)lsg::moments_blocks(N > M ? N : M) * 10 * sizeof(double));
   ENSURE(nrm, (size_t)M * 3 * sizeof(float));
   ENSURE(kap, (size_t)M * sizeof(float));
   ENSURE(alp, (size_t)M * sizeof(float));
-  const int ns = lsg::knn_choose_splits(M);
-  ENSURE(knn, lsg::knn_workspace_bytes(M, ns));
-  HIPCHK(lsg::launch_normals(Y, M, p->k, p->alpha_max, p->lambda, (float *)ctx->nrm.p,
-                             (float *)ctx->kap.p, (float *)ctx->alp.p, ctx->knn.p, ns, st));
+  RETURN_IF(sort_targets(ctx, Y, M, st));
+  RETURN_IF(normals_sorted(ctx, Y, M, p->k, p->alpha_max, p->lambda, (float *)ctx->nrm.p,
+                           (float *)ctx->kap.p, (float *)ctx->alp.p, st));
 
   const lsg::EstepPlan pl =
       lsg::estep_plan(N, M, backend_of(p->flags), (p->flags & LSGCPD_DENSE) ? 0 : 1, work_items());
   RETURN_IF(ensure_estep(ctx, pl, N));
-  // With tile culling both clouds are put in spatial (Morton) order once, so
-  // that a wave's sources and a tile's targets are neighbours.  Every
-  // statistic is a sum over all sources and all targets, so the order changes
-  // only the rounding of the sums.
+  // With culling the target records follow the Morton order of Y and the
+  // sources are put in Morton order too, so that a source group's and a target
+  // tile's points are neighbours.  Every statistic is a sum over all sources
+  // and all targets, so the order changes only the rounding of the sums.
   const uint32_t *yperm = nullptr;
   if (pl.backend == lsg::kBackendScalar && pl.cull && N > 256) {
-    const int nb = lsg::moments_blocks(N > M ? N : M);
-    ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
-    ENSURE(mom, 48 * sizeof(double));
-    const size_t wb = lsg::morton_workspace_bytes(N > M ? N : M);
-    ENSURE(order, wb);
     ENSURE(xperm, (size_t)N * 3 * sizeof(float));
-    ENSURE(yperm, (size_t)M * sizeof(uint32_t));
     double *xbox = (double *)ctx->mom.p + 32;
     HIPCHK(lsg::launch_moments(X, N, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(N),
                                xbox, st));
     HIPCHK(lsg::launch_morton_order(X, N, xbox, ctx->order.p, ctx->order.cap,
-                                    (float *)ctx->xperm.p, nullptr, st));
+                                    (float *)ctx->xperm.p, nullptr, nullptr, st));
     X = (const float *)ctx->xperm.p;
-    HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(M),
-                               xbox, st));
-    HIPCHK(lsg::launch_morton_order(Y, M, xbox, ctx->order.p, ctx->order.cap, nullptr,
-                                    (uint32_t *)ctx->yperm.p, st));
     yperm = (const uint32_t *)ctx->yperm.p;
   }
   ENSURE(trace, (size_t)(p->max_iter > 0 ? p->max_iter : 1) * sizeof(double));

@@ -1,22 +1,25 @@
-// Target geometry on the GPU (Sec. 3.1 and Eq. 3 of LSG-CPD): brute-force k
+// Target geometry on the GPU (Sec. 3.1 and Eq. 3 of LSG-CPD): exact k
 // nearest neighbours, FP64 3x3 PCA of each neighbourhood, surface variation
 // kappa and the penalty alpha.
 //
-// Pass 1 (knn_partial): the target range is split into `nsplit` chunks; block
-// (qb, split) streams its chunk through LDS in tiles and every thread keeps the
-// k best (distance, index) pairs of one query in registers.  Distances are
-// float32 ((dx*dx + dy*dy) + dz*dz), no contraction, so that the neighbour set
-// is decided exactly as the float32 definition says; pairs are ordered by the
-// 64-bit key (distance bits, index), i.e. by distance with ties to the lower
-// index.  Before the scan each query takes, as an upper bound tau0 of its k-th
-// distance, the k-th smallest distance to its 2k+1 index neighbours; only keys
-// <= (tau0, any index) can belong to the answer, so the list starts filled
-// with (tau0, +inf) sentinels.  On clouds stored in scan or image order (index
-// neighbours are spatial neighbours) this removes almost all list updates;
-// the result is exact for any order.
-// Pass 2 (knn_merge_pca): one thread per query merges the nsplit partial
-// lists, forms the neighbourhood covariance about its mean in FP64 and
-// diagonalises it by cyclic Jacobi rotations.
+// The caller puts the cloud in Morton order (order.hip) and passes the sorted
+// copy Ys (x, y, z, original index).  Pass 1 (knn_tiles): S waves per tile of
+// 64 sorted queries keep the k best (distance, original index) keys of each
+// query in registers.  Each scans the own tile and the two next to it first;
+// then every other tile whose box lies farther from the box of the wave's
+// queries than their largest current k-th distance is skipped, which cannot
+// change any answer (with a relative margin of 1e-5 for the float32 rounding
+// of the distances), and the S waves share the remaining tiles; knn_merge
+// combines their lists.  Isolated queries, whose k-th distance would widen
+// the search of the whole wave, are instead answered by pass 2 (knn_hard),
+// one wave per query over all points.
+// Distances are float32 ((dx*dx + dy*dy) + dz*dz), no contraction, so that
+// the neighbour set is decided exactly as the float32 definition says; keys
+// are ordered by (distance bits, original index), i.e. by distance with ties
+// to the lower index, so the result does not depend on the order of the scan.
+// Pass 3 (knn_pca): one thread per query forms the neighbourhood covariance
+// about its mean in FP64, diagonalises it by cyclic Jacobi rotations and
+// writes the results at the query's original index.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -26,8 +29,13 @@ namespace lsg {
 namespace {
 
 constexpr int kKnnBlock = 256;
-constexpr int kKnnTile = 256;
+constexpr int kKnnTileW = 64;  // sorted points per tile (one wave of queries)
 constexpr uint32_t kNoIndex = 0xffffffffu;
+
+struct TBoxF {
+  float lo[3], hi[3];
+  float pad[2];
+};
 
 __device__ __forceinline__ float dist2_f32(float ax, float ay, float az, float bx, float by,
                                            float bz) {
@@ -81,65 +89,299 @@ struct TopK {
   }
 };
 
-// tau0: k-th smallest distance from query q to its 2k+1 index neighbours.
-template <int KM>
-__device__ float index_window_bound(const float *__restrict__ Y, int M, int k, int q, float qx,
-                                    float qy, float qz) {
-  TopK<KM> t;
-  t.init(k, ~(uint64_t)0);
-  int lo = q - k, hi = q + k;
-  if (lo < 0) {
-    hi -= lo;
-    lo = 0;
+// Lower bound of the float32 squared distance between points of two boxes:
+// the gap per axis in FP64, shrunk by a relative 1e-5 (far above the rounding
+// of the float32 distance) and an absolute 1e-30 (float32 underflow).
+__device__ __forceinline__ double box_gap2(const TBoxF &a, const TBoxF &b) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double g = fmax(0.0, fmax((double)a.lo[i] - (double)b.hi[i],
+                                    (double)b.lo[i] - (double)a.hi[i]));
+    d2 = fma(g, g, d2);
   }
-  if (hi > M - 1) {
-    lo -= hi - (M - 1);
-    hi = M - 1;
-    if (lo < 0) lo = 0;
-  }
-  for (int j = lo; j <= hi; ++j)
-    t.offer(make_key(dist2_f32(qx, qy, qz, Y[3 * j], Y[3 * j + 1], Y[3 * j + 2]), (uint32_t)j));
-  return key_dist(t.worst);
+  return d2 * (1.0 - 1e-5) - 1e-30;
 }
 
+__device__ __forceinline__ float lanef(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+// Tile u as one vector load (lane j holds point j; zeros past the end).
+__device__ __forceinline__ float4 load_tile(const float4 *__restrict__ Ys, int M, int u) {
+  const int lane = threadIdx.x & 63;
+  const int j = u * kKnnTileW + lane;
+  return j < M ? Ys[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Offers the n points of a loaded tile to every lane's list, reading them back
+// with readlane.
 template <int KM>
-__global__ __launch_bounds__(kKnnBlock) void knn_partial(const float *__restrict__ Y, int M,
-                                                         int k, int chunk,
-                                                         uint64_t *__restrict__ out) {
+__device__ __forceinline__ void scan_loaded(const float4 &p, int n, float qx, float qy, float qz,
+                                            TopK<KM> &top) {
+  for (int j = 0; j < n; ++j) {
+    const float d = dist2_f32(qx, qy, qz, lanef(p.x, j), lanef(p.y, j), lanef(p.z, j));
+    // cheap float test first; the exact key order decides inside
+    if (d <= key_dist(top.worst))
+      top.offer(make_key(d, (uint32_t)__builtin_amdgcn_readlane(__float_as_int(p.w), j)));
+  }
+}
+
+__device__ __forceinline__ int tile_count(int M, int u) {
+  return M - u * kKnnTileW < kKnnTileW ? M - u * kKnnTileW : kKnnTileW;
+}
+
+// Pass 1, wave (query tile t, split s of S).  After the own tile and its two
+// Morton neighbours every query has a current k-th distance tau.  Queries
+// whose tau is far above the wave's 75th percentile (isolated points such as
+// outliers) are "hard": they are listed for pass 2 and left out of the
+// culling, so that they do not widen the search of the whole wave; if the
+// other queries would still need more than kLiveCap * S tiles, the queries
+// with the largest tau are moved to the hard list, 4 at a time.  Every other
+// tile is scanned unless its box lies farther from the box of the wave's easy
+// queries than their largest tau, which is exact for those queries.  The S
+// waves of a query tile take every S-th live tile and write S partial lists.
+constexpr int kLiveCap = 32;
+
+template <int KM>
+__global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict__ Ys, int M,
+                                                       int k, const TBoxF *__restrict__ boxes,
+                                                       int ntiles, int S,
+                                                       uint64_t *__restrict__ out,
+                                                       uint32_t *__restrict__ hard,
+                                                       unsigned int *__restrict__ nhard) {
+  const int lane = threadIdx.x & 63;
+  const int t =
+      __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kKnnBlock / 64) + (threadIdx.x >> 6)));
   const int split = blockIdx.y;
-  const int q = blockIdx.x * kKnnBlock + threadIdx.x;
-  const int j0 = split * chunk;
-  const int j1 = min(M, j0 + chunk);
+  if (t >= ntiles) return;  // wave-uniform
+  const int q = t * kKnnTileW + lane;
+  const bool valid = q < M;
   float qx = 0.f, qy = 0.f, qz = 0.f;
-  float tau = 0.f;
-  if (q < M) {
-    qx = Y[3 * q];
-    qy = Y[3 * q + 1];
-    qz = Y[3 * q + 2];
-    tau = index_window_bound<KM>(Y, M, k, q, qx, qy, qz);
+  if (valid) {
+    const float4 p = Ys[q];
+    qx = p.x;
+    qy = p.y;
+    qz = p.z;
   }
-  __shared__ float4 tile[kKnnTile];
   TopK<KM> top;
-  top.init(k, make_key(tau, kNoIndex));
-  for (int jt = j0; jt < j1; jt += kKnnTile) {
-    const int cnt = min(kKnnTile, j1 - jt);
-    if (threadIdx.x < cnt) {
-      const int j = jt + threadIdx.x;
-      tile[threadIdx.x] = make_float4(Y[3 * j], Y[3 * j + 1], Y[3 * j + 2], 0.f);
-    }
-    __syncthreads();
-    for (int jj = 0; jj < cnt; ++jj) {
-      const float4 p = tile[jj];
-      const float d = dist2_f32(qx, qy, qz, p.x, p.y, p.z);
-      // cheap float test first; the exact key order decides inside
-      if (d <= key_dist(top.worst)) top.offer(make_key(d, (uint32_t)(jt + jj)));
-    }
-    __syncthreads();
+  top.init(k, make_key(INFINITY, kNoIndex));
+  // own tile and its two neighbours in Morton order give the first bounds
+  {
+    const float4 p0 = load_tile(Ys, M, t);
+    const float4 pm = t > 0 ? load_tile(Ys, M, t - 1) : p0;
+    const float4 pp = t + 1 < ntiles ? load_tile(Ys, M, t + 1) : p0;
+    scan_loaded<KM>(p0, tile_count(M, t), qx, qy, qz, top);
+    if (t > 0) scan_loaded<KM>(pm, kKnnTileW, qx, qy, qz, top);
+    if (t + 1 < ntiles) scan_loaded<KM>(pp, tile_count(M, t + 1), qx, qy, qz, top);
   }
-  if (q < M) {
+  // rank of tau among the valid lanes (ties by lane), the 75th percentile
+  const float tau = key_dist(top.worst);
+  int rank = 0;
+  const int nvalid = tile_count(M, t);
+  for (int l = 0; l < nvalid; ++l) {
+    const float o = lanef(tau, l);
+    rank += (o < tau || (o == tau && l < lane)) ? 1 : 0;
+  }
+  const uint64_t at = __ballot(valid && rank == (3 * nvalid) / 4);
+  const float p75 = at ? lanef(tau, (int)__builtin_ctzll(at)) : INFINITY;
+  // the other S - 1 waves start again from sentinels at tau (no query's
+  // answer has a key above (tau, any index)), so that every candidate enters
+  // exactly one of the S lists
+  if (split != 0) top.init(k, make_key(tau, kNoIndex));
+  // easy lanes: rank < h
+  int h = __popcll(__ballot(valid && !(tau > 16.0f * p75)));
+  TBoxF own;
+  for (int rep = 0;; ++rep) {
+    const bool easy = valid && rank < h;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (easy) {
+      lo[0] = hi[0] = qx;
+      lo[1] = hi[1] = qy;
+      lo[2] = hi[2] = qz;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+        hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+      }
+    for (int a = 0; a < 3; ++a) {
+      own.lo[a] = lo[a];
+      own.hi[a] = hi[a];
+    }
+    if (rep == 8 || h <= nvalid / 2) break;
+    double r2 = easy ? (double)tau : -INFINITY;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
+    int live = 0;
+    for (int c0 = 0; c0 < ntiles; c0 += 64) {
+      const int u = c0 + lane;
+      live += __popcll(__ballot(u < ntiles && !(box_gap2(own, boxes[u]) > r2)));
+    }
+    if (live <= kLiveCap * S) break;
+    h -= 4;
+  }
+  const bool easy = valid && rank < h;
+  // scan: the live tiles other than the first three, every S-th to this wave.
+  // Which tiles are live, and so which wave owns which, is decided with the
+  // bound r20 after the first three tiles, which all S waves share; a wave
+  // also skips an owned tile beyond the largest current k-th distance of its
+  // own lists (those are never below the merged ones, so this is exact too).
+  double r20 = easy ? (double)tau : -INFINITY;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r20 = fmax(r20, __shfl_xor(r20, o, 64));
+  int ord = 0;
+  for (int c0 = 0; c0 < ntiles; c0 += 64) {
+    double r2 = easy ? (double)key_dist(top.worst) : -INFINITY;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
+    const int u = c0 + lane;
+    bool live = u < ntiles && (u < t - 1 || u > t + 1);
+    double gap = 0.0;
+    if (live) {
+      gap = box_gap2(own, boxes[u]);
+      live = !(gap > r20);
+    }
+    const uint64_t lm = __ballot(live);
+    const int mine = ord + __popcll(lm & ((1ull << lane) - 1ull));
+    uint64_t mk = __ballot(live && mine % S == split && !(gap > r2));
+    ord += __popcll(lm);
+    // walk the tiles, loading the next one while the current one is scanned
+    if (mk) {
+      int b = __builtin_ctzll(mk);
+      mk &= mk - 1;
+      float4 cur = load_tile(Ys, M, c0 + b);
+      for (;;) {
+        const int n = tile_count(M, c0 + b);
+        const bool more = mk != 0;
+        int bn = b;
+        float4 nxt = cur;
+        if (more) {
+          bn = __builtin_ctzll(mk);
+          mk &= mk - 1;
+          nxt = load_tile(Ys, M, c0 + bn);
+        }
+        scan_loaded<KM>(cur, n, qx, qy, qz, top);
+        if (!more) break;
+        cur = nxt;
+        b = bn;
+      }
+    }
+  }
+  if (valid) {
 #pragma unroll
     for (int j = 0; j < KM; ++j)
       if (j < k) out[((size_t)split * k + j) * M + q] = top.key[j];
+  }
+  if (split == 0 && valid && !easy) hard[atomicAdd(nhard, 1u)] = (uint32_t)q;
+}
+
+// Merge of the S partial lists of every query into list 0 (each list is
+// sorted, so a list is left at its first key that cannot enter; the
+// sentinels of lists 1..S-1 never can, since list 0 holds k real keys that
+// are not above them).
+template <int KM>
+__global__ __launch_bounds__(256) void knn_merge(int M, int k, int S,
+                                                 uint64_t *__restrict__ keys) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M || S == 1) return;
+  TopK<KM> top;
+  top.init(k, ~(uint64_t)0);
+  for (int s = 0; s < S; ++s)
+    for (int j = 0; j < k; ++j) {
+      const uint64_t kk = keys[((size_t)s * k + j) * M + q];
+      if (!(kk < top.worst)) break;
+      top.insert(kk);
+    }
+#pragma unroll
+  for (int j = 0; j < KM; ++j)
+    if (j < k) keys[(size_t)j * M + q] = top.key[j];
+}
+
+// Pass 2: one wave per hard query; lane l keeps the k best of the points
+// l, l + 64, ... (loaded 8 at a time), then k rounds of a wave minimum merge
+// the 64 lists (keys are unique, so exactly one lane pops per round).  Hard
+// queries are taken in list order by a grid-stride loop that every wave
+// leaves.  Writes list 0.
+template <int KM>
+__global__ __launch_bounds__(kKnnBlock) void knn_hard(const float4 *__restrict__ Ys, int M,
+                                                      int k, const uint32_t *__restrict__ hard,
+                                                      const unsigned int *__restrict__ nhard,
+                                                      uint64_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int w0 = blockIdx.x * (kKnnBlock / 64) + (threadIdx.x >> 6);
+  const int nw = gridDim.x * (kKnnBlock / 64);
+  const int nh = (int)*nhard;
+  for (int h = w0; h < nh; h += nw) {
+    const int q = (int)hard[h];
+    const float4 qp = Ys[q];
+    TopK<KM> top;
+    top.init(k, make_key(INFINITY, kNoIndex));
+    for (int j0 = 0; j0 < M; j0 += 8 * 64) {
+      float4 p[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int j = j0 + i * 64 + lane;
+        p[i] = j < M ? Ys[j] : make_float4(NAN, NAN, NAN, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float d = dist2_f32(qp.x, qp.y, qp.z, p[i].x, p[i].y, p[i].z);
+        if (d <= key_dist(top.worst)) top.offer(make_key(d, __float_as_uint(p[i].w)));
+      }
+    }
+    for (int r = 0; r < k; ++r) {
+      uint64_t m = top.key[0];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t mh = (uint32_t)__shfl_xor((int)(uint32_t)(m >> 32), o, 64);
+        const uint32_t ml = (uint32_t)__shfl_xor((int)(uint32_t)m, o, 64);
+        const uint64_t v = ((uint64_t)mh << 32) | ml;
+        m = v < m ? v : m;
+      }
+      if (lane == 0) out[(size_t)r * M + q] = m;
+      if (top.key[0] == m) {  // pop the head
+#pragma unroll
+        for (int j = 0; j + 1 < KM; ++j) top.key[j] = top.key[j + 1];
+        top.key[KM - 1] = make_key(INFINITY, kNoIndex);
+      }
+    }
+  }
+}
+
+// Bounding box of every tile of kKnnTileW sorted points (one wave per tile).
+// Also clears the counter of hard queries.
+__global__ void knn_boxes(const float4 *__restrict__ Ys, int M, int ntiles,
+                          TBoxF *__restrict__ boxes, unsigned int *__restrict__ nhard) {
+  const int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t == 0 && lane == 0) *nhard = 0u;
+  if (t >= ntiles) return;  // wave-uniform
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const int q = t * kKnnTileW + lane;
+  if (q < M) {
+    const float4 p = Ys[q];
+    lo[0] = hi[0] = p.x;
+    lo[1] = hi[1] = p.y;
+    lo[2] = hi[2] = p.z;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+    }
+  if (lane == 0) {
+    TBoxF b;
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = lo[a];
+      b.hi[a] = hi[a];
+    }
+    b.pad[0] = b.pad[1] = 0.f;
+    boxes[t] = b;
   }
 }
 
@@ -183,29 +425,25 @@ __device__ void jacobi3(double a[3][3], double v[3][3]) {
   }
 }
 
+// Query q (sorted position) is target qorig[q] of the caller's order; keys
+// hold original indices into Y.
 template <int KM>
-__global__ __launch_bounds__(256) void knn_merge_pca(const float *__restrict__ Y, int M, int k,
-                                                     int nsplit,
-                                                     const uint64_t *__restrict__ keys,
-                                                     double alpha_max, double lambda,
-                                                     float *__restrict__ normals,
-                                                     float *__restrict__ kappa,
-                                                     float *__restrict__ alpha) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= M) return;
-  TopK<KM> top;
-  top.init(k, ~(uint64_t)0);
-  for (int s = 0; s < nsplit; ++s)
-    for (int j = 0; j < k; ++j) {
-      const uint64_t kk = keys[((size_t)s * k + j) * M + q];
-      if (key_index(kk) < (uint32_t)M) top.offer(kk);
-    }
+__global__ __launch_bounds__(256) void knn_pca(const float *__restrict__ Y, int M, int k,
+                                               const uint64_t *__restrict__ keys,
+                                               const uint32_t *__restrict__ qorig,
+                                               double alpha_max, double lambda,
+                                               float *__restrict__ normals,
+                                               float *__restrict__ kappa,
+                                               float *__restrict__ alpha) {
+  const int qs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qs >= M) return;
+  const int q = (int)qorig[qs];
   // every slot holds a valid index unless the inputs were not finite; such
   // slots fall back to the query point itself
   int idx[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j) {
-    const uint32_t i = key_index(top.key[j]);
+    const uint32_t i = j < k ? key_index(keys[(size_t)j * M + qs]) : kNoIndex;
     idx[j] = i < (uint32_t)M ? (int)i : q;
   }
   double mx = 0.0, my = 0.0, mz = 0.0;
@@ -272,33 +510,48 @@ __global__ __launch_bounds__(256) void knn_merge_pca(const float *__restrict__ Y
 
 }  // namespace
 
-int knn_choose_splits(int64_t M) {
-  const int64_t qb = (M + kKnnBlock - 1) / kKnnBlock;
-  int64_t ns = (1536 + qb - 1) / qb;
-  const int64_t cap = M / 512 > 1 ? M / 512 : 1;
-  if (ns > cap) ns = cap;
-  if (ns > 64) ns = 64;
-  if (ns < 1) ns = 1;
-  return (int)ns;
+// Target splits of pass 1: about 4096 waves in all, at most 256 / k lists.
+int knn_splits(int64_t M, int k) {
+  const int64_t ntiles = (M + kKnnTileW - 1) / kKnnTileW;
+  int64_t S = (4096 + ntiles - 1) / ntiles;
+  const int64_t cap = 256 / (k > 8 ? k : 8);
+  if (S > cap) S = cap;
+  if (S > 16) S = 16;
+  if (S < 1) S = 1;
+  return (int)S;
 }
 
-size_t knn_workspace_bytes(int64_t M, int nsplit) {
-  return (size_t)nsplit * 32 * (size_t)M * sizeof(uint64_t);
+// Workspace: keys[S][k][M], tile boxes, hard list[M], hard counter.
+size_t knn_workspace_bytes(int64_t M, int k) {
+  const size_t ntiles = (size_t)((M + kKnnTileW - 1) / kKnnTileW);
+  return (size_t)knn_splits(M, k) * k * (size_t)M * sizeof(uint64_t) + ntiles * sizeof(TBoxF) +
+         (size_t)M * sizeof(uint32_t) + 256;
 }
 
-hipError_t launch_normals(const float *Y, int64_t M, int k, double alpha_max, double lambda,
-                          float *normals, float *kappa, float *alpha, void *work, int nsplit,
-                          hipStream_t st) {
+hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uint32_t *perm,
+                          int k, double alpha_max, double lambda, float *normals, float *kappa,
+                          float *alpha, void *work, hipStream_t st) {
   const int Mi = (int)M;
-  const int chunk = (int)((M + nsplit - 1) / nsplit);
+  const int ntiles = (int)((M + kKnnTileW - 1) / kKnnTileW);
+  const int S = knn_splits(M, k);
   uint64_t *keys = (uint64_t *)work;
-  dim3 g1((unsigned)((M + kKnnBlock - 1) / kKnnBlock), (unsigned)nsplit);
-  dim3 g2((unsigned)((M + 255) / 256));
-#define LSG_KNN(KM_)                                                                         \
-  do {                                                                                       \
-    hipLaunchKernelGGL(knn_partial<KM_>, g1, dim3(kKnnBlock), 0, st, Y, Mi, k, chunk, keys); \
-    hipLaunchKernelGGL(knn_merge_pca<KM_>, g2, dim3(256), 0, st, Y, Mi, k, nsplit, keys,     \
-                       alpha_max, lambda, normals, kappa, alpha);                            \
+  TBoxF *boxes = (TBoxF *)(keys + (size_t)S * k * M);
+  uint32_t *hard = (uint32_t *)(boxes + ntiles);
+  unsigned int *nhard = (unsigned int *)(hard + M);
+  hipLaunchKernelGGL(knn_boxes, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, Ys, Mi,
+                     ntiles, boxes, nhard);
+  const dim3 g1((unsigned)((ntiles + kKnnBlock / 64 - 1) / (kKnnBlock / 64)), (unsigned)S);
+  const dim3 gh(512);
+  const dim3 g2((unsigned)((M + 255) / 256));
+#define LSG_KNN(KM_)                                                                            \
+  do {                                                                                          \
+    hipLaunchKernelGGL(knn_tiles<KM_>, g1, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles, S, \
+                       keys, hard, nhard);                                                      \
+    hipLaunchKernelGGL(knn_merge<KM_>, g2, dim3(256), 0, st, Mi, k, S, keys);                   \
+    hipLaunchKernelGGL(knn_hard<KM_>, gh, dim3(kKnnBlock), 0, st, Ys, Mi, k, hard, nhard,       \
+                       keys);                                                                   \
+    hipLaunchKernelGGL(knn_pca<KM_>, g2, dim3(256), 0, st, Y, Mi, k, keys, perm, alpha_max,     \
+                       lambda, normals, kappa, alpha);                                          \
   } while (0)
   if (k <= 8) LSG_KNN(8);
   else if (k <= 16) LSG_KNN(16);

@@ -77,12 +77,13 @@ struct DevState {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the hipError_t of the launch.
 
-// Normals: k nearest neighbours (split over target ranges) + PCA + alpha.
-size_t knn_workspace_bytes(int64_t M, int nsplit);
-int knn_choose_splits(int64_t M);
-hipError_t launch_normals(const float *Y, int64_t M, int k, double alpha_max, double lambda,
-                          float *normals, float *kappa, float *alpha, void *work, int nsplit,
-                          hipStream_t st);
+// Normals: k nearest neighbours over the Morton-sorted copy Ys (x, y, z,
+// original index bits; perm[i] = original index of Ys[i]) + PCA + alpha,
+// written in the original order of Y.
+size_t knn_workspace_bytes(int64_t M, int k);
+hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uint32_t *perm,
+                          int k, double alpha_max, double lambda, float *normals, float *kappa,
+                          float *alpha, void *work, hipStream_t st);
 
 // Bounding box and first/second moments of a cloud, optionally after the
 // state's pose: out[0..2]=sum x', out[3]=sum |x'|^2, out[4..6]=min, out[7..9]=max.
@@ -96,11 +97,13 @@ hipError_t launch_init_state(DevState *s, const double *ymom, const double *xmom
                              int64_t N, int v_auto, int s2_auto, hipStream_t st);
 
 // Points sorted by a Morton code of their position (box = moments of the
-// cloud): writes the permuted cloud to `out` and/or the permutation (sorted
-// position -> original index) to `perm`; either may be null.
+// cloud): writes the permuted cloud to out3 (x, y, z) and/or out4 (x, y, z,
+// original index bits), and the permutation (sorted position -> original
+// index) to perm; any of them may be null.
 size_t morton_workspace_bytes(int64_t n);
 hipError_t launch_morton_order(const float *P, int64_t n, const double *box, void *work,
-                               size_t work_bytes, float *out, uint32_t *perm, hipStream_t st);
+                               size_t work_bytes, float *out3, float4 *out4, uint32_t *perm,
+                               hipStream_t st);
 
 // Target records.
 // Record i describes target perm[i] (perm may be null); rec[M] is a sentinel

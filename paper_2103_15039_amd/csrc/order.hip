@@ -1,10 +1,12 @@
-// Spatial ordering of the source cloud for the E step.
+// Spatial ordering of the clouds for the E step and the neighbour search.
 //
-// The pair kernel gives each wave 256 consecutive sources and walks the
-// targets in tiles of 64 records.  When a wave's sources and a tile's targets
-// are each close together in space, the bounding boxes prove that every
-// exponential between them is an exact zero and the wave skips the tile (see
-// estep.hip).  Sorting both clouds by a 30-bit Morton code of their position
+// The pair kernel takes sources in groups of 256 consecutive points and
+// targets in tiles of 64 records, and the neighbour search takes queries and
+// candidates in tiles of 64 points.  When the points of a group or tile are
+// close together in space, bounding boxes prove that whole tiles cannot
+// contribute (exact-zero exponentials, or points beyond the current k-th
+// neighbour) and they are skipped.  Sorting by a 30-bit Morton code of the
+// position
 // (10 bits per axis inside the cloud's bounding box) makes consecutive points
 // spatial neighbours.  The sort is rocPRIM's stable radix sort, so the order
 // is deterministic.  Every E-step sum runs over all sources and all targets,
@@ -43,14 +45,19 @@ __global__ void morton_codes(const float *__restrict__ P, int n, const double *_
   idx[i] = (uint32_t)i;
 }
 
-__global__ void gather3(const float *__restrict__ P, int n, const uint32_t *__restrict__ idx,
-                        float *__restrict__ out) {
+// sorted copies: out3 (x, y, z) and/or out4 (x, y, z, original index bits)
+__global__ void gather_points(const float *__restrict__ P, int n, const uint32_t *__restrict__ idx,
+                              float *__restrict__ out3, float4 *__restrict__ out4) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t j = idx[i];
-  out[3 * i] = P[3 * j];
-  out[3 * i + 1] = P[3 * j + 1];
-  out[3 * i + 2] = P[3 * j + 2];
+  const float x = P[3 * j], y = P[3 * j + 1], z = P[3 * j + 2];
+  if (out3) {
+    out3[3 * i] = x;
+    out3[3 * i + 1] = y;
+    out3[3 * i + 2] = z;
+  }
+  if (out4) out4[i] = make_float4(x, y, z, __uint_as_float(j));
 }
 
 }  // namespace
@@ -66,7 +73,8 @@ size_t morton_workspace_bytes(int64_t n) {
 }
 
 hipError_t launch_morton_order(const float *P, int64_t n, const double *box, void *work,
-                               size_t work_bytes, float *out, uint32_t *perm, hipStream_t st) {
+                               size_t work_bytes, float *out3, float4 *out4, uint32_t *perm,
+                               hipStream_t st) {
   uint32_t *code_in = (uint32_t *)work;
   uint32_t *code_out = code_in + n;
   uint32_t *idx_in = code_out + n;
@@ -81,7 +89,9 @@ hipError_t launch_morton_order(const float *P, int64_t n, const double *box, voi
   e = rocprim::radix_sort_pairs(tmp, tmp_bytes, code_in, code_out, idx_in, idx_out, (unsigned)n,
                                 0, 30, st);
   if (e != hipSuccess) return e;
-  if (out) hipLaunchKernelGGL(gather3, dim3(blocks), dim3(256), 0, st, P, (int)n, idx_out, out);
+  if (out3 || out4)
+    hipLaunchKernelGGL(gather_points, dim3(blocks), dim3(256), 0, st, P, (int)n, idx_out, out3,
+                       out4);
   if (perm) {
     e = hipMemcpyAsync(perm, idx_out, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;

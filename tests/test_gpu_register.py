@@ -60,6 +60,17 @@ def test_normals_rgbd_sampled():
     _check_normals(p.Y, 20, q)
 
 
+@pytest.mark.parametrize("wl,k,nq", [("rgbd_20000x20000", 20, None), ("rgbd_20000x20000", 32, None),
+                                     ("lidar_100000x50000", 20, 20000)])
+def test_normals_full_size(wl, k, nq):
+    """Every query (or 20,000 sampled ones) of the benchmark clouds: the tiled
+    search with its target splits, hard queries (the RGB-D cloud has 5%
+    outliers) and merge must give exactly the brute-force neighbour sets."""
+    p = datagen.WORKLOADS[wl]()
+    q = None if nq is None else np.random.default_rng(1).choice(len(p.Y), size=nq, replace=False)
+    _check_normals(p.Y, k, q)
+
+
 def _reg_pair(p, k, max_iter, tol=0.0, exact=False):
     g = L.register(dev(p.X), dev(p.Y), k=k, max_iter=max_iter, tol=tol, exact=exact)
     o = O.register(p.X, p.Y, k=k, max_iter=max_iter, tol=tol, exact_normalizer=exact)
