@@ -10,12 +10,13 @@ Prints one JSON line:
   value       = E-step pair evaluations per second of the whole step
                 (M * N * 50 / wall time of the step, normals and M steps
                 included)
-  roofline    = the E-step pair stage (work-item plan + pair kernel), timed
-                live with HIP events on its stream inside the timed region,
-                credited with 38 FP32 flops per (target, source) pair it
-                evaluated (pairs in blocks proven to hold only exact-zero
-                exponentials are dropped and not credited), against the
-                157.3 TFLOP/s FP32 vector peak of MI355X
+  roofline    = the E-step pair kernel, timed live with HIP events on its
+                stream inside the timed region, credited with the 40 FP64
+                flops it executes per (target, source) pair it evaluates
+                (pairs proven to hold exact-zero exponentials are dropped and
+                not credited), against the 78.6 TFLOP/s FP64 vector peak of
+                MI355X; traffic = HBM bytes per launch from the committed
+                rocprofv3 counter summary of the same kernel source
   cpu_baseline= the FP64 C oracle (one full E step of the same pair) on the
                 host cores
 """
@@ -28,8 +29,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_PAIR = 38          # credited FP32 flops per (m, n) pair
-PEAK_FP32 = 157.3e12         # MI355X FP32 vector, FLOP/s
+FLOPS_PER_PAIR = 40          # FP64 flops per evaluated (m, n) pair
+PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
 EM_ITERS = 50
 
 
@@ -160,8 +161,8 @@ def main():
         "config": {"workload": a.workload, "M": M, "N": N, "em_iters": EM_ITERS,
                    "knn": knn, "alpha_max": 30.0, "lambda": 0.2, "w0": 0.1,
                    "pair_kernel": a.backend},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic},
         "estep": {"pair_kernel_ms": k_ms, "estep_ms": e_ms,
                   "evaluated_frac": evaluated / (M * N),
                   "pair_kernel_pair_evals_per_s": M * N / (k_ms * 1e-3),

@@ -206,9 +206,10 @@ lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const 
 
 /* Event-based timing of the E step inside lsgcpd_estep / lsgcpd_register.
  * While enabled, every E step records HIP events on the call's stream around
- * (a) the pair kernel (exponents + feature accumulation) and (b) the whole
- * E step (pair kernel + per-source finalisation + block reduction).  Elapsed
- * times are summed when the call synchronises.  Off by default. */
+ * (a) the pair kernel alone (exponents + feature accumulation) and (b) the
+ * whole E step (work-item plan, pair kernel, per-source finalisation and the
+ * block statistics; the M step is not included).  Elapsed times are summed
+ * when the call synchronises.  Off by default. */
 typedef struct {
   int64_t launches;        /* E steps timed                                 */
   int64_t pairs;           /* sum of M * N over those E steps               */

@@ -34,7 +34,8 @@ struct lsgcpd_ctx {
       trace, order, xperm, yperm, ys4;
   DevState *dstate = nullptr;  // device
   DevState *hstate = nullptr;  // pinned host staging
-  // E-step timing: 3 events per E step (start, after pair kernel, end)
+  // E-step timing: 4 events per E step (start, before and after the pair
+  // kernel, end)
   bool prof = false;
   std::vector<hipEvent_t> events;
   int ev_used = 0;
@@ -205,7 +206,7 @@ lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int k, 
 // Makes room for `steps` more timed E steps (no-op unless profiling).
 lsgcpd_status prof_reserve(lsgcpd_ctx *ctx, int steps) {
   if (!ctx->prof) return LSGCPD_OK;
-  const size_t need = (size_t)(ctx->ev_used + 3 * steps);
+  const size_t need = (size_t)(ctx->ev_used + 4 * steps);
   while (ctx->events.size() < need) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
@@ -225,10 +226,10 @@ lsgcpd_status prof_record(lsgcpd_ctx *ctx, hipStream_t st) {
 lsgcpd_status prof_collect(lsgcpd_ctx *ctx, int64_t evaluated) {
   if (!ctx->prof) return LSGCPD_OK;
   ctx->totals.evaluated_pairs += evaluated;
-  for (int i = 0; i + 3 <= ctx->ev_used; i += 3) {
+  for (int i = 0; i + 4 <= ctx->ev_used; i += 4) {
     float a = 0.f, b = 0.f;
-    HIPCHK(hipEventElapsedTime(&a, ctx->events[i], ctx->events[i + 1]));
-    HIPCHK(hipEventElapsedTime(&b, ctx->events[i], ctx->events[i + 2]));
+    HIPCHK(hipEventElapsedTime(&a, ctx->events[i + 1], ctx->events[i + 2]));
+    HIPCHK(hipEventElapsedTime(&b, ctx->events[i], ctx->events[i + 3]));
     ctx->totals.pair_kernel_ms += a;
     ctx->totals.estep_ms += b;
     ctx->totals.launches += 1;
@@ -245,9 +246,12 @@ lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::EstepPlan &pl, const float *
                         hipStream_t st) {
   lsgcpd_status s = prof_record(ctx, st);
   if (s != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep(pl, X, N, (const lsg::TRec *)ctx->rec.p,
-                           (const lsg::TPt *)ctx->pts.p, (const lsg::TBox *)ctx->boxes.p, M,
-                           ctx->dstate, ctx->plan.p, (double *)ctx->partial.p, st));
+  HIPCHK(lsg::launch_estep_plan(pl, X, N, (const lsg::TBox *)ctx->boxes.p, ctx->dstate,
+                                ctx->plan.p, st));
+  if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
+  HIPCHK(lsg::launch_estep_pairs(pl, X, N, (const lsg::TRec *)ctx->rec.p,
+                                 (const lsg::TPt *)ctx->pts.p, M, ctx->dstate, ctx->plan.p,
+                                 (double *)ctx->partial.p, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_finalize(pl, X, N, w, ctx->dstate, ctx->plan.p,
                               (const double *)ctx->partial.p, (double *)ctx->blockstats.p,

@@ -151,7 +151,7 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 // ------------------------------------------------------- pair kernel (VALU)
 // Scalar-cache back end with exact tile culling and balanced work items.
 //
-// Sources form groups of kGroup = 256 consecutive points (4 per lane of a
+// Sources form groups of kGroup = 128 consecutive points (2 per lane of a
 // wave); targets form tiles of kCullTile = 64 consecutive records.  Once per
 // E step
 //  * cull_groups (one block per group) takes the group's bounding box in
@@ -160,7 +160,7 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 //  * cull_items (one block) cuts every group's list into items of L tiles,
 //    with L chosen so that there are at most about `target` items in all, and
 //    writes the item -> group map;
-//  * estep_pairs_items runs one block per item: the 4 waves hold the same 256
+//  * estep_pairs_items runs one block per item: the 4 waves hold the same 128
 //    sources and take every 4th tile of the item.  Per tile, one lane per
 //    target tests the target against the group box, and the wave walks the
 //    set bits of the resulting 64-bit mask.  The 4 waves' sums are added
@@ -170,7 +170,10 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 // so the blocks carry about equal work whatever the culling removes.  All
 // counts are integers and every sum runs in a fixed order, so results are
 // bitwise reproducible.
-constexpr int kGroup = 256;
+// 2 sources per lane measured faster than 4 (tighter group boxes, twice the
+// groups to balance, more waves per SIMD) and than 1 on both benchmark pairs
+constexpr int kSrcPerLane = 2;
+constexpr int kGroup = 64 * kSrcPerLane;
 
 // Scaled-coordinate bounding box of each source group (kept for the pair
 // kernel), then the live tiles in increasing order.
@@ -188,9 +191,10 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const float *__restrict__ 
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
   const double sc = sqrt_c_of(st);
   const int n = g * kGroup + threadIdx.x;
-  const Src x = load_src(X, n, N, R, t, sc);
+  const bool mine = threadIdx.x < kGroup && n < N;
+  const Src x = load_src(X, mine ? n : N, N, R, t, sc);
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (n < N) {
+  if (mine) {
     lo[0] = hi[0] = x.x0;
     lo[1] = hi[1] = x.x1;
     lo[2] = hi[2] = x.x2;
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
     const int *__restrict__ off, const int *__restrict__ map, const int *__restrict__ list,
     const double *__restrict__ gbox, int ntiles, unsigned long long *__restrict__ evcount,
     double *__restrict__ partial) {
-  constexpr int S = 4;
+  constexpr int S = kSrcPerLane;
   if (st->done) return;
   const int item = blockIdx.x;
   if (item >= hdr->items) return;
@@ -528,51 +532,63 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kFinBlock = 64;
 
-// ITEMS: partials per work item ([item][feature][256], the items of source
-// group g are off[g] .. off[g+1]-1); otherwise per target chunk
-// ([chunk][feature][N]).
+// ITEMS: partials per work item ([item][feature][kGroup], the items of source
+// group g are off[g] .. off[g+1]-1), summed by 4 waves per block (wave p
+// takes items p, p + 4, ...; the 4 sums are added in a fixed order);
+// otherwise per target chunk ([chunk][feature][N]), one wave per block.
 template <bool ITEMS>
-__global__ __launch_bounds__(kFinBlock) void estep_finalize(
+__global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
     const float *__restrict__ X, int N, const float *__restrict__ w,
     const DevState *__restrict__ st, const double *__restrict__ partial, int nsplit,
     const int *__restrict__ off, double *__restrict__ blockstats, double *__restrict__ colS,
     double *__restrict__ colstats) {
   if (st->done) return;
-  const int n = blockIdx.x * kFinBlock + threadIdx.x;
+  const int l = threadIdx.x & (kFinBlock - 1);
+  const int part = threadIdx.x / kFinBlock;  // 0 without ITEMS
+  const int n = blockIdx.x * kFinBlock + l;
   double p = 0.0, W[6] = {0, 0, 0, 0, 0, 0}, B[3] = {0, 0, 0}, C = 0.0, lg = 0.0, outl = 0.0,
          logw = 0.0;
   double xt[4] = {0.0, 0.0, 0.0, 0.0};
-  if (n < N) {
-    double T[kFeatUsed];
+  double T[kFeatUsed];
 #pragma unroll
-    for (int c = 0; c < kFeatUsed; ++c) T[c] = 0.0;
-    if (ITEMS) {
-      // items in increasing order; the loads of 4 items are issued together
+  for (int c = 0; c < kFeatUsed; ++c) T[c] = 0.0;
+  if (ITEMS) {
+    if (n < N) {
+      // this wave's items in increasing order, the loads of 4 issued together
       const int g = n / kGroup, j = n % kGroup;
       const int i1 = off[g + 1];
-      int it = off[g];
-      for (; it + 4 <= i1; it += 4) {
+      int it = off[g] + part;
+      for (; it + 12 < i1; it += 16) {
         double v[4][kFeatUsed];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int c = 0; c < kFeatUsed; ++c)
-            v[u][c] = partial[((size_t)(it + u) * kFeatUsed + c) * kGroup + j];
+            v[u][c] = partial[((size_t)(it + 4 * u) * kFeatUsed + c) * kGroup + j];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int c = 0; c < kFeatUsed; ++c) T[c] += v[u][c];
       }
-      for (; it < i1; ++it)
+      for (; it < i1; it += 4)
 #pragma unroll
         for (int c = 0; c < kFeatUsed; ++c)
           T[c] += partial[((size_t)it * kFeatUsed + c) * kGroup + j];
-    } else {
-      for (int sp = 0; sp < nsplit; ++sp)
-#pragma unroll
-        for (int c = 0; c < kFeatUsed; ++c)
-          T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
     }
+    __shared__ double tr[3][kFeatUsed][kFinBlock];
+    if (part > 0)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) tr[part - 1][c][l] = T[c];
+    __syncthreads();
+    if (part == 0)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) T[c] = ((T[c] + tr[0][c][l]) + tr[1][c][l]) + tr[2][c][l];
+  } else if (n < N) {
+    for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
+  }
+  if (part == 0 && n < N) {
     const double wn = w ? (double)w[n] : st->w0;
     const double rho = (1.0 - wn) / wn;
     const double gam = gamma_of(st);
@@ -617,23 +633,24 @@ __global__ __launch_bounds__(kFinBlock) void estep_finalize(
   // statistic i of this source (layout documented with the public header),
   // written to LDS and summed over the block's sources in a fixed order
   __shared__ double red[kStats][kFinBlock + 1];
-  const int l = threadIdx.x;
+  if (part == 0) {
 #pragma unroll
-  for (int i = 0; i < 10; ++i) red[i][l] = p * xx[i];
+    for (int i = 0; i < 10; ++i) red[i][l] = p * xx[i];
 #pragma unroll
-  for (int ab = 0; ab < 6; ++ab)
+    for (int ab = 0; ab < 6; ++ab)
 #pragma unroll
-    for (int i = 0; i < 10; ++i) red[10 + 10 * ab + i][l] = W[ab] * xx[i];
+      for (int i = 0; i < 10; ++i) red[10 + 10 * ab + i][l] = W[ab] * xx[i];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[70 + 4 * a + j][l] = B[a] * xt[j];
-  red[82][l] = C;
-  red[83][l] = lg;
-  red[84][l] = outl;
-  red[85][l] = logw;
+      for (int j = 0; j < 4; ++j) red[70 + 4 * a + j][l] = B[a] * xt[j];
+    red[82][l] = C;
+    red[83][l] = lg;
+    red[84][l] = outl;
+    red[85][l] = logw;
+  }
   __syncthreads();
-  for (int i = l; i < kStats; i += kFinBlock) {
+  for (int i = threadIdx.x; i < kStats; i += blockDim.x) {
     double s = 0.0;
     for (int k = 0; k < kFinBlock; ++k) s += red[i][k];
     blockstats[(size_t)i * gridDim.x + blockIdx.x] = s;  // stat-major
@@ -719,7 +736,7 @@ __global__ void tile_boxes(const TPt *__restrict__ pts, int64_t M, TBox *__restr
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double lmax = -INFINITY;
   const int64_t m = t * kCullTile + lane;
-  if (m < M) {
+  if (lane < kCullTile && m < M) {
     for (int a = 0; a < 3; ++a) lo[a] = hi[a] = pts[m].y[a];
     lmax = pts[m].l;
   }
@@ -893,28 +910,35 @@ unsigned long long *estep_plan_counter(const EstepPlan &pl, void *plan_ws) {
   return pl.backend == kBackendScalar ? plan_ptrs(pl, plan_ws).evcount : nullptr;
 }
 
-hipError_t launch_estep(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
-                        const TPt *pts, const TBox *boxes, int64_t M, DevState *s,
-                        void *plan_ws, double *partial, hipStream_t st) {
+hipError_t launch_estep_plan(const EstepPlan &pl, const float *X, int64_t N, const TBox *boxes,
+                             DevState *s, void *plan_ws, hipStream_t st) {
+  if (pl.backend != kBackendScalar) return hipSuccess;
+  const PlanPtrs q = plan_ptrs(pl, plan_ws);
+  if (pl.cull) {
+    hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.ngroups), dim3(kBlock), 0, st, X, (int)N, s,
+                       boxes, pl.ntiles, q.counts, q.gbox, q.list);
+    hipLaunchKernelGGL(cull_items<true>, dim3(1), dim3(kBlock), 0, st, s, q.counts, pl.ngroups,
+                       pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off, q.map, q.evcount);
+  } else {
+    hipLaunchKernelGGL(cull_items<false>, dim3(1), dim3(kBlock), 0, st, s, q.counts, pl.ngroups,
+                       pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off, q.map, q.evcount);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_estep_pairs(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
+                              const TPt *pts, int64_t M, DevState *s, void *plan_ws,
+                              double *partial, hipStream_t st) {
   if (pl.backend == kBackendScalar) {
     const PlanPtrs q = plan_ptrs(pl, plan_ws);
-    if (pl.cull) {
-      hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.ngroups), dim3(kBlock), 0, st, X, (int)N,
-                         s, boxes, pl.ntiles, q.counts, q.gbox, q.list);
-      hipLaunchKernelGGL(cull_items<true>, dim3(1), dim3(kBlock), 0, st, s, q.counts,
-                         pl.ngroups, pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off,
-                         q.map, q.evcount);
+    if (pl.cull)
       hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.cap_items), dim3(kBlock), 0,
                          st, X, (int)N, rec, pts, M, s, q.hdr, q.counts, q.off, q.map, q.list,
                          q.gbox, pl.ntiles, q.evcount, partial);
-    } else {
-      hipLaunchKernelGGL(cull_items<false>, dim3(1), dim3(kBlock), 0, st, s, q.counts,
-                         pl.ngroups, pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off,
-                         q.map, q.evcount);
+    else
       hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.cap_items), dim3(kBlock), 0,
                          st, X, (int)N, rec, pts, M, s, q.hdr, q.counts, q.off, q.map, q.list,
                          q.gbox, pl.ntiles, q.evcount, partial);
-    }
     return hipGetLastError();
   }
   dim3 grid((unsigned)(pl.nsrc_blocks * pl.nsplit));
@@ -931,7 +955,7 @@ hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const
                            const DevState *s, const void *plan_ws, const double *partial,
                            double *blockstats, double *colS, double *colstats, hipStream_t st) {
   if (pl.backend == kBackendScalar)
-    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.nfin_blocks), dim3(kFinBlock), 0,
+    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.nfin_blocks), dim3(4 * kFinBlock), 0,
                        st, X, (int)N, w, s, partial, 0,
                        (const int *)plan_ptrs(pl, (void *)plan_ws).off, blockstats, colS,
                        colstats);

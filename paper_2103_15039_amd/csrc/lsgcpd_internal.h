@@ -150,9 +150,13 @@ size_t estep_partial_bytes(const EstepPlan &pl, int64_t N);
 size_t estep_plan_bytes(const EstepPlan &pl);
 unsigned long long *estep_plan_counter(const EstepPlan &pl, void *plan_ws);
 
-hipError_t launch_estep(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
-                        const TPt *pts, const TBox *boxes, int64_t M, DevState *s,
-                        void *plan_ws, double *partial, hipStream_t st);
+// The work-item plan of the scalar back end (no-op for the others), then the
+// pair kernel.
+hipError_t launch_estep_plan(const EstepPlan &pl, const float *X, int64_t N, const TBox *boxes,
+                             DevState *s, void *plan_ws, hipStream_t st);
+hipError_t launch_estep_pairs(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
+                              const TPt *pts, int64_t M, DevState *s, void *plan_ws,
+                              double *partial, hipStream_t st);
 hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const float *w,
                            const DevState *s, const void *plan_ws, const double *partial,
                            double *blockstats, double *colS, double *colstats, hipStream_t st);
