@@ -811,15 +811,32 @@ __global__ __launch_bounds__(256) void moments_partial(const float *__restrict__
   }
 }
 
-__global__ void moments_final(const double *__restrict__ part, int nblk, double *__restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= 10) return;
-  double a = part[k];
-  for (int b = 1; b < nblk; ++b) {
-    const double c = part[b * 10 + k];
-    a = k < 4 ? a + c : (k < 7 ? fmin(a, c) : fmax(a, c));
+// nblk <= 512 block partials: thread t combines partials t and t + 256, then a
+// fixed tree combines the threads (sums for 0-3, min for 4-6, max for 7-9).
+__global__ __launch_bounds__(256) void moments_final(const double *__restrict__ part, int nblk,
+                                                     double *__restrict__ out) {
+  const int t = threadIdx.x;
+  __shared__ double r[10][256];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    double a = k < 4 ? 0.0 : (k < 7 ? INFINITY : -INFINITY);
+    for (int b = t; b < nblk; b += 256) {
+      const double c = part[b * 10 + k];
+      a = k < 4 ? a + c : (k < 7 ? fmin(a, c) : fmax(a, c));
+    }
+    r[k][t] = a;
   }
-  out[k] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        const double a = r[k][t], c = r[k][t + o];
+        r[k][t] = k < 4 ? a + c : (k < 7 ? fmin(a, c) : fmax(a, c));
+      }
+    __syncthreads();
+  }
+  if (t < 10) out[t] = r[t][0];
 }
 
 }  // namespace
@@ -998,7 +1015,7 @@ hipError_t launch_moments(const float *P, int64_t n, const DevState *pose, doubl
                           int nblk, double *out, hipStream_t st) {
   hipLaunchKernelGGL(moments_partial, dim3((unsigned)nblk), dim3(256), 0, st, P, (int)n, pose,
                      partials);
-  hipLaunchKernelGGL(moments_final, dim3(1), dim3(64), 0, st, partials, nblk, out);
+  hipLaunchKernelGGL(moments_final, dim3(1), dim3(256), 0, st, partials, nblk, out);
   return hipGetLastError();
 }
 

@@ -289,12 +289,16 @@ __global__ __launch_bounds__(256) void knn_merge(int M, int k, int S,
   if (q >= M || S == 1) return;
   TopK<KM> top;
   top.init(k, ~(uint64_t)0);
-  for (int s = 0; s < S; ++s)
-    for (int j = 0; j < k; ++j) {
-      const uint64_t kk = keys[((size_t)s * k + j) * M + q];
-      if (!(kk < top.worst)) break;
-      top.insert(kk);
-    }
+  for (int s = 0; s < S; ++s) {
+    // the whole list at once (k loads in flight), then in order until a key
+    // cannot enter
+    uint64_t v[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) v[j] = j < k ? keys[((size_t)s * k + j) * M + q] : ~(uint64_t)0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < k && v[j] < top.worst) top.insert(v[j]);
+  }
 #pragma unroll
   for (int j = 0; j < KM; ++j)
     if (j < k) keys[(size_t)j * M + q] = top.key[j];
