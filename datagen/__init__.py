@@ -315,6 +315,91 @@ def plane_patch(rng, n, normal=(0.0, 0.0, 1.0), size=1.0, offset=0.0):
     return uv[:, :1] * a + uv[:, 1:] * b + offset * nrm
 
 
+# ---------------------------------------------------------------------------
+# Batches of small pairs of uneven sizes (box / sphere / plane-patch scenes)
+# ---------------------------------------------------------------------------
+
+def _primitive_scene(rng):
+    """1-3 primitives: (kind, parameters, area)."""
+    prims = []
+    for _ in range(int(rng.integers(1, 4))):
+        kind = int(rng.integers(0, 3))
+        c = rng.uniform(-0.3, 0.3, size=3)
+        if kind == 0:      # box: rotation, centre, half extents
+            h = rng.uniform(0.1, 0.35, size=3)
+            R = random_rotation(rng, rng.uniform(0, math.pi))
+            area = 8.0 * (h[0] * h[1] + h[1] * h[2] + h[0] * h[2])
+            prims.append(("box", (R, c, h), area))
+        elif kind == 1:    # sphere
+            r = rng.uniform(0.1, 0.35)
+            prims.append(("sphere", (c, r), 4.0 * math.pi * r * r))
+        else:              # square plane patch
+            size = rng.uniform(0.3, 0.8)
+            prims.append(("plane", (random_unit(rng), c, size), size * size))
+    return prims
+
+
+def _sample_scene(rng, prims, n):
+    areas = np.array([a for _, _, a in prims])
+    counts = rng.multinomial(n, areas / areas.sum())
+    parts = []
+    for (kind, par, _), k in zip(prims, counts):
+        if k == 0:
+            continue
+        if kind == "box":
+            R, c, h = par
+            # faces drawn in proportion to their area
+            fa = np.array([h[1] * h[2], h[1] * h[2], h[0] * h[2], h[0] * h[2],
+                           h[0] * h[1], h[0] * h[1]])
+            face = rng.choice(6, size=k, p=fa / fa.sum())
+            ax = face // 2
+            sign = np.where(face % 2 == 0, -1.0, 1.0)
+            P = rng.uniform(-1.0, 1.0, size=(k, 3)) * h
+            P[np.arange(k), ax] = sign * h[ax]
+            parts.append(P @ R.T + c)
+        elif kind == "sphere":
+            c, r = par
+            v = rng.normal(size=(k, 3))
+            parts.append(r * v / np.linalg.norm(v, axis=1, keepdims=True) + c)
+        else:
+            nrm, c, size = par
+            parts.append(plane_patch(rng, k, normal=nrm, size=size) + c)
+    P = np.vstack(parts)
+    return P[rng.permutation(len(P))]
+
+
+def scene_pair(rng, M, N, max_angle_deg=60.0, trans=0.1, noise=0.005, max_outliers=0.1,
+               name="scene"):
+    """Target: M points on a random primitive scene.  Source: an independent
+    N-point resample, rotated by U(0, max_angle) about a uniform axis,
+    translated by U(-trans, trans)^3, noise N(0, noise^2) per coordinate, then
+    a U(0, max_outliers) fraction replaced by uniform points in its box."""
+    prims = _primitive_scene(rng)
+    Y = _sample_scene(rng, prims, M)
+    S = _sample_scene(rng, prims, N)
+    Ra = random_rotation(rng, math.radians(rng.uniform(0.0, max_angle_deg)))
+    ta = rng.uniform(-trans, trans, size=3)
+    X = S @ Ra.T + ta + rng.normal(scale=noise, size=S.shape)
+    nout = int(round(rng.uniform(0.0, max_outliers) * N))
+    if nout:
+        lo, hi = X.min(axis=0), X.max(axis=0)
+        X[rng.choice(N, size=nout, replace=False)] = rng.uniform(lo, hi, size=(nout, 3))
+    return Pair(X=X.astype(np.float32), Y=Y.astype(np.float32), R_gt=Ra.T.copy(),
+                t_gt=-(Ra.T @ ta), name=name)
+
+
+def batch_pairs(n=256, trial=0, nmin=1000, nmax=30000):
+    """n scene pairs with M and N independently log-uniform in [nmin, nmax]."""
+    rng = rng_for(3, trial)
+    lo, hi = math.log(nmin), math.log(nmax)
+    out = []
+    for i in range(n):
+        M = int(round(math.exp(rng.uniform(lo, hi))))
+        N = int(round(math.exp(rng.uniform(lo, hi))))
+        out.append(scene_pair(rng, M, N, name=f"batch{trial}_{i}_{M}x{N}"))
+    return out
+
+
 WORKLOADS = {
     "range_scanner_2000x2000": range_scanner_pair,
     "rgbd_20000x20000": rgbd_pair,

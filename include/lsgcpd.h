@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LSGCPD_ABI_VERSION 2
+#define LSGCPD_ABI_VERSION 3
 
 typedef struct lsgcpd_ctx lsgcpd_ctx;
 typedef void *lsgcpd_stream;  /* a hipStream_t */
@@ -201,6 +201,25 @@ lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const 
                               int64_t M, const lsgcpd_params *p, const lsgcpd_pose *init,
                               lsgcpd_pose *out, lsgcpd_report *report, double *nll_trace,
                               lsgcpd_stream stream);
+
+/* Registers npairs independent pairs (X[i], N[i]) to (Y[i], M[i]) with the
+ * same parameters, as lsgcpd_register does each of them, but in one pipeline:
+ * every EM iteration runs the E steps and M steps of all pairs in the same
+ * kernel launches, with the work items of the pair kernel shared out in
+ * proportion to M[i] N[i].  X, N, Y, M, init (NULL => identity for every
+ * pair), out and reports (may be NULL) are HOST arrays of npairs entries;
+ * X[i] and Y[i] are device pointers.  Each pair stops on its own tol test.
+ * Results equal lsgcpd_register's up to the grouping of the sums (the work
+ * items differ).  Requires 1 <= npairs <= 65536, sum of N[i] + M[i] at most
+ * 2^27, k <= M[i], and the default pair kernel (LSGCPD_PAIRS_LDS / _MFMA give
+ * LSGCPD_E_UNSUPPORTED for npairs > 1).  Synchronises `stream`.  (The
+ * batched-registration row of the design: many pairs of uneven sizes per
+ * launch.) */
+lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs, const float *const *X,
+                                    const int64_t *N, const float *const *Y, const int64_t *M,
+                                    const lsgcpd_params *p, const lsgcpd_pose *init,
+                                    lsgcpd_pose *out, lsgcpd_report *reports,
+                                    lsgcpd_stream stream);
 
 /* ---- kernel timing (benchmarks) ----------------------------------------- */
 

@@ -26,8 +26,8 @@ NSTATS = 86
 
 SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
            "lsgcpd_ctx_destroy", "lsgcpd_last_error", "lsgcpd_params_default",
-           "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_profile_enable",
-           "lsgcpd_profile_read")
+           "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_register_batch",
+           "lsgcpd_profile_enable", "lsgcpd_profile_read")
 
 
 class Pose(C.Structure):
@@ -103,6 +103,9 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_register.restype = C.c_int
     lib.lsgcpd_register.argtypes = [vp, vp, i64, vp, i64, C.POINTER(Params), C.POINTER(Pose),
                                     C.POINTER(Pose), C.POINTER(Report), vp, vp]
+    lib.lsgcpd_register_batch.restype = C.c_int
+    lib.lsgcpd_register_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Params),
+                                          C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Report), vp]
     lib.lsgcpd_profile_enable.restype = C.c_int
     lib.lsgcpd_profile_enable.argtypes = [vp, C.c_int]
     lib.lsgcpd_profile_read.restype = C.c_int
@@ -297,6 +300,50 @@ def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, to
     return RegistrationResult(R=R, t=t, sigma2=rep.sigma2, iters=rep.iters,
                               converged=bool(rep.converged), gn_fallbacks=rep.gn_fallbacks,
                               nll=np.array(trace[:filled]), V=rep.V)
+
+
+def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
+                   sigma2_init=0.0, newton_max=20, exact=False, dense=False, init=None):
+    """Registers every (X, Y) of `pairs` in one batched pipeline
+    (lsgcpd_register_batch); returns one RegistrationResult per pair (its
+    `nll` holds the first and the last value of Eq. 4 only)."""
+    n = len(pairs)
+    if n < 1:
+        raise ValueError("no pairs")
+    Xs, Ys = [], []
+    dev = None
+    for X, Y in pairs:
+        X = _dev_tensor(X, (3,), "X", dev)
+        dev = X.device.index
+        Xs.append(X)
+        Ys.append(_dev_tensor(Y, (3,), "Y", dev))
+    p = Params(k=int(k), alpha_max=float(alpha_max), lambda_=float(lam), w0=float(w0),
+               V=float(V), max_iter=int(max_iter), tol=float(tol),
+               sigma2_init=float(sigma2_init), newton_max=int(newton_max),
+               flags=(EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0))
+    xp = (C.c_void_p * n)(*[_ptr(X) for X in Xs])
+    yp = (C.c_void_p * n)(*[_ptr(Y) for Y in Ys])
+    nn = (C.c_int64 * n)(*[X.shape[0] for X in Xs])
+    mm = (C.c_int64 * n)(*[Y.shape[0] for Y in Ys])
+    poses = None
+    if init is not None:
+        poses = (Pose * n)(*[_pose(R, t) for R, t in init])
+    out = (Pose * n)()
+    rep = (Report * n)()
+    ctx = context(dev)
+    st = load_library().lsgcpd_register_batch(ctx, n, C.cast(xp, C.c_void_p),
+                                              C.cast(nn, C.c_void_p), C.cast(yp, C.c_void_p),
+                                              C.cast(mm, C.c_void_p), C.byref(p), poses, out, rep,
+                                              _stream(dev))
+    _check(st, ctx)
+    res = []
+    for i in range(n):
+        R, t = _pose_np(out[i])
+        r = rep[i]
+        res.append(RegistrationResult(R=R, t=t, sigma2=r.sigma2, iters=r.iters,
+                                      converged=bool(r.converged), gn_fallbacks=r.gn_fallbacks,
+                                      nll=np.array([r.nll_first, r.nll_last]), V=r.V))
+    return res
 
 
 def profile_enable(on=True, device=0):

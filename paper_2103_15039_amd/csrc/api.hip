@@ -19,6 +19,7 @@ using lsg::DevState;
 namespace {
 
 constexpr int64_t kMaxPoints = (int64_t)1 << 27;
+constexpr int kMaxBatch = 1 << 16;
 
 struct Buf {
   void *p = nullptr;
@@ -31,9 +32,12 @@ struct lsgcpd_ctx {
   int device = 0;
   std::string err;
   Buf knn, rec, pts, boxes, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
-      trace, order, xperm, yperm, ys4;
-  DevState *dstate = nullptr;  // device
-  DevState *hstate = nullptr;  // pinned host staging
+      trace, order, xperm, yperm, ys4, tables, states;
+  DevState *dstate = nullptr;  // device states (ctx->states), one per problem of a batch
+  DevState *hstate = nullptr;  // pinned host staging for hcap states
+  size_t hcap = 0;
+  std::vector<char> htables;   // host copy of the batch tables
+  std::vector<double> htrace;
   // E-step timing: 4 events per E step (start, before and after the pair
   // kernel, end)
   bool prof = false;
@@ -82,6 +86,12 @@ lsgcpd_status ensure(lsgcpd_ctx *ctx, Buf &b, size_t bytes) {
   return LSGCPD_OK;
 }
 
+#define RETURN_IF(x)                \
+  do {                              \
+    lsgcpd_status s_ = (x);         \
+    if (s_ != LSGCPD_OK) return s_; \
+  } while (0)
+
 #define ENSURE(buf, bytes)                                     \
   do {                                                         \
     lsgcpd_status s_ = ensure(ctx, ctx->buf, (size_t)(bytes)); \
@@ -129,6 +139,26 @@ lsgcpd_status check_pose(lsgcpd_ctx *ctx, const lsgcpd_pose *g) {
   return LSGCPD_OK;
 }
 
+// Checks shared by the registration calls.
+lsgcpd_status check_params(lsgcpd_ctx *ctx, const lsgcpd_params *p) {
+  if (p->k < 1 || p->k > 32)
+    return fail(ctx, LSGCPD_E_INVALID, "k = %d must satisfy 1 <= k <= min(M, 32)", p->k);
+  if (!(p->alpha_max >= 0.0) || !isfinite(p->alpha_max))
+    return fail(ctx, LSGCPD_E_INVALID, "alpha_max must be finite and >= 0");
+  if (!finite_pos(p->lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
+  if (!(p->w0 > 0.0 && p->w0 < 1.0)) return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
+  if (!isfinite(p->V) || !isfinite(p->tol) || !isfinite(p->sigma2_init))
+    return fail(ctx, LSGCPD_E_INVALID, "V, tol and sigma2_init must be finite");
+  if (p->max_iter < 0 || p->max_iter > 100000)
+    return fail(ctx, LSGCPD_E_INVALID, "max_iter = %d out of range", p->max_iter);
+  if (p->newton_max < 1 || p->newton_max > 1000)
+    return fail(ctx, LSGCPD_E_INVALID, "newton_max = %d out of range", p->newton_max);
+  if (p->flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", p->flags);
+  if ((p->flags & LSGCPD_PAIRS_LDS) && (p->flags & LSGCPD_PAIRS_MFMA))
+    return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
+  return LSGCPD_OK;
+}
+
 lsgcpd_status set_device(lsgcpd_ctx *ctx) {
   HIPCHK(hipSetDevice(ctx->device));
   return LSGCPD_OK;
@@ -151,55 +181,80 @@ void fill_state(DevState *s, const lsgcpd_pose *g, double sigma2, double V, doub
   s->max_iter = max_iter;
 }
 
-// Target records (record i describes target yperm[i], or target i if yperm is
-// null) and their tile boxes + moments of Y, X at the state's pose + init_state.
-lsgcpd_status setup(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
-                    const float *normals, const float *alpha, const float *pi,
-                    const uint32_t *yperm, int64_t M, uint32_t flags, int v_auto, int s2_auto,
-                    hipStream_t st) {
-  ENSURE(rec, (size_t)(M + 1) * sizeof(lsg::TRec));  // + sentinel
-  ENSURE(pts, (size_t)M * sizeof(lsg::TPt));
-  ENSURE(boxes, (size_t)((M + lsg::kCullTile - 1) / lsg::kCullTile) * sizeof(lsg::TBox));
-  const int nb = lsg::moments_blocks(N > M ? N : M);
-  ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
-  ENSURE(mom, 48 * sizeof(double));
-  HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
-  HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, pi, yperm, M,
-                                  (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0,
-                                  (lsg::TRec *)ctx->rec.p, (lsg::TPt *)ctx->pts.p,
-                                  (lsg::TBox *)ctx->boxes.p, st));
-  double *ymom = (double *)ctx->mom.p;
-  double *xmom = ymom + 16;
-  HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(M),
-                             ymom, st));
-  if (s2_auto)
-    HIPCHK(lsg::launch_moments(X, N, ctx->dstate, (double *)ctx->mom_part.p,
-                               lsg::moments_blocks(N), xmom, st));
-  HIPCHK(lsg::launch_init_state(ctx->dstate, ymom, xmom, M, N, v_auto, s2_auto, st));
+// Device and pinned host states for n problems.
+lsgcpd_status ensure_states(lsgcpd_ctx *ctx, int n) {
+  ENSURE(states, (size_t)n * sizeof(DevState));
+  ctx->dstate = (DevState *)ctx->states.p;
+  if (ctx->hcap < (size_t)n) {
+    if (ctx->hstate) (void)hipHostFree(ctx->hstate);
+    ctx->hstate = nullptr;
+    ctx->hcap = 0;
+    if (hipHostMalloc((void **)&ctx->hstate, (size_t)n * sizeof(DevState), hipHostMallocDefault) !=
+        hipSuccess) {
+      ctx->hstate = nullptr;
+      (void)hipGetLastError();
+      return fail(ctx, LSGCPD_E_NOMEM, "pinned host staging for %d states failed", n);
+    }
+    ctx->hcap = (size_t)n;
+  }
   return LSGCPD_OK;
 }
 
-// Y in Morton order: ctx->ys4 (x, y, z, original index) and ctx->yperm.
-lsgcpd_status sort_targets(lsgcpd_ctx *ctx, const float *Y, int64_t M, hipStream_t st) {
+// Problem p of a batch: target records (record i of the problem describes its
+// target yperm[i], or target i if yperm is null) and their tile boxes, then
+// moments of Y, X at the problem's pose, then init_state.
+lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, int p, const float *Y,
+                            const float *normals, const float *alpha, const float *pi,
+                            const uint32_t *yperm, uint32_t flags, int v_auto, int s2_auto,
+                            hipStream_t st) {
+  const lsg::Slot &sl = pl.slots[p];
+  HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, pi, yperm, sl.M,
+                                  (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0,
+                                  (lsg::TRec *)ctx->rec.p + sl.y_off + p,
+                                  (lsg::TPt *)ctx->pts.p + sl.y_off,
+                                  (lsg::TBox *)ctx->boxes.p + sl.t_off, st));
+  double *ymom = (double *)ctx->mom.p;
+  double *xmom = ymom + 16;
+  HIPCHK(lsg::launch_moments(Y, sl.M, nullptr, (double *)ctx->mom_part.p,
+                             lsg::moments_blocks(sl.M), ymom, st));
+  if (s2_auto)
+    HIPCHK(lsg::launch_moments(sl.X, sl.N, ctx->dstate + p, (double *)ctx->mom_part.p,
+                               lsg::moments_blocks(sl.N), xmom, st));
+  HIPCHK(lsg::launch_init_state(ctx->dstate + p, ymom, xmom, sl.M, sl.N, v_auto, s2_auto, st));
+  return LSGCPD_OK;
+}
+
+// Y (M points) in Morton order into ys4 + off (x, y, z, index within Y) and
+// yperm + off.
+lsgcpd_status sort_targets(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t off,
+                           hipStream_t st) {
   const int nb = lsg::moments_blocks(M);
-  ENSURE(mom_part, (size_t)nb * 10 * sizeof(double));
-  ENSURE(mom, 48 * sizeof(double));
-  ENSURE(order, lsg::morton_workspace_bytes(M));
-  ENSURE(yperm, (size_t)M * sizeof(uint32_t));
-  ENSURE(ys4, (size_t)M * sizeof(float4));
   double *box = (double *)ctx->mom.p + 32;
   HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, nb, box, st));
   HIPCHK(lsg::launch_morton_order(Y, M, box, ctx->order.p, ctx->order.cap, nullptr,
-                                  (float4 *)ctx->ys4.p, (uint32_t *)ctx->yperm.p, st));
+                                  (float4 *)ctx->ys4.p + off, (uint32_t *)ctx->yperm.p + off, st));
   return LSGCPD_OK;
 }
 
-lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int k, double alpha_max,
-                             double lambda, float *normals, float *kappa, float *alpha,
-                             hipStream_t st) {
-  ENSURE(knn, lsg::knn_workspace_bytes(M, k));
-  HIPCHK(lsg::launch_normals(Y, M, (const float4 *)ctx->ys4.p, (const uint32_t *)ctx->yperm.p, k,
-                             alpha_max, lambda, normals, kappa, alpha, ctx->knn.p, st));
+lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t off, int k,
+                             double alpha_max, double lambda, float *normals, float *kappa,
+                             float *alpha, hipStream_t st) {
+  HIPCHK(lsg::launch_normals(Y, M, (const float4 *)ctx->ys4.p + off,
+                             (const uint32_t *)ctx->yperm.p + off, k, alpha_max, lambda, normals,
+                             kappa, alpha, ctx->knn.p, st));
+  return LSGCPD_OK;
+}
+
+// Workspace shared by the target sort and the neighbour search of clouds of
+// at most `nmax` points (k neighbours), and the sorted copies of `mtot`
+// targets.
+lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int64_t nmax, int64_t mmax, int64_t mtot, int k) {
+  ENSURE(order, lsg::morton_workspace_bytes(nmax));
+  ENSURE(mom_part, (size_t)lsg::moments_blocks(nmax) * 10 * sizeof(double));
+  ENSURE(mom, 48 * sizeof(double));
+  ENSURE(yperm, (size_t)mtot * sizeof(uint32_t));
+  ENSURE(ys4, (size_t)mtot * sizeof(float4));
+  ENSURE(knn, lsg::knn_workspace_bytes(mmax, k));
   return LSGCPD_OK;
 }
 
@@ -240,44 +295,171 @@ lsgcpd_status prof_collect(lsgcpd_ctx *ctx, int64_t evaluated) {
   return LSGCPD_OK;
 }
 
-// One E step (accumulation, finalisation) + reduction/M step in `mode`.
-lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::EstepPlan &pl, const float *X, int64_t N,
-                        int64_t M, const float *w, double *colstats, double *trace, int mode,
-                        hipStream_t st) {
+// One E step (plan, accumulation, finalisation) + reduction/M step in
+// `mode`, for every problem of the batch.
+lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::BatchDev &bd,
+                        double *colS, double *colstats, double *trace, int trace_stride,
+                        int mode, hipStream_t st) {
   lsgcpd_status s = prof_record(ctx, st);
   if (s != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_plan(pl, X, N, (const lsg::TBox *)ctx->boxes.p, ctx->dstate,
+  HIPCHK(lsg::launch_estep_plan(pl, bd, (const lsg::TBox *)ctx->boxes.p, ctx->dstate,
                                 ctx->plan.p, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_pairs(pl, X, N, (const lsg::TRec *)ctx->rec.p,
-                                 (const lsg::TPt *)ctx->pts.p, M, ctx->dstate, ctx->plan.p,
+  HIPCHK(lsg::launch_estep_pairs(pl, bd, (const lsg::TRec *)ctx->rec.p,
+                                 (const lsg::TPt *)ctx->pts.p, ctx->dstate, ctx->plan.p,
                                  (double *)ctx->partial.p, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_finalize(pl, X, N, w, ctx->dstate, ctx->plan.p,
-                              (const double *)ctx->partial.p, (double *)ctx->blockstats.p,
-                              (double *)ctx->colS.p, colstats, st));
+  HIPCHK(lsg::launch_finalize(pl, bd, ctx->dstate, ctx->plan.p, (const double *)ctx->partial.p,
+                              (double *)ctx->blockstats.p, colS, colstats, st));
   if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  if (ctx->prof) ctx->prof_pairs_pending += M * N;
-  HIPCHK(lsg::launch_reduce_mstep((double *)ctx->blockstats.p, pl.nfin_blocks, N, ctx->dstate,
-                                  trace, lsg::estep_plan_counter(pl, ctx->plan.p), mode, st));
+  if (ctx->prof)
+    for (const lsg::Slot &sl : pl.slots) ctx->prof_pairs_pending += (int64_t)sl.M * sl.N;
+  HIPCHK(lsg::launch_reduce_mstep(pl, bd, (double *)ctx->blockstats.p, ctx->dstate, trace,
+                                  trace_stride, lsg::estep_plan_counter(pl, ctx->plan.p), mode,
+                                  st));
   return LSGCPD_OK;
 }
 
-lsgcpd_status ensure_estep(lsgcpd_ctx *ctx, const lsg::EstepPlan &pl, int64_t N) {
+// E-step workspace and the tables of the plan (uploaded on `st`).
+lsgcpd_status ensure_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl) {
   ENSURE(plan, lsg::estep_plan_bytes(pl));
-  ENSURE(partial, lsg::estep_partial_bytes(pl, N));
-  ENSURE(blockstats, (size_t)pl.nfin_blocks * lsg::kStats * sizeof(double));
-  ENSURE(colS, (size_t)N * sizeof(double));
+  ENSURE(partial, lsg::estep_partial_bytes(pl));
+  ENSURE(blockstats, (size_t)pl.fins * lsg::kStats * sizeof(double));
+  ENSURE(tables, lsg::batch_tables_bytes(pl));
+  ENSURE(rec, (size_t)(pl.targets + pl.npairs) * sizeof(lsg::TRec));  // + a sentinel each
+  ENSURE(pts, (size_t)pl.targets * sizeof(lsg::TPt));
+  ENSURE(boxes, (size_t)pl.tiles * sizeof(lsg::TBox));
+  ENSURE(mom, 48 * sizeof(double));
+  int64_t nmax = 1;
+  for (const lsg::Slot &sl : pl.slots) {
+    nmax = sl.N > nmax ? sl.N : nmax;
+    nmax = sl.M > nmax ? sl.M : nmax;
+  }
+  ENSURE(mom_part, (size_t)lsg::moments_blocks(nmax) * 10 * sizeof(double));
   return LSGCPD_OK;
+}
+
+lsgcpd_status upload_tables(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, hipStream_t st,
+                            lsg::BatchDev *bd) {
+  lsg::batch_tables_pack(pl, ctx->htables);
+  HIPCHK(hipMemcpyAsync(ctx->tables.p, ctx->htables.data(), ctx->htables.size(),
+                        hipMemcpyHostToDevice, st));
+  *bd = lsg::batch_tables_view(pl, ctx->tables.p);
+  return LSGCPD_OK;
+}
+
+// Registration of npairs problems that share the parameters: the E steps and
+// M steps of all problems run in the same launches.
+lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const *X,
+                                const int64_t *N, const float *const *Y, const int64_t *M,
+                                const lsgcpd_params *p, const lsgcpd_pose *init,
+                                lsgcpd_pose *out, lsgcpd_report *reports, double *nll_trace,
+                                hipStream_t st) {
+  const int backend = backend_of(p->flags);
+  if (npairs > 1 && backend != lsg::kBackendScalar)
+    return fail(ctx, LSGCPD_E_UNSUPPORTED, "batches use the default pair kernel only");
+  lsg::BatchPlan pl =
+      lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1, work_items());
+  int64_t nmax = 1, mmax = 1;
+  for (int i = 0; i < npairs; ++i) {
+    nmax = N[i] > nmax ? N[i] : nmax;
+    mmax = M[i] > mmax ? M[i] : mmax;
+  }
+  RETURN_IF(ensure_geometry(ctx, nmax > mmax ? nmax : mmax, mmax, pl.targets, p->k));
+  ENSURE(nrm, (size_t)pl.targets * 3 * sizeof(float));
+  ENSURE(kap, (size_t)pl.targets * sizeof(float));
+  ENSURE(alp, (size_t)pl.targets * sizeof(float));
+  const int stride = p->max_iter > 0 ? p->max_iter : 1;
+  ENSURE(trace, (size_t)npairs * stride * sizeof(double));
+  if (pl.cull) ENSURE(xperm, (size_t)pl.sources * 3 * sizeof(float));
+  RETURN_IF(ensure_states(ctx, npairs));
+  lsg::BatchDev bd;
+  RETURN_IF(ensure_estep(ctx, pl));
+
+  float *nrm = (float *)ctx->nrm.p, *kap = (float *)ctx->kap.p, *alp = (float *)ctx->alp.p;
+  // target geometry: neighbours over each Y in Morton order
+  for (int i = 0; i < npairs; ++i) {
+    const int64_t yo = pl.slots[i].y_off;
+    RETURN_IF(sort_targets(ctx, Y[i], M[i], yo, st));
+    RETURN_IF(normals_sorted(ctx, Y[i], M[i], yo, p->k, p->alpha_max, p->lambda, nrm + 3 * yo,
+                             kap + yo, alp + yo, st));
+  }
+  // With culling the target records follow the Morton order of Y and the
+  // sources are put in Morton order too, so that a source group's and a target
+  // tile's points are neighbours.  Every statistic is a sum over all sources
+  // and all targets, so the order changes only the rounding of the sums.
+  for (int i = 0; i < npairs; ++i) {
+    lsg::Slot &sl = pl.slots[i];
+    sl.X = X[i];
+    sl.w = nullptr;
+    if (pl.cull && N[i] > 256) {
+      float *xs = (float *)ctx->xperm.p + 3 * sl.x_off;
+      double *xbox = (double *)ctx->mom.p + 32;
+      HIPCHK(lsg::launch_moments(X[i], N[i], nullptr, (double *)ctx->mom_part.p,
+                                 lsg::moments_blocks(N[i]), xbox, st));
+      HIPCHK(lsg::launch_morton_order(X[i], N[i], xbox, ctx->order.p, ctx->order.cap, xs,
+                                      nullptr, nullptr, st));
+      sl.X = xs;
+    }
+  }
+  RETURN_IF(upload_tables(ctx, pl, st, &bd));
+  const int s2_auto = p->sigma2_init > 0.0 ? 0 : 1;
+  for (int i = 0; i < npairs; ++i)
+    fill_state(ctx->hstate + i, init ? init + i : nullptr, s2_auto ? 1.0 : p->sigma2_init,
+               p->V > 0.0 ? p->V : 0.0, p->w0, p->tol, p->newton_max, p->max_iter);
+  HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, (size_t)npairs * sizeof(DevState),
+                        hipMemcpyHostToDevice, st));
+  for (int i = 0; i < npairs; ++i) {
+    const int64_t yo = pl.slots[i].y_off;
+    RETURN_IF(setup_problem(ctx, pl, i, Y[i], nrm + 3 * yo, alp + yo, nullptr,
+                            pl.cull ? (const uint32_t *)ctx->yperm.p + yo : nullptr, p->flags,
+                            p->V > 0.0 ? 0 : 1, s2_auto, st));
+  }
+  RETURN_IF(prof_reserve(ctx, p->max_iter));
+  for (int it = 0; it < p->max_iter; ++it)
+    RETURN_IF(run_estep(ctx, pl, bd, nullptr, nullptr, (double *)ctx->trace.p, stride, 1, st));
+  HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, (size_t)npairs * sizeof(DevState),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  ctx->htrace.resize((size_t)npairs * stride);
+  HIPCHK(hipMemcpy(ctx->htrace.data(), ctx->trace.p, ctx->htrace.size() * sizeof(double),
+                   hipMemcpyDeviceToHost));
+  int64_t evaluated = 0;
+  for (int i = 0; i < npairs; ++i) {
+    const DevState &s = ctx->hstate[i];
+    evaluated += backend == lsg::kBackendScalar ? s.evaluated_pairs
+                                                : M[i] * N[i] * (s.iter + s.converged);
+  }
+  RETURN_IF(prof_collect(ctx, evaluated));
+  lsgcpd_status status = LSGCPD_OK;
+  for (int i = 0; i < npairs; ++i) {
+    const DevState &s = ctx->hstate[i];
+    const int filled = s.iter + s.converged;
+    const double *tr = ctx->htrace.data() + (size_t)i * stride;
+    memcpy(out[i].R, s.R, sizeof out[i].R);
+    memcpy(out[i].t, s.t, sizeof out[i].t);
+    if (reports) {
+      lsgcpd_report &r = reports[i];
+      r.iters = s.iter;
+      r.converged = s.converged;
+      r.gn_fallbacks = s.gn_fallbacks;
+      r.sigma2 = s.sigma2;
+      r.V = s.V;
+      r.nll_last = s.nll;
+      r.nll_first = p->max_iter > 0 && filled > 0 ? tr[0] : s.nll;
+    }
+    if (i == 0 && nll_trace && p->max_iter > 0)
+      memcpy(nll_trace, tr, (size_t)filled * sizeof(double));
+    if (status == LSGCPD_OK && s.numeric_error)
+      status = fail(ctx, LSGCPD_E_NUMERIC, "EM produced a non-finite pose or sigma^2 (pair %d)", i);
+    if (status == LSGCPD_OK && !finite_pos(s.sigma2))
+      status = fail(ctx, LSGCPD_E_NUMERIC, "sigma^2 is not finite (pair %d)", i);
+  }
+  return status;
 }
 
 }  // namespace
 
-#define RETURN_IF(x)                \
-  do {                              \
-    lsgcpd_status s_ = (x);         \
-    if (s_ != LSGCPD_OK) return s_; \
-  } while (0)
 
 LSG_API int lsgcpd_abi_version(void) { return LSGCPD_ABI_VERSION; }
 
@@ -303,11 +485,8 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
   }
   lsgcpd_ctx *c = new lsgcpd_ctx();
   c->device = device;
-  if (hipSetDevice(device) != hipSuccess ||
-      hipMalloc((void **)&c->dstate, sizeof(DevState)) != hipSuccess ||
-      hipHostMalloc((void **)&c->hstate, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess) {
     (void)hipGetLastError();
-    if (c->dstate) (void)hipFree(c->dstate);
     delete c;
     return LSGCPD_E_HIP;
   }
@@ -318,13 +497,13 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
 LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  Buf *bufs[] = {&c->knn,  &c->rec,      &c->pts, &c->boxes, &c->plan,  &c->partial,
-                 &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm, &c->kap,
-                 &c->alp,  &c->trace,    &c->order, &c->xperm, &c->yperm, &c->ys4};
+  Buf *bufs[] = {&c->knn,   &c->rec,   &c->pts,        &c->boxes, &c->plan,  &c->partial,
+                 &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm,  &c->kap,
+                 &c->alp,   &c->trace, &c->order,      &c->xperm, &c->yperm, &c->ys4,
+                 &c->tables, &c->states};
   for (Buf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-  if (c->dstate) (void)hipFree(c->dstate);
   if (c->hstate) (void)hipHostFree(c->hstate);
   delete c;
 }
@@ -358,8 +537,9 @@ LSG_API lsgcpd_status lsgcpd_normals(lsgcpd_ctx *ctx, const float *Y, int64_t M,
   if (!finite_pos(lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
-  RETURN_IF(sort_targets(ctx, Y, M, st));
-  return normals_sorted(ctx, Y, M, k, alpha_max, lambda, normals, kappa, alpha, st);
+  RETURN_IF(ensure_geometry(ctx, M, M, M, k));
+  RETURN_IF(sort_targets(ctx, Y, M, 0, st));
+  return normals_sorted(ctx, Y, M, 0, k, alpha_max, lambda, normals, kappa, alpha, st);
 }
 
 LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
@@ -383,14 +563,21 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   RETURN_IF(check_pose(ctx, g));
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
-  const lsg::EstepPlan pl =
-      lsg::estep_plan(N, M, backend_of(flags), (flags & LSGCPD_DENSE) ? 0 : 1, work_items());
-  RETURN_IF(ensure_estep(ctx, pl, N));
+  lsg::BatchPlan pl =
+      lsg::batch_plan(1, &N, &M, backend_of(flags), (flags & LSGCPD_DENSE) ? 0 : 1, work_items());
+  pl.slots[0].X = X;
+  pl.slots[0].w = w;
+  RETURN_IF(ensure_states(ctx, 1));
+  RETURN_IF(ensure_estep(ctx, pl));
+  ENSURE(colS, (size_t)N * sizeof(double));
+  lsg::BatchDev bd;
+  RETURN_IF(upload_tables(ctx, pl, st, &bd));
   fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 20, 1);
-  RETURN_IF(
-      setup(ctx, X, N, Y, normals, alpha, pi, nullptr, M, flags, V > 0.0 ? 0 : 1, 0, st));
+  HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
+  RETURN_IF(setup_problem(ctx, pl, 0, Y, normals, alpha, pi, nullptr, flags, V > 0.0 ? 0 : 1, 0,
+                          st));
   RETURN_IF(prof_reserve(ctx, 1));
-  RETURN_IF(run_estep(ctx, pl, X, N, M, w, colstats, nullptr, 0, st));
+  RETURN_IF(run_estep(ctx, pl, bd, (double *)ctx->colS.p, colstats, nullptr, 1, 0, st));
   if (P)
     HIPCHK(lsg::launch_dump_P(X, N, (const lsg::TRec *)ctx->rec.p, M, w, ctx->dstate,
                               (const double *)ctx->colS.p, P, st));
@@ -427,91 +614,43 @@ LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N
   if (N < 1 || M < 1 || N > kMaxPoints || M > kMaxPoints)
     return fail(ctx, LSGCPD_E_INVALID, "M = %lld, N = %lld out of range", (long long)M,
                 (long long)N);
-  if (p->k < 1 || p->k > 32 || p->k > M)
+  if (p->k > M)
     return fail(ctx, LSGCPD_E_INVALID, "k = %d must satisfy 1 <= k <= min(M, 32)", p->k);
-  if (!(p->alpha_max >= 0.0) || !isfinite(p->alpha_max))
-    return fail(ctx, LSGCPD_E_INVALID, "alpha_max must be finite and >= 0");
-  if (!finite_pos(p->lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
-  if (!(p->w0 > 0.0 && p->w0 < 1.0)) return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
-  if (!isfinite(p->V) || !isfinite(p->tol) || !isfinite(p->sigma2_init))
-    return fail(ctx, LSGCPD_E_INVALID, "V, tol and sigma2_init must be finite");
-  if (p->max_iter < 0 || p->max_iter > 100000)
-    return fail(ctx, LSGCPD_E_INVALID, "max_iter = %d out of range", p->max_iter);
-  if (p->newton_max < 1 || p->newton_max > 1000)
-    return fail(ctx, LSGCPD_E_INVALID, "newton_max = %d out of range", p->newton_max);
-  if (p->flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", p->flags);
-  if ((p->flags & LSGCPD_PAIRS_LDS) && (p->flags & LSGCPD_PAIRS_MFMA))
-    return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
+  RETURN_IF(check_params(ctx, p));
   if (init) RETURN_IF(check_pose(ctx, init));
   RETURN_IF(set_device(ctx));
-  hipStream_t st = (hipStream_t)stream;
+  return register_problems(ctx, 1, &X, &N, &Y, &M, p, init, out, report, nll_trace,
+                           (hipStream_t)stream);
+}
 
-  // target geometry: neighbours over Y in Morton order (the sort workspace is
-  // sized for both clouds up front, so it is not reallocated while in use)
-  ENSURE(order, lsg::morton_workspace_bytes(N > M ? N : M));
-  ENSURE(mom_part, (size_t)lsg::moments_blocks(N > M ? N : M) * 10 * sizeof(double));
-  ENSURE(nrm, (size_t)M * 3 * sizeof(float));
-  ENSURE(kap, (size_t)M * sizeof(float));
-  ENSURE(alp, (size_t)M * sizeof(float));
-  RETURN_IF(sort_targets(ctx, Y, M, st));
-  RETURN_IF(normals_sorted(ctx, Y, M, p->k, p->alpha_max, p->lambda, (float *)ctx->nrm.p,
-                           (float *)ctx->kap.p, (float *)ctx->alp.p, st));
-
-  const lsg::EstepPlan pl =
-      lsg::estep_plan(N, M, backend_of(p->flags), (p->flags & LSGCPD_DENSE) ? 0 : 1, work_items());
-  RETURN_IF(ensure_estep(ctx, pl, N));
-  // With culling the target records follow the Morton order of Y and the
-  // sources are put in Morton order too, so that a source group's and a target
-  // tile's points are neighbours.  Every statistic is a sum over all sources
-  // and all targets, so the order changes only the rounding of the sums.
-  const uint32_t *yperm = nullptr;
-  if (pl.backend == lsg::kBackendScalar && pl.cull && N > 256) {
-    ENSURE(xperm, (size_t)N * 3 * sizeof(float));
-    double *xbox = (double *)ctx->mom.p + 32;
-    HIPCHK(lsg::launch_moments(X, N, nullptr, (double *)ctx->mom_part.p, lsg::moments_blocks(N),
-                               xbox, st));
-    HIPCHK(lsg::launch_morton_order(X, N, xbox, ctx->order.p, ctx->order.cap,
-                                    (float *)ctx->xperm.p, nullptr, nullptr, st));
-    X = (const float *)ctx->xperm.p;
-    yperm = (const uint32_t *)ctx->yperm.p;
+LSG_API lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs,
+                                            const float *const *X, const int64_t *N,
+                                            const float *const *Y, const int64_t *M,
+                                            const lsgcpd_params *p, const lsgcpd_pose *init,
+                                            lsgcpd_pose *out, lsgcpd_report *reports,
+                                            lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!X || !N || !Y || !M || !p || !out)
+    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  if (npairs < 1 || npairs > kMaxBatch)
+    return fail(ctx, LSGCPD_E_INVALID, "npairs = %d out of range", npairs);
+  RETURN_IF(check_params(ctx, p));
+  int64_t total = 0;
+  for (int i = 0; i < npairs; ++i) {
+    if (!X[i] || !Y[i]) return fail(ctx, LSGCPD_E_INVALID, "NULL cloud of pair %d", i);
+    if (N[i] < 1 || M[i] < 1 || N[i] > kMaxPoints || M[i] > kMaxPoints)
+      return fail(ctx, LSGCPD_E_INVALID, "pair %d: M = %lld, N = %lld out of range", i,
+                  (long long)M[i], (long long)N[i]);
+    if (p->k > M[i])
+      return fail(ctx, LSGCPD_E_INVALID, "pair %d: k = %d exceeds M = %lld", i, p->k,
+                  (long long)M[i]);
+    if (init) RETURN_IF(check_pose(ctx, init + i));
+    total += N[i] + M[i];
   }
-  ENSURE(trace, (size_t)(p->max_iter > 0 ? p->max_iter : 1) * sizeof(double));
-  const int s2_auto = p->sigma2_init > 0.0 ? 0 : 1;
-  fill_state(ctx->hstate, init, s2_auto ? 1.0 : p->sigma2_init, p->V > 0.0 ? p->V : 0.0, p->w0,
-             p->tol, p->newton_max, p->max_iter);
-  RETURN_IF(setup(ctx, X, N, Y, (const float *)ctx->nrm.p, (const float *)ctx->alp.p, nullptr,
-                  yperm, M, p->flags, p->V > 0.0 ? 0 : 1, s2_auto, st));
-  RETURN_IF(prof_reserve(ctx, p->max_iter));
-  for (int it = 0; it < p->max_iter; ++it)
-    RETURN_IF(run_estep(ctx, pl, X, N, M, nullptr, nullptr, (double *)ctx->trace.p, 1, st));
-  HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, sizeof(DevState), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  RETURN_IF(prof_collect(ctx, pl.backend == lsg::kBackendScalar
-                                  ? ctx->hstate->evaluated_pairs
-                                  : M * N * (ctx->hstate->iter + ctx->hstate->converged)));
-  double first = ctx->hstate->nll;
-  if (p->max_iter > 0 && ctx->hstate->iter + ctx->hstate->converged > 0) {
-    HIPCHK(hipMemcpy(&first, ctx->trace.p, sizeof(double), hipMemcpyDeviceToHost));
-    const int filled = ctx->hstate->iter + ctx->hstate->converged;
-    if (nll_trace)
-      HIPCHK(hipMemcpy(nll_trace, ctx->trace.p, (size_t)filled * sizeof(double),
-                       hipMemcpyDeviceToHost));
-  }
-  const DevState &s = *ctx->hstate;
-  memcpy(out->R, s.R, sizeof out->R);
-  memcpy(out->t, s.t, sizeof out->t);
-  if (report) {
-    report->iters = s.iter;
-    report->converged = s.converged;
-    report->gn_fallbacks = s.gn_fallbacks;
-    report->sigma2 = s.sigma2;
-    report->V = s.V;
-    report->nll_last = s.nll;
-    report->nll_first = first;
-  }
-  if (s.numeric_error) return fail(ctx, LSGCPD_E_NUMERIC, "EM produced a non-finite pose or sigma^2");
-  if (!finite_pos(s.sigma2)) return fail(ctx, LSGCPD_E_NUMERIC, "sigma^2 is not finite");
-  return LSGCPD_OK;
+  if (total > kMaxPoints) return fail(ctx, LSGCPD_E_INVALID, "batch holds more than 2^27 points");
+  RETURN_IF(set_device(ctx));
+  return register_problems(ctx, npairs, X, N, Y, M, p, init, out, reports, nullptr,
+                           (hipStream_t)stream);
 }
 
 LSG_API lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on) {

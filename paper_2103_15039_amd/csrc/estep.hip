@@ -40,6 +40,7 @@
 // small N; their partial sums are combined in a fixed order by estep_finalize,
 // so results are bitwise reproducible.
 #include <math.h>
+#include <string.h>
 
 #include "lsgcpd_internal.h"
 
@@ -176,15 +177,23 @@ constexpr int kSrcPerLane = 2;
 constexpr int kGroup = 64 * kSrcPerLane;
 
 // Scaled-coordinate bounding box of each source group (kept for the pair
-// kernel), then the live tiles in increasing order.
-__global__ __launch_bounds__(kBlock) void cull_groups(const float *__restrict__ X, int N,
-                                                      const DevState *__restrict__ st,
+// kernel), then the live tiles in increasing order.  One block per group of
+// every problem of the batch.
+__global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ slots,
+                                                      const int *__restrict__ grp_slot,
+                                                      const DevState *__restrict__ states,
                                                       const TBox *__restrict__ boxes,
-                                                      int ntiles, int *__restrict__ counts,
+                                                      int *__restrict__ counts,
                                                       double *__restrict__ gbox,
                                                       int *__restrict__ list) {
+  const int b = blockIdx.x;
+  const int p = grp_slot[b];
+  const DevState *st = states + p;
   if (st->done) return;
-  const int g = blockIdx.x;
+  const Slot &sl = slots[p];
+  const int g = b - sl.g_off, N = sl.N, ntiles = sl.ntiles;
+  const float *X = sl.X;
+  const TBox *bx_t = boxes + sl.t_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double R[9], t[3];
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
@@ -220,15 +229,15 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const float *__restrict__ 
   }
   if (threadIdx.x == 0)
     for (int a = 0; a < 3; ++a) {
-      gbox[g * 8 + a] = lo[a];
-      gbox[g * 8 + 3 + a] = hi[a];
+      gbox[b * 8 + a] = lo[a];
+      gbox[b * 8 + 3 + a] = hi[a];
     }
-  int *out = list + (int64_t)g * ntiles;
+  int *out = list + sl.list_off + (int64_t)g * ntiles;
   int base = 0;
   for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
     const int ti = t0 + threadIdx.x;
     const bool live =
-        ti < ntiles && box_live(boxes[ti].lo, boxes[ti].hi, boxes[ti].lmax, lo, hi, sc);
+        ti < ntiles && box_live(bx_t[ti].lo, bx_t[ti].hi, bx_t[ti].lmax, lo, hi, sc);
     const uint64_t bal = __ballot(live);
     if (lane == 0) wc[wave] = __popcll(bal);
     __syncthreads();
@@ -238,27 +247,35 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const float *__restrict__ 
     base += wc[0] + wc[1] + wc[2] + wc[3];
     __syncthreads();
   }
-  if (threadIdx.x == 0) counts[g] = base;
+  if (threadIdx.x == 0) counts[b] = base;
 }
 
-// Items: L tiles each (L a multiple of 4, at least 4), about `target` in all.
-// Without culling every group lists all tiles and no per-group pass runs.
-// Also clears the counter of evaluated pairs for the pair kernel.
+// Items of one problem (one block per problem): L tiles each (L a multiple
+// of 4, at least 4), about `target` in all.  Without culling every group
+// lists all tiles.  Also clears the problem's counter of evaluated pairs.
+// Offsets: group g of problem p has its items at off[g_off + p + g] ..
+// off[g_off + p + g + 1] - 1 (local to the problem's item range).
 template <bool CULL>
-__global__ __launch_bounds__(kBlock) void cull_items(const DevState *__restrict__ st,
+__global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ slots,
+                                                     const DevState *__restrict__ states,
                                                      const int *__restrict__ counts,
-                                                     int ngroups, int ntiles, int target,
-                                                     int cap, CullHdr *__restrict__ hdr,
-                                                     int *__restrict__ off,
-                                                     int *__restrict__ map,
-                                                     unsigned long long *__restrict__ evcount) {
-  if (st->done) return;
+                                                     CullHdr *__restrict__ hdrs,
+                                                     int *__restrict__ offs,
+                                                     int *__restrict__ maps,
+                                                     unsigned long long *__restrict__ evcounts) {
+  const int p = blockIdx.x;
+  if (states[p].done) return;
+  const Slot &sl = slots[p];
+  const int ngroups = sl.ngroups, ntiles = sl.ntiles, target = sl.target, cap = sl.item_cap;
+  const int *cnts = counts + sl.g_off;
+  int *off = offs + sl.g_off + p;
+  int *map = maps + sl.item_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ int64_t red[4];
   __shared__ int scan[kBlock];
   int64_t tiles = 0;
   if (CULL) {
-    for (int g = threadIdx.x; g < ngroups; g += kBlock) tiles += counts[g];
+    for (int g = threadIdx.x; g < ngroups; g += kBlock) tiles += cnts[g];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tiles += __shfl_xor(tiles, o, 64);
     if (lane == 0) red[wave] = tiles;
@@ -272,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void cull_items(const DevState *__restrict_
   int run = 0;
   for (int g0 = 0; g0 < ngroups; g0 += kBlock) {
     const int g = g0 + threadIdx.x;
-    const int64_t cnt = g < ngroups ? (CULL ? counts[g] : ntiles) : 0;
+    const int64_t cnt = g < ngroups ? (CULL ? cnts[g] : ntiles) : 0;
     const int v = (int)((cnt + L - 1) / L);
     scan[threadIdx.x] = v;
     __syncthreads();
@@ -292,35 +309,45 @@ __global__ __launch_bounds__(kBlock) void cull_items(const DevState *__restrict_
   }
   if (threadIdx.x == 0) {
     off[ngroups] = run;
-    hdr->items = run < cap ? run : cap;
-    hdr->tiles_per_item = (int)L;
-    *evcount = 0ull;
+    hdrs[p].items = run < cap ? run : cap;
+    hdrs[p].tiles_per_item = (int)L;
+    evcounts[p] = 0ull;
   }
 }
 
 template <bool CULL>
 // 4 waves per SIMD (at most 128 VGPRs) hide the scalar-load latency
 __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
-    const float *__restrict__ X, int N, const TRec *__restrict__ rec,
-    const TPt *__restrict__ pts, int64_t M, const DevState *__restrict__ st,
-    const CullHdr *__restrict__ hdr, const int *__restrict__ counts,
-    const int *__restrict__ off, const int *__restrict__ map, const int *__restrict__ list,
-    const double *__restrict__ gbox, int ntiles, unsigned long long *__restrict__ evcount,
-    double *__restrict__ partial) {
+    const Slot *__restrict__ slots, const int *__restrict__ item_slot,
+    const DevState *__restrict__ states, const TRec *__restrict__ recs,
+    const TPt *__restrict__ ptss, const CullHdr *__restrict__ hdrs,
+    const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
+    const int *__restrict__ list, const double *__restrict__ gboxes,
+    unsigned long long *__restrict__ evcounts, double *__restrict__ partial) {
   constexpr int S = kSrcPerLane;
+  const int b = blockIdx.x;
+  const int p = item_slot[b];
+  const DevState *st = states + p;
   if (st->done) return;
-  const int item = blockIdx.x;
-  if (item >= hdr->items) return;
+  const Slot &sl = slots[p];
+  const int item = b - sl.item_off;
+  if (item >= hdrs[p].items) return;
   // the wave index is wave-uniform; readfirstlane tells the compiler so, which
   // keeps the tile loop (and so the record loads) scalar
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = map[item];
-  const int L = hdr->tiles_per_item;
-  const int k0 = (item - off[g]) * L;
-  const int cnt = CULL ? counts[g] : ntiles;
+  const int N = sl.N, ntiles = sl.ntiles;
+  const int64_t M = sl.M;
+  const float *X = sl.X;
+  const TRec *rec = recs + sl.y_off + p;  // the problem's records, sentinel at rec[M]
+  const TPt *pts = ptss + sl.y_off;
+  const int g = maps[b];
+  const int L = hdrs[p].tiles_per_item;
+  const int k0 = (item - offs[sl.g_off + p + g]) * L;
+  const int cnt = CULL ? counts[sl.g_off + g] : ntiles;
   const int kn = cnt - k0 < L ? cnt - k0 : L;
-  const int *tl = list + (int64_t)g * ntiles + k0;
+  const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
+  const double *gbox = gboxes + (int64_t)(sl.g_off + g) * 8;
   double R[9], t[3];
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
@@ -337,8 +364,8 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   double blo[3], bhi[3];
   if constexpr (CULL)
     for (int a = 0; a < 3; ++a) {
-      blo[a] = gbox[g * 8 + a];
-      bhi[a] = gbox[g * 8 + 3 + a];
+      blo[a] = gbox[a];
+      bhi[a] = gbox[3 + a];
     }
   const int Mi = (int)M;  // M < 2^27: 32-bit scalar loop arithmetic
   // the wave's tiles are j = wave, wave + 4, ...; their indices are fetched 64
@@ -393,7 +420,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   __shared__ int wdone[4];
   if (lane == 0) wdone[wave] = done;
   __shared__ double red[3][kFeatUsed][64];
-  double *dst = partial + (size_t)item * kFeatUsed * kGroup;
+  double *dst = partial + (size_t)b * kFeatUsed * kGroup;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     if (wave > 0)
@@ -411,7 +438,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   if (threadIdx.x == 0) {
     const unsigned long long nv =
         (unsigned long long)(N - g * kGroup < kGroup ? N - g * kGroup : kGroup);
-    atomicAdd(evcount,
+    atomicAdd(evcounts + p,
               nv * (unsigned long long)(wdone[0] + wdone[1] + wdone[2] + wdone[3]));
   }
 }
@@ -532,20 +559,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kFinBlock = 64;
 
-// ITEMS: partials per work item ([item][feature][kGroup], the items of source
-// group g are off[g] .. off[g+1]-1), summed by 4 waves per block (wave p
-// takes items p, p + 4, ...; the 4 sums are added in a fixed order);
-// otherwise per target chunk ([chunk][feature][N]), one wave per block.
+// ITEMS: partials per work item ([item][feature][kGroup]; the items of
+// source group g of problem p are its items off[g_off + p + g] ..
+// off[g_off + p + g + 1] - 1), summed by 4 waves per block (wave q takes items
+// q, q + 4, ...; the 4 sums are added in a fixed order); otherwise per target
+// chunk ([chunk][feature][N], one problem), one wave per block.  Block b
+// belongs to problem fin_slot[b]; its statistics go to the problem's
+// stat-major rows.
 template <bool ITEMS>
 __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
-    const float *__restrict__ X, int N, const float *__restrict__ w,
-    const DevState *__restrict__ st, const double *__restrict__ partial, int nsplit,
-    const int *__restrict__ off, double *__restrict__ blockstats, double *__restrict__ colS,
+    const Slot *__restrict__ slots, const int *__restrict__ fin_slot,
+    const DevState *__restrict__ states, const double *__restrict__ partial, int nsplit,
+    const int *__restrict__ offs, double *__restrict__ blockstats, double *__restrict__ colS,
     double *__restrict__ colstats) {
+  const int ps = fin_slot[blockIdx.x];
+  const DevState *st = states + ps;
   if (st->done) return;
+  const Slot &sl = slots[ps];
+  const int N = sl.N;
+  const float *X = sl.X;
+  const float *w = sl.w;
+  const int fb = blockIdx.x - sl.fin_off;
   const int l = threadIdx.x & (kFinBlock - 1);
   const int part = threadIdx.x / kFinBlock;  // 0 without ITEMS
-  const int n = blockIdx.x * kFinBlock + l;
+  const int n = fb * kFinBlock + l;
   double p = 0.0, W[6] = {0, 0, 0, 0, 0, 0}, B[3] = {0, 0, 0}, C = 0.0, lg = 0.0, outl = 0.0,
          logw = 0.0;
   double xt[4] = {0.0, 0.0, 0.0, 0.0};
@@ -556,8 +593,9 @@ __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
     if (n < N) {
       // this wave's items in increasing order, the loads of 4 issued together
       const int g = n / kGroup, j = n % kGroup;
-      const int i1 = off[g + 1];
-      int it = off[g] + part;
+      const int *off = offs + sl.g_off + ps;
+      const int i1 = sl.item_off + off[g + 1];
+      int it = sl.item_off + off[g] + part;
       for (; it + 12 < i1; it += 16) {
         double v[4][kFeatUsed];
 #pragma unroll
@@ -604,9 +642,9 @@ __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
     lg = log(den + gam);
     outl = gam * inv;
     logw = log(wn);
-    colS[n] = T[0];
+    if (colS) colS[sl.x_off + n] = T[0];
     if (colstats) {
-      double *cs = colstats + (size_t)n * kColStats;
+      double *cs = colstats + (size_t)(sl.x_off + n) * kColStats;
       cs[0] = T[0];
       cs[1] = den;
       cs[2] = p;
@@ -653,7 +691,7 @@ __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
   for (int i = threadIdx.x; i < kStats; i += blockDim.x) {
     double s = 0.0;
     for (int k = 0; k < kFinBlock; ++k) s += red[i][k];
-    blockstats[(size_t)i * gridDim.x + blockIdx.x] = s;  // stat-major
+    blockstats[(size_t)kStats * sl.fin_off + (size_t)i * sl.nfin + fb] = s;  // stat-major
   }
 }
 
@@ -843,48 +881,123 @@ __global__ __launch_bounds__(256) void moments_final(const double *__restrict__ 
 
 // ----------------------------------------------------------------- launchers
 
-EstepPlan estep_plan(int64_t N, int64_t M, int backend, int cull, int target_items) {
-  EstepPlan pl = {};
+BatchPlan batch_plan(int npairs, const int64_t *N, const int64_t *M, int backend, int cull,
+                     int target_items) {
+  BatchPlan pl;
   pl.backend = backend;
-  pl.nfin_blocks = (int)((N + kFinBlock - 1) / kFinBlock);
-  if (backend == kBackendScalar) {
-    pl.ngroups = (int)((N + kGroup - 1) / kGroup);
-    pl.ntiles = (int)((M + kCullTile - 1) / kCullTile);
-    // the live-tile lists take 4 bytes per (group, tile); beyond 2^28 of
-    // them (1 GiB) every pair is evaluated
-    pl.cull = cull && (int64_t)pl.ngroups * pl.ntiles <= ((int64_t)1 << 28);
-    pl.target_items = target_items >= 64 ? target_items : 8192;
+  pl.npairs = npairs;
+  pl.slots.resize(npairs);
+  double work = 0.0;
+  for (int p = 0; p < npairs; ++p) work += (double)N[p] * (double)M[p];
+  const int target = target_items >= 64 ? target_items : 8192;
+  for (int p = 0; p < npairs; ++p) {
+    Slot &sl = pl.slots[p];
+    sl = Slot{};
+    sl.N = (int32_t)N[p];
+    sl.M = (int32_t)M[p];
+    sl.x_off = pl.sources;
+    sl.y_off = pl.targets;
+    pl.sources += N[p];
+    pl.targets += M[p];
+    sl.ngroups = (int32_t)((N[p] + kGroup - 1) / kGroup);
+    sl.ntiles = (int32_t)((M[p] + kCullTile - 1) / kCullTile);
+    sl.g_off = (int32_t)pl.groups;
+    sl.t_off = (int32_t)pl.tiles;
+    sl.list_off = pl.list_ints;
+    pl.groups += sl.ngroups;
+    pl.tiles += sl.ntiles;
+    pl.list_ints += (int64_t)sl.ngroups * sl.ntiles;
+    // the problem's share of the work items, in proportion to M N;
     // sum_g ceil(count_g / L) < tiles / L + ngroups <= target + ngroups
-    pl.cap_items = pl.target_items + pl.ngroups;
-    return pl;
+    int64_t tp = (int64_t)((double)target * ((double)N[p] * (double)M[p]) / work + 0.5);
+    sl.target = (int32_t)(tp < 16 ? 16 : tp);
+    sl.item_cap = sl.target + sl.ngroups;
+    sl.item_off = (int32_t)pl.items;
+    pl.items += sl.item_cap;
+    sl.nfin = (int32_t)((N[p] + kFinBlock - 1) / kFinBlock);
+    sl.fin_off = (int32_t)pl.fins;
+    pl.fins += sl.nfin;
   }
-  // LDS and MFMA back ends: sources per block, target chunks (split-M)
-  const int64_t per_block = backend == kBackendLds ? (int64_t)kBlock * kPairS : (int64_t)kBlock;
-  pl.nsrc_blocks = (int)((N + per_block - 1) / per_block);
-  // about 1024 blocks (4096 waves) fill the 256 CUs; every split adds one
-  // FP64 partial per source and feature, so no more splits than that
-  const int64_t want = 1024;
-  int64_t ns = (want + pl.nsrc_blocks - 1) / pl.nsrc_blocks;
-  const int64_t maxs = (M + 127) / 128;
-  if (ns > maxs) ns = maxs;
-  if (ns > 64) ns = 64;
-  if (ns < 1) ns = 1;
-  int64_t chunk = (M + ns - 1) / ns;
-  chunk = (chunk + 3) / 4 * 4;
-  ns = (M + chunk - 1) / chunk;
-  pl.nsplit = (int)ns;
-  pl.mchunk = chunk;
+  // the live-tile lists take 4 bytes per (group, tile); beyond 2^28 of
+  // them (1 GiB) every pair is evaluated
+  pl.cull = backend == kBackendScalar && cull && pl.list_ints <= ((int64_t)1 << 28);
+  if (!pl.cull)
+    for (Slot &sl : pl.slots) sl.list_off = 0;
+  if (!pl.cull) pl.list_ints = 0;
+  pl.grp_slot.resize(pl.groups);
+  pl.item_slot.resize(backend == kBackendScalar ? pl.items : 0);
+  pl.fin_slot.resize(pl.fins);
+  for (int p = 0; p < npairs; ++p) {
+    const Slot &sl = pl.slots[p];
+    for (int g = 0; g < sl.ngroups; ++g) pl.grp_slot[sl.g_off + g] = p;
+    if (backend == kBackendScalar)
+      for (int i = 0; i < sl.item_cap; ++i) pl.item_slot[sl.item_off + i] = p;
+    for (int f = 0; f < sl.nfin; ++f) pl.fin_slot[sl.fin_off + f] = p;
+  }
+  if (backend != kBackendScalar) {
+    // LDS and MFMA back ends (one problem): sources per block, target chunks
+    const int64_t n = N[0], m = M[0];
+    const int64_t per_block = backend == kBackendLds ? (int64_t)kBlock * kPairS : (int64_t)kBlock;
+    pl.nsrc_blocks = (int)((n + per_block - 1) / per_block);
+    // about 1024 blocks (4096 waves) fill the 256 CUs; every split adds one
+    // FP64 partial per source and feature, so no more splits than that
+    const int64_t want = 1024;
+    int64_t ns = (want + pl.nsrc_blocks - 1) / pl.nsrc_blocks;
+    const int64_t maxs = (m + 127) / 128;
+    if (ns > maxs) ns = maxs;
+    if (ns > 64) ns = 64;
+    if (ns < 1) ns = 1;
+    int64_t chunk = (m + ns - 1) / ns;
+    chunk = (chunk + 3) / 4 * 4;
+    ns = (m + chunk - 1) / chunk;
+    pl.nsplit = (int)ns;
+    pl.mchunk = chunk;
+  }
   return pl;
 }
 
-size_t estep_partial_bytes(const EstepPlan &pl, int64_t N) {
-  if (pl.backend == kBackendScalar)
-    return (size_t)pl.cap_items * kFeatUsed * kGroup * sizeof(double);
-  return (size_t)pl.nsplit * kFeatUsed * (size_t)N * sizeof(double);
+namespace {
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+size_t batch_tables_bytes(const BatchPlan &pl) {
+  return align256(pl.slots.size() * sizeof(Slot)) + align256(pl.grp_slot.size() * sizeof(int)) +
+         align256(pl.item_slot.size() * sizeof(int)) + align256(pl.fin_slot.size() * sizeof(int));
 }
 
-// Work-item plan layout: CullHdr, evaluated-pair counter, counts[ngroups],
-// off[ngroups + 1], map[cap_items], gbox[ngroups][8], list[ngroups * ntiles].
+void batch_tables_pack(const BatchPlan &pl, std::vector<char> &host) {
+  host.assign(batch_tables_bytes(pl), 0);
+  char *p = host.data();
+  memcpy(p, pl.slots.data(), pl.slots.size() * sizeof(Slot));
+  p += align256(pl.slots.size() * sizeof(Slot));
+  memcpy(p, pl.grp_slot.data(), pl.grp_slot.size() * sizeof(int));
+  p += align256(pl.grp_slot.size() * sizeof(int));
+  if (!pl.item_slot.empty()) memcpy(p, pl.item_slot.data(), pl.item_slot.size() * sizeof(int));
+  p += align256(pl.item_slot.size() * sizeof(int));
+  memcpy(p, pl.fin_slot.data(), pl.fin_slot.size() * sizeof(int));
+}
+
+BatchDev batch_tables_view(const BatchPlan &pl, const void *dev) {
+  const char *p = (const char *)dev;
+  BatchDev d;
+  d.slots = (const Slot *)p;
+  p += align256(pl.slots.size() * sizeof(Slot));
+  d.grp_slot = (const int *)p;
+  p += align256(pl.grp_slot.size() * sizeof(int));
+  d.item_slot = (const int *)p;
+  p += align256(pl.item_slot.size() * sizeof(int));
+  d.fin_slot = (const int *)p;
+  return d;
+}
+
+size_t estep_partial_bytes(const BatchPlan &pl) {
+  if (pl.backend == kBackendScalar) return (size_t)pl.items * kFeatUsed * kGroup * sizeof(double);
+  return (size_t)pl.nsplit * kFeatUsed * (size_t)pl.slots[0].N * sizeof(double);
+}
+
+// Work-item plan layout: CullHdr[npairs], evaluated-pair counters[npairs],
+// counts[groups], off[groups + npairs], map[items], gbox[groups][8],
+// list[list_ints].
 namespace {
 struct PlanPtrs {
   CullHdr *hdr;
@@ -892,94 +1005,95 @@ struct PlanPtrs {
   int *counts, *off, *map, *list;
   double *gbox;
 };
-size_t align256(size_t b) { return (b + 255) / 256 * 256; }
-PlanPtrs plan_ptrs(const EstepPlan &pl, void *ws) {
+PlanPtrs plan_ptrs(const BatchPlan &pl, void *ws) {
   char *p = (char *)ws;
   PlanPtrs q;
   q.hdr = (CullHdr *)p;
-  p += align256(sizeof(CullHdr));
+  p += align256((size_t)pl.npairs * sizeof(CullHdr));
   q.evcount = (unsigned long long *)p;
-  p += 256;
+  p += align256((size_t)pl.npairs * sizeof(unsigned long long));
   q.counts = (int *)p;
-  p += align256((size_t)pl.ngroups * sizeof(int));
+  p += align256((size_t)pl.groups * sizeof(int));
   q.off = (int *)p;
-  p += align256((size_t)(pl.ngroups + 1) * sizeof(int));
+  p += align256((size_t)(pl.groups + pl.npairs) * sizeof(int));
   q.map = (int *)p;
-  p += align256((size_t)pl.cap_items * sizeof(int));
+  p += align256((size_t)pl.items * sizeof(int));
   q.gbox = (double *)p;
-  p += align256((size_t)pl.ngroups * 8 * sizeof(double));
+  p += align256((size_t)pl.groups * 8 * sizeof(double));
   q.list = (int *)p;
   return q;
 }
 }  // namespace
 
-size_t estep_plan_bytes(const EstepPlan &pl) {
+size_t estep_plan_bytes(const BatchPlan &pl) {
   if (pl.backend != kBackendScalar) return 256;
-  size_t b = align256(sizeof(CullHdr)) + 256 + align256((size_t)pl.ngroups * sizeof(int)) +
-             align256((size_t)(pl.ngroups + 1) * sizeof(int)) +
-             align256((size_t)pl.cap_items * sizeof(int)) +
-             align256((size_t)pl.ngroups * 8 * sizeof(double));
-  if (pl.cull) b += (size_t)pl.ngroups * pl.ntiles * sizeof(int);
-  return b;
+  return align256((size_t)pl.npairs * sizeof(CullHdr)) +
+         align256((size_t)pl.npairs * sizeof(unsigned long long)) +
+         align256((size_t)pl.groups * sizeof(int)) +
+         align256((size_t)(pl.groups + pl.npairs) * sizeof(int)) +
+         align256((size_t)pl.items * sizeof(int)) +
+         align256((size_t)pl.groups * 8 * sizeof(double)) + (size_t)pl.list_ints * sizeof(int);
 }
 
-unsigned long long *estep_plan_counter(const EstepPlan &pl, void *plan_ws) {
+unsigned long long *estep_plan_counter(const BatchPlan &pl, void *plan_ws) {
   return pl.backend == kBackendScalar ? plan_ptrs(pl, plan_ws).evcount : nullptr;
 }
 
-hipError_t launch_estep_plan(const EstepPlan &pl, const float *X, int64_t N, const TBox *boxes,
+hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox *boxes,
                              DevState *s, void *plan_ws, hipStream_t st) {
   if (pl.backend != kBackendScalar) return hipSuccess;
   const PlanPtrs q = plan_ptrs(pl, plan_ws);
   if (pl.cull) {
-    hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.ngroups), dim3(kBlock), 0, st, X, (int)N, s,
-                       boxes, pl.ntiles, q.counts, q.gbox, q.list);
-    hipLaunchKernelGGL(cull_items<true>, dim3(1), dim3(kBlock), 0, st, s, q.counts, pl.ngroups,
-                       pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off, q.map, q.evcount);
+    hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.groups), dim3(kBlock), 0, st, bd.slots,
+                       bd.grp_slot, s, boxes, q.counts, q.gbox, q.list);
+    hipLaunchKernelGGL(cull_items<true>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st, bd.slots,
+                       s, q.counts, q.hdr, q.off, q.map, q.evcount);
   } else {
-    hipLaunchKernelGGL(cull_items<false>, dim3(1), dim3(kBlock), 0, st, s, q.counts, pl.ngroups,
-                       pl.ntiles, pl.target_items, pl.cap_items, q.hdr, q.off, q.map, q.evcount);
+    hipLaunchKernelGGL(cull_items<false>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st,
+                       bd.slots, s, q.counts, q.hdr, q.off, q.map, q.evcount);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_estep_pairs(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
-                              const TPt *pts, int64_t M, DevState *s, void *plan_ws,
-                              double *partial, hipStream_t st) {
+hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRec *rec,
+                              const TPt *pts, DevState *s, void *plan_ws, double *partial,
+                              hipStream_t st) {
   if (pl.backend == kBackendScalar) {
     const PlanPtrs q = plan_ptrs(pl, plan_ws);
     if (pl.cull)
-      hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.cap_items), dim3(kBlock), 0,
-                         st, X, (int)N, rec, pts, M, s, q.hdr, q.counts, q.off, q.map, q.list,
-                         q.gbox, pl.ntiles, q.evcount, partial);
+      hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
+                         bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
+                         q.list, q.gbox, q.evcount, partial);
     else
-      hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.cap_items), dim3(kBlock), 0,
-                         st, X, (int)N, rec, pts, M, s, q.hdr, q.counts, q.off, q.map, q.list,
-                         q.gbox, pl.ntiles, q.evcount, partial);
+      hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
+                         bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
+                         q.list, q.gbox, q.evcount, partial);
     return hipGetLastError();
   }
+  // one problem: its records start at rec + 0
+  const Slot &sl = pl.slots[0];
   dim3 grid((unsigned)(pl.nsrc_blocks * pl.nsplit));
   if (pl.backend == kBackendMfma)
-    hipLaunchKernelGGL(estep_mfma, grid, dim3(kBlock), 0, st, X, (int)N, rec, M, s, pl.mchunk,
-                       pl.nsplit, partial);
-  else
-    hipLaunchKernelGGL(estep_pairs_lds<kPairS>, grid, dim3(kBlock), 0, st, X, (int)N, rec, M, s,
+    hipLaunchKernelGGL(estep_mfma, grid, dim3(kBlock), 0, st, sl.X, sl.N, rec, (int64_t)sl.M, s,
                        pl.mchunk, pl.nsplit, partial);
+  else
+    hipLaunchKernelGGL(estep_pairs_lds<kPairS>, grid, dim3(kBlock), 0, st, sl.X, sl.N, rec,
+                       (int64_t)sl.M, s, pl.mchunk, pl.nsplit, partial);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const float *w,
-                           const DevState *s, const void *plan_ws, const double *partial,
-                           double *blockstats, double *colS, double *colstats, hipStream_t st) {
+hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
+                           const void *plan_ws, const double *partial, double *blockstats,
+                           double *colS, double *colstats, hipStream_t st) {
   if (pl.backend == kBackendScalar)
-    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.nfin_blocks), dim3(4 * kFinBlock), 0,
-                       st, X, (int)N, w, s, partial, 0,
+    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.fins), dim3(4 * kFinBlock), 0, st,
+                       bd.slots, bd.fin_slot, s, partial, 0,
                        (const int *)plan_ptrs(pl, (void *)plan_ws).off, blockstats, colS,
                        colstats);
   else
-    hipLaunchKernelGGL(estep_finalize<false>, dim3((unsigned)pl.nfin_blocks), dim3(kFinBlock), 0,
-                       st, X, (int)N, w, s, partial, pl.nsplit, (const int *)nullptr, blockstats,
-                       colS, colstats);
+    hipLaunchKernelGGL(estep_finalize<false>, dim3((unsigned)pl.fins), dim3(kFinBlock), 0, st,
+                       bd.slots, bd.fin_slot, s, partial, pl.nsplit, (const int *)nullptr,
+                       blockstats, colS, colstats);
   return hipGetLastError();
 }
 

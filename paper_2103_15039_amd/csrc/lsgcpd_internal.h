@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 namespace lsg {
@@ -121,55 +123,87 @@ constexpr int kBackendLds = 1;     // target records staged in LDS
 constexpr int kBackendMfma = 2;    // FP64 matrix-core accumulation
 constexpr int kPairS = 2;          // sources per thread in the LDS back end
 
-struct EstepPlan {
-  int backend;
-  // scalar back end (work items over live tiles)
-  int cull;          // drop target tiles whose exponentials are all exact zeros
-  int ngroups;       // source groups of 256
-  int ntiles;        // target tiles of kCullTile records
-  int target_items;  // about this many work items per E step
-  int cap_items;     // upper bound on the work items (grid of the pair kernel)
-  // LDS and MFMA back ends (target chunks)
-  int nsplit;        // target chunks
-  int64_t mchunk;    // targets per chunk
-  int nsrc_blocks;   // source blocks of the accumulation kernel
-  int nfin_blocks;   // blocks of the finalisation kernel
+// One registration problem of a batch, as the kernels see it (a table in
+// device memory; the single-pair calls are batches of one).
+struct Slot {
+  const float *X;   // sources, N x 3 (Morton order when culled)
+  const float *w;   // per-source weights, or null (then w0 of the state)
+  int64_t x_off;    // first source in the batch numbering (colS, colstats)
+  int64_t y_off;    // first target in the packed positions; records start at y_off + slot
+  int64_t list_off; // live-tile lists of the problem: ngroups x ntiles ints
+  int32_t N, M;
+  int32_t g_off, ngroups;            // source groups of kGroup (kernel-side constant)
+  int32_t t_off, ntiles;             // target tiles of kCullTile
+  int32_t item_off, item_cap, target;  // work items (scalar back end)
+  int32_t fin_off, nfin;             // finalisation blocks
+  int32_t pad;
 };
 
-// Written on the device by each E step of the scalar back end.
+// Host-side plan of one E step over a batch, with the tables the kernels
+// index: the problem of every source group, work item and finalisation block.
+struct BatchPlan {
+  int backend = 0;
+  int cull = 0;        // drop target tiles whose exponentials are all exact zeros
+  int npairs = 0;
+  int64_t groups = 0, tiles = 0, items = 0, fins = 0, list_ints = 0;
+  int64_t sources = 0, targets = 0;
+  std::vector<Slot> slots;
+  std::vector<int> grp_slot, item_slot, fin_slot;
+  // LDS and MFMA back ends (one problem): target chunks
+  int nsplit = 0;
+  int64_t mchunk = 0;
+  int nsrc_blocks = 0;
+};
+
+// Device copies of the tables (one buffer, see batch_tables_*).
+struct BatchDev {
+  const Slot *slots;
+  const int *grp_slot, *item_slot, *fin_slot;
+};
+
+// Written on the device by each E step of the scalar back end, per problem.
 struct CullHdr {
-  int items;           // work items of the pair kernel
+  int items;           // work items of the problem
   int tiles_per_item;
 };
 
-EstepPlan estep_plan(int64_t N, int64_t M, int backend, int cull, int target_items);
-size_t estep_partial_bytes(const EstepPlan &pl, int64_t N);
+// Plans a batch of sizes N[p], M[p]: work items about target_items in all,
+// shared in proportion to M N.  The caller sets slots[p].X and .w.
+BatchPlan batch_plan(int npairs, const int64_t *N, const int64_t *M, int backend, int cull,
+                     int target_items);
+size_t batch_tables_bytes(const BatchPlan &pl);
+// Packs the tables for one host-to-device copy and returns the device view of
+// a buffer at `dev` holding that copy.
+void batch_tables_pack(const BatchPlan &pl, std::vector<char> &host);
+BatchDev batch_tables_view(const BatchPlan &pl, const void *dev);
 
-// Device workspace of the work-item plan, and the counter of evaluated pairs
-// inside it (scalar back end; null otherwise).
-size_t estep_plan_bytes(const EstepPlan &pl);
-unsigned long long *estep_plan_counter(const EstepPlan &pl, void *plan_ws);
+size_t estep_partial_bytes(const BatchPlan &pl);
+// Device workspace of the work-item plan, and the per-problem counters of
+// evaluated pairs inside it (scalar back end; null otherwise).
+size_t estep_plan_bytes(const BatchPlan &pl);
+unsigned long long *estep_plan_counter(const BatchPlan &pl, void *plan_ws);
 
 // The work-item plan of the scalar back end (no-op for the others), then the
-// pair kernel.
-hipError_t launch_estep_plan(const EstepPlan &pl, const float *X, int64_t N, const TBox *boxes,
+// pair kernel, then the per-source finalisation into stat-major block rows
+// (problem p: rows at kStats * fin_off, nfin per row).
+hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox *boxes,
                              DevState *s, void *plan_ws, hipStream_t st);
-hipError_t launch_estep_pairs(const EstepPlan &pl, const float *X, int64_t N, const TRec *rec,
-                              const TPt *pts, int64_t M, DevState *s, void *plan_ws,
-                              double *partial, hipStream_t st);
-hipError_t launch_finalize(const EstepPlan &pl, const float *X, int64_t N, const float *w,
-                           const DevState *s, const void *plan_ws, const double *partial,
-                           double *blockstats, double *colS, double *colstats, hipStream_t st);
+hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRec *rec,
+                              const TPt *pts, DevState *s, void *plan_ws, double *partial,
+                              hipStream_t st);
+hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
+                           const void *plan_ws, const double *partial, double *blockstats,
+                           double *colS, double *colstats, hipStream_t st);
 hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, const float *w,
                          const DevState *s, const double *colS, float *P, hipStream_t st);
 
-// Reduce the block statistics and run the M step.  mode 0: derive only
-// (gradient, Hessian, next pose into the *_next fields); mode 1: EM update of
-// the state (pose, sigma2, iteration, convergence).
-// evcount (may be null): pairs the pair kernel evaluated, added to
-// s->evaluated_pairs.
-hipError_t launch_reduce_mstep(double *blockstats, int nblk, int64_t N, DevState *s,
-                               double *nll_trace, const unsigned long long *evcount, int mode,
-                               hipStream_t st);
+// Reduce the block statistics and run the M step of every problem.  mode 0:
+// derive only (gradient, Hessian, next pose into the *_next fields); mode 1:
+// EM update of the state (pose, sigma2, iteration, convergence).  nll_trace:
+// null or trace_stride doubles per problem.  evcounts (may be null): pairs the
+// pair kernel evaluated, added to s[p].evaluated_pairs.
+hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *blockstats,
+                               DevState *s, double *nll_trace, int trace_stride,
+                               const unsigned long long *evcounts, int mode, hipStream_t st);
 
 }  // namespace lsg

@@ -12,10 +12,10 @@
 // steps are halved until D does not grow beyond a rounding allowance (the
 // change of D is evaluated as the exact difference of the quadratic).  After
 // the pose, sigma^2 = D(G_new) / (3 N_P) (Sec. 3.5, last paragraph).
-// reduce_stats sums the block statistics with one block per statistic;
-// reduce_mstep runs the Newton iteration in one block, whose threads share
-// the 12 x 12 products while thread 0 does the 6 x 6 Cholesky solve and the
-// exponential map.
+// reduce_stats sums the block statistics with one block per statistic and
+// problem; reduce_mstep runs the Newton iteration of each problem of a batch
+// in one block, whose threads share the 12 x 12 products while thread 0 does
+// the 6 x 6 Cholesky solve and the exponential map.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -145,15 +145,18 @@ __device__ double block_quad(MSh &m, const double *v, double *rowbuf) {
   return tot;
 }
 
-// Sum of row i of the stat-major block statistics (one block per statistic,
-// so that the reads are spread over many CUs): thread t adds the partials
-// t, t + 256, ... in order, then a fixed tree adds the threads.  The result
-// does not depend on timing.
-__global__ __launch_bounds__(256) void reduce_stats(const double *__restrict__ blockstats,
-                                                     int nblk, DevState *__restrict__ s) {
+// Sum of row i of a problem's stat-major block statistics (one block per
+// statistic and problem, so that the reads are spread over many CUs): thread
+// t adds the partials t, t + 256, ... in order, then a fixed tree adds the
+// threads.  The result does not depend on timing.
+__global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slots,
+                                                     const double *__restrict__ blockstats,
+                                                     DevState *__restrict__ states) {
+  const int p = blockIdx.x / kStats, i = blockIdx.x % kStats, tid = threadIdx.x;
+  DevState *s = states + p;
   if (s->done) return;
-  const int i = blockIdx.x, tid = threadIdx.x;
-  const double *row = blockstats + (size_t)i * nblk;
+  const int nblk = slots[p].nfin;
+  const double *row = blockstats + (size_t)kStats * slots[p].fin_off + (size_t)i * nblk;
   double a = 0.0;
   for (int c0 = 0; c0 < nblk; c0 += 8 * 256) {
     double v[8];
@@ -176,12 +179,17 @@ __global__ __launch_bounds__(256) void reduce_stats(const double *__restrict__ b
 }
 
 // The M step from the 86 statistics in s->stats.
-__global__ __launch_bounds__(256) void reduce_mstep(int N, DevState *__restrict__ s,
-                                                    double *__restrict__ trace,
-                                                    const unsigned long long *__restrict__ evcount,
+__global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slots,
+                                                    DevState *__restrict__ states,
+                                                    double *__restrict__ traces, int trace_stride,
+                                                    const unsigned long long *__restrict__ evcounts,
                                                     int mode) {
+  const int pidx = blockIdx.x;
+  DevState *s = states + pidx;
   if (s->done) return;
-  if (evcount && threadIdx.x == 0) s->evaluated_pairs += (int64_t)*evcount;
+  const int N = slots[pidx].N;
+  double *trace = traces ? traces + (size_t)pidx * trace_stride : nullptr;
+  if (evcounts && threadIdx.x == 0) s->evaluated_pairs += (int64_t)evcounts[pidx];
   __shared__ double S[kStats];
   __shared__ MSh m;
   __shared__ double rowbuf[12];
@@ -429,12 +437,13 @@ __global__ void init_state(DevState *__restrict__ s, const double *__restrict__ 
 
 }  // namespace
 
-hipError_t launch_reduce_mstep(double *blockstats, int nblk, int64_t N, DevState *s,
-                               double *nll_trace, const unsigned long long *evcount, int mode,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_stats, dim3(kStats), dim3(256), 0, st, blockstats, nblk, s);
-  hipLaunchKernelGGL(reduce_mstep, dim3(1), dim3(256), 0, st, (int)N, s, nll_trace, evcount,
-                     mode);
+hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *blockstats,
+                               DevState *s, double *nll_trace, int trace_stride,
+                               const unsigned long long *evcounts, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_stats, dim3((unsigned)(kStats * pl.npairs)), dim3(256), 0, st,
+                     bd.slots, blockstats, s);
+  hipLaunchKernelGGL(reduce_mstep, dim3((unsigned)pl.npairs), dim3(256), 0, st, bd.slots, s,
+                     nll_trace, trace_stride, evcounts, mode);
   return hipGetLastError();
 }
 

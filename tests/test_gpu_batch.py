@@ -1,0 +1,96 @@
+"""GPU parity of batched registration (lsgcpd_register_batch): every pair of
+a batch against the same pair registered alone, and against the FP64 oracle
+on small pairs.
+
+Bar: against the single-pair call, the same iterations and convergence, and
+poses and sigma^2 equal up to the grouping of the sums (rotation <= 1e-6 deg,
+translation <= 1e-8 x box diagonal, sigma^2 and NLL 1e-9 relative); against
+the oracle the registration bar of test_gpu_register (rotation <= 1e-3 deg,
+translation <= 1e-5 x diagonal, same iterations).
+"""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import lsgcpd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2103_15039_amd")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _pairs(sizes, seed):
+    rng = datagen.rng_for(7, seed)
+    return [datagen.scene_pair(rng, M, N, max_angle_deg=25.0) for M, N in sizes]
+
+
+def _close(b, s, diag, tight=True):
+    assert b.iters == s.iters and b.converged == s.converged
+    rot = O.rotation_error_deg(b.R, s.R)
+    assert rot <= (1e-6 if tight else 1e-3)
+    assert O.translation_error(b.t, s.t) <= (1e-8 if tight else 1e-5) * diag
+    np.testing.assert_allclose(b.sigma2, s.sigma2, rtol=1e-9 if tight else 1e-3)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_batch_matches_single_pairs(dense):
+    # uneven sizes incl. a tiny pair, ragged tails and M < 64 / N < 128
+    sizes = [(37, 53), (2100, 1700), (600, 3100), (50, 120), (4999, 257), (1, 1)]
+    sizes[-1] = (12, 9)
+    pairs = _pairs(sizes, 1)
+    kw = dict(k=8, max_iter=30)
+    res = L.register_batch([(dev(p.X), dev(p.Y)) for p in pairs], dense=dense, **kw)
+    for p, b in zip(pairs, res):
+        s = L.register(dev(p.X), dev(p.Y), backend="dense" if dense else "scalar", **kw)
+        _close(b, s, O.bbox_diag(p.Y))
+        np.testing.assert_allclose(b.nll, [s.nll[0], s.nll[-1]], rtol=1e-9)
+
+
+def test_batch_tolerance_stop_and_initial_poses():
+    pairs = _pairs([(800, 700), (1500, 1200), (300, 400)], 2)
+    rng = np.random.default_rng(5)
+    init = [(datagen.random_rotation(rng, 0.1), rng.uniform(-0.01, 0.01, 3)) for _ in pairs]
+    kw = dict(k=10, max_iter=80, tol=1e-7)
+    res = L.register_batch([(dev(p.X), dev(p.Y)) for p in pairs], init=init, **kw)
+    for p, (R0, t0), b in zip(pairs, init, res):
+        s = L.register(dev(p.X), dev(p.Y), R0=R0, t0=t0, **kw)
+        assert s.converged and s.iters < 80
+        _close(b, s, O.bbox_diag(p.Y))
+
+
+def test_batch_against_oracle():
+    pairs = _pairs([(500, 450), (350, 600)], 3)
+    res = L.register_batch([(dev(p.X), dev(p.Y)) for p in pairs], k=10, max_iter=30)
+    for p, b in zip(pairs, res):
+        o = O.register(p.X, p.Y, k=10, max_iter=30)
+        assert b.iters == o.iters
+        assert O.rotation_error_deg(b.R, o.R) <= 1e-3
+        assert O.translation_error(b.t, o.t) <= 1e-5 * O.bbox_diag(p.Y)
+        assert b.sigma2 == pytest.approx(o.sigma2, rel=1e-3)
+
+
+def test_batch_deterministic_and_many_pairs():
+    pairs = datagen.batch_pairs(24, trial=9, nmin=200, nmax=3000)
+    args = [(dev(p.X), dev(p.Y)) for p in pairs]
+    a = L.register_batch(args, k=10, max_iter=20)
+    b = L.register_batch(args, k=10, max_iter=20)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.R, y.R) and np.array_equal(x.t, y.t) and x.sigma2 == y.sigma2
+    # each pair's result is the single-pair result
+    for p, x in zip(pairs[:6], a[:6]):
+        s = L.register(dev(p.X), dev(p.Y), k=10, max_iter=20)
+        _close(x, s, O.bbox_diag(p.Y))
+
+
+def test_batch_invalid_arguments():
+    p = _pairs([(100, 100)], 4)[0]
+    with pytest.raises(ValueError):
+        L.register_batch([])
+    with pytest.raises(L.LsgcpdError) as ei:
+        L.register_batch([(dev(p.X), dev(p.Y)), (dev(p.X), dev(p.Y[:5]))], k=10)
+    assert ei.value.status == L.E_INVALID
