@@ -241,20 +241,37 @@ lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t
                              float *alpha, hipStream_t st) {
   HIPCHK(lsg::launch_normals(Y, M, (const float4 *)ctx->ys4.p + off,
                              (const uint32_t *)ctx->yperm.p + off, k, alpha_max, lambda, normals,
-                             kappa, alpha, ctx->knn.p, st));
+                             kappa, alpha, ctx->knn.p, ctx->knn.cap, st));
   return LSGCPD_OK;
 }
 
-// Workspace shared by the target sort and the neighbour search of clouds of
-// at most `nmax` points (k neighbours), and the sorted copies of `mtot`
-// targets.
-lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int64_t nmax, int64_t mmax, int64_t mtot, int k) {
-  ENSURE(order, lsg::morton_workspace_bytes(nmax));
+// Workspace of the Morton sorts and moments of the npairs clouds of N[i]
+// sources (N may be null) and M[i] targets, of the neighbour search (k
+// neighbours) over each target cloud, and the sorted copies of `mtot`
+// targets.  The sort and search workspaces are maxima over the clouds, not
+// the workspace of the largest cloud: the number of target splits of the
+// search falls as M grows, and so may the sort's scratch.
+lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int npairs, const int64_t *N, const int64_t *M,
+                              int64_t mtot, int k) {
+  size_t ob = 0, kb = 0;
+  int64_t nmax = 1;
+  for (int i = 0; i < npairs; ++i) {
+    const int64_t n = N ? N[i] : 0;
+    const size_t a = lsg::morton_workspace_bytes(M[i]);
+    const size_t b = n > 0 ? lsg::morton_workspace_bytes(n) : 0;
+    const size_t c = lsg::knn_workspace_bytes(M[i], k);
+    ob = a > ob ? a : ob;
+    ob = b > ob ? b : ob;
+    kb = c > kb ? c : kb;
+    nmax = M[i] > nmax ? M[i] : nmax;
+    nmax = n > nmax ? n : nmax;
+  }
+  ENSURE(order, ob);
   ENSURE(mom_part, (size_t)lsg::moments_blocks(nmax) * 10 * sizeof(double));
   ENSURE(mom, 48 * sizeof(double));
   ENSURE(yperm, (size_t)mtot * sizeof(uint32_t));
   ENSURE(ys4, (size_t)mtot * sizeof(float4));
-  ENSURE(knn, lsg::knn_workspace_bytes(mmax, k));
+  ENSURE(knn, kb);
   return LSGCPD_OK;
 }
 
@@ -360,12 +377,7 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
     return fail(ctx, LSGCPD_E_UNSUPPORTED, "batches use the default pair kernel only");
   lsg::BatchPlan pl =
       lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1, work_items());
-  int64_t nmax = 1, mmax = 1;
-  for (int i = 0; i < npairs; ++i) {
-    nmax = N[i] > nmax ? N[i] : nmax;
-    mmax = M[i] > mmax ? M[i] : mmax;
-  }
-  RETURN_IF(ensure_geometry(ctx, nmax > mmax ? nmax : mmax, mmax, pl.targets, p->k));
+  RETURN_IF(ensure_geometry(ctx, npairs, N, M, pl.targets, p->k));
   ENSURE(nrm, (size_t)pl.targets * 3 * sizeof(float));
   ENSURE(kap, (size_t)pl.targets * sizeof(float));
   ENSURE(alp, (size_t)pl.targets * sizeof(float));
@@ -537,7 +549,7 @@ LSG_API lsgcpd_status lsgcpd_normals(lsgcpd_ctx *ctx, const float *Y, int64_t M,
   if (!finite_pos(lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
-  RETURN_IF(ensure_geometry(ctx, M, M, M, k));
+  RETURN_IF(ensure_geometry(ctx, 1, nullptr, &M, M, k));
   RETURN_IF(sort_targets(ctx, Y, M, 0, st));
   return normals_sorted(ctx, Y, M, 0, k, alpha_max, lambda, normals, kappa, alpha, st);
 }

@@ -534,7 +534,8 @@ size_t knn_workspace_bytes(int64_t M, int k) {
 
 hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uint32_t *perm,
                           int k, double alpha_max, double lambda, float *normals, float *kappa,
-                          float *alpha, void *work, hipStream_t st) {
+                          float *alpha, void *work, size_t work_bytes, hipStream_t st) {
+  if (knn_workspace_bytes(M, k) > work_bytes) return hipErrorInvalidValue;
   const int Mi = (int)M;
   const int ntiles = (int)((M + kKnnTileW - 1) / kKnnTileW);
   const int S = knn_splits(M, k);

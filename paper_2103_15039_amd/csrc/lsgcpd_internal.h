@@ -85,7 +85,7 @@ struct DevState {
 size_t knn_workspace_bytes(int64_t M, int k);
 hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uint32_t *perm,
                           int k, double alpha_max, double lambda, float *normals, float *kappa,
-                          float *alpha, void *work, hipStream_t st);
+                          float *alpha, void *work, size_t work_bytes, hipStream_t st);
 
 // Bounding box and first/second moments of a cloud, optionally after the
 // state's pose: out[0..2]=sum x', out[3]=sum |x'|^2, out[4..6]=min, out[7..9]=max.

@@ -80,6 +80,7 @@ hipError_t launch_morton_order(const float *P, int64_t n, const double *box, voi
   uint32_t *idx_in = code_out + n;
   uint32_t *idx_out = idx_in + n;
   void *tmp = (void *)(idx_out + n);
+  if (work_bytes < morton_workspace_bytes(n)) return hipErrorInvalidValue;
   size_t tmp_bytes = work_bytes - 4 * (size_t)n * sizeof(uint32_t);
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(morton_codes, dim3(blocks), dim3(256), 0, st, P, (int)n, box, code_in,

@@ -51,6 +51,18 @@ def test_batch_matches_single_pairs(dense):
         np.testing.assert_allclose(b.nll, [s.nll[0], s.nll[-1]], rtol=1e-9)
 
 
+def test_batch_mixed_target_sizes_share_the_search_workspace():
+    # The neighbour-search workspace is not monotone in M (fewer target splits
+    # for larger clouds): a 20,000-point target needs more of it than a
+    # 30,000-point one at k = 10, so the batch must size it over all pairs.
+    pairs = _pairs([(30000, 300), (20000, 300), (12000, 200)], 4)
+    kw = dict(k=10, max_iter=8)
+    res = L.register_batch([(dev(p.X), dev(p.Y)) for p in pairs], **kw)
+    for p, b in zip(pairs, res):
+        s = L.register(dev(p.X), dev(p.Y), **kw)
+        _close(b, s, O.bbox_diag(p.Y))
+
+
 def test_batch_tolerance_stop_and_initial_poses():
     pairs = _pairs([(800, 700), (1500, 1200), (300, 400)], 2)
     rng = np.random.default_rng(5)
