@@ -171,9 +171,10 @@ def _room_scene(rng):
     return lo, hi, boxes, quads
 
 
-def _render_depth(rng, scene, Rc, tc):
+def _render_depth(rng, scene, Rc, tc, noise=(0.0, 0.002, 0.0)):
     """Render the scene from a pinhole camera (camera-to-world Rc, tc; camera
-    looks along +z).  Returns camera-frame points, one per pixel."""
+    looks along +z).  Returns camera-frame points, one per pixel, with depth
+    noise N(0, s(z)^2), s(z) = noise[0] + noise[1] z + noise[2] z^2."""
     lo, hi, boxes, quads = scene
     u, v = np.meshgrid(np.arange(_W), np.arange(_H))
     dc = np.stack([(u.ravel() - _CX) / _F, (v.ravel() - _CY) / _F, np.ones(u.size)], axis=1)
@@ -185,7 +186,7 @@ def _render_depth(rng, scene, Rc, tc):
     for (c, uu, vv, hu, hv) in quads:
         t = np.minimum(t, _hit_quad(o, dw, c, uu, vv, hu, hv))
     z = t  # dc has unit z component, so the ray parameter is the depth
-    z = z + rng.normal(size=z.shape) * (0.002 * z)
+    z = z + rng.normal(size=z.shape) * (noise[0] + noise[1] * z + noise[2] * z * z)
     return dc * z[:, None]
 
 
@@ -213,6 +214,36 @@ def rgbd_pair(trial=0, outlier_frac=0.05, angle_deg=15.0, trans=0.05):
     t_gt = R1.T @ (t2 - t1)
     return Pair(X=X.astype(np.float32), Y=Y.astype(np.float32), R_gt=R_gt, t_gt=t_gt,
                 name="rgbd_20000x20000")
+
+
+# Depth noise of depth_pair: standard deviation c0 + c1 z + c2 z^2 metres at
+# depth z, over a sensor range of 0.4-6.5 m; its smallest value in that range
+# is the one at 0.4 m.
+DEPTH_ERROR = (1.0e-3, 0.0, 1.5e-3)
+DEPTH_ERROR_MIN = 1.24e-3
+
+
+def depth_pair(trial=0, M=20000, N=20000, outlier_frac=0.02, angle_deg=10.0, trans=0.05):
+    """Two depth frames of one random room (as rgbd_pair) whose depth noise
+    grows with the square of the depth (DEPTH_ERROR), the setting of the
+    paper's confidence filtering (Sec. 3.3); M and N of the 20,000 pixels of
+    each frame are kept at random, 2 % of them replaced by uniform samples in
+    the cloud's box.  Each cloud is in its own camera frame (depth = z)."""
+    rng = rng_for(4, trial)
+    scene = _room_scene(rng)
+    R2 = random_rotation(rng, math.radians(angle_deg))
+    t2 = trans * random_unit(rng)
+    clouds = []
+    for (Rc, tc), n in (((np.eye(3), np.zeros(3)), M), ((R2, t2), N)):
+        P = _render_depth(rng, scene, Rc, tc, noise=DEPTH_ERROR)
+        P = P[rng.choice(P.shape[0], size=n, replace=False)]
+        n_out = int(round(outlier_frac * n))
+        idx = rng.choice(n, size=n_out, replace=False)
+        P[idx] = rng.uniform(P.min(axis=0), P.max(axis=0), size=(n_out, 3))
+        clouds.append(P)
+    Y, X = clouds
+    return Pair(X=X.astype(np.float32), Y=Y.astype(np.float32), R_gt=R2, t_gt=t2,
+                name=f"depth_{M}x{N}")
 
 
 # ---------------------------------------------------------------------------

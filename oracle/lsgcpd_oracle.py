@@ -497,6 +497,67 @@ def mstep(cols, X, R, t, sigma2, newton_max=20, sigma2_floor=0.0):
 
 
 # ----------------------------------------------------------------------------
+# Outlier weight from the outlier ratio (Sec. 3.2), confidence filtering (Sec. 3.3)
+# ----------------------------------------------------------------------------
+
+def component_peak(alpha, sigma2, exact_normalizer=False):
+    """c_m: the largest value of the component density p(x|m) of Eq. (2), i.e.
+    its value at x = y_m.  With the normaliser the E step uses (Eq. 9) this is
+    (2 pi sigma^2)^{-3/2} for every m; with exact_normalizer it is the true
+    Gaussian's sqrt(det Sigma_m^{-1}) / (2 pi)^{3/2} = sqrt(1 + alpha_m) (2 pi
+    sigma^2)^{-3/2} (reading: c_m is taken for the same density the E step
+    evaluates, so that p(x|m) <= c_m holds for it)."""
+    a = _f64(alpha)
+    c = np.full(a.shape, (2.0 * math.pi * sigma2) ** -1.5)
+    if exact_normalizer:
+        c = c * np.sqrt(1.0 + a)
+    return c
+
+
+def outlier_weight_max(eta, V, pi, alpha, sigma2, exact_normalizer=False):
+    """Sec. 3.2: the largest uniform outlier weight consistent with an expected
+    outlier count of eta N, w_max = eta V S / ((1 - eta) + eta V S) with
+    S = sum_m pi(m) c_m.  c_m depends on sigma^2, so w_max does too; register
+    evaluates it once, at the initial sigma^2, and keeps w0 fixed (reading:
+    re-evaluating it as sigma^2 shrinks would drive w0 towards 1, the regime
+    Sec. 3.2 warns against).  pi None => uniform 1/M.  Requires 0 <= eta < 1."""
+    if not (0.0 <= eta < 1.0):
+        raise ValueError("eta must lie in [0, 1)")
+    a = _f64(alpha)
+    pi = np.full(a.shape, 1.0 / a.shape[0]) if pi is None else _f64(pi)
+    S = float(np.sum(pi * component_peak(a, sigma2, exact_normalizer)))
+    return eta * V * S / ((1.0 - eta) + eta * V * S)
+
+
+def depth_confidence(P, coef, e_min):
+    """Sec. 3.3: measurement confidence phi(x) = e_min / e(x) of a point seen by
+    a depth sensor, with the error model e(x) = c0 + c1 z + c2 z^2 of its depth
+    z = x_3 in the sensor frame.  The paper leaves the model to the sensor;
+    this quadratic-in-depth form is the reading.  Points whose modelled error
+    is below e_min (outside the range e_min was taken over) get phi = 1."""
+    z = _f64(P)[:, 2]
+    c0, c1, c2 = (float(c) for c in coef)
+    e = c0 + c1 * z + c2 * z * z
+    return np.minimum(1.0, float(e_min) / e)
+
+
+def confidence_priors(phi_y, phi_x, w0):
+    """Sec. 3.3 (confidence filtering): component priors
+    pi(m) = phi(y_m) / sum_m phi(y_m) and outlier weights
+    w_n = 1 - (1 - w0) phi(x_n).  Either side may be None (uniform)."""
+    pi = None if phi_y is None else _f64(phi_y) / float(np.sum(_f64(phi_y)))
+    w = None if phi_x is None else 1.0 - (1.0 - float(w0)) * _f64(phi_x)
+    return pi, w
+
+
+def truncate(P, phi, threshold):
+    """Sec. 3.3: the points whose confidence is at least `threshold`, in their
+    original order, with their confidences."""
+    keep = _f64(phi) >= float(threshold)
+    return np.asarray(P)[keep], np.asarray(phi)[keep]
+
+
+# ----------------------------------------------------------------------------
 # EM driver
 # ----------------------------------------------------------------------------
 
@@ -514,18 +575,27 @@ class Registration:
     normals: np.ndarray | None = None
     alpha: np.ndarray | None = None
     V: float = 0.0
+    N: int = 0                                    # points used (after truncation)
+    M: int = 0
+    w0: float = 0.0                               # uniform outlier weight used
 
 
 def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=50, tol=0.0,
              R0=None, t0=None, sigma2_0=None, V=None, newton_max=20,
              exact_normalizer=False, target_normals=None, target_alpha=None,
-             estep_columns=None):
+             estep_columns=None, eta=None, phi_x=None, phi_y=None, cf_threshold=0.0):
     """LSG-CPD rigid registration by EM (Sec. 3): target normals and penalty
     (Sec. 3.1, Eq. 3), working volume and initial sigma^2, then alternate the
     E step (Eq. 5/9) and the M step (Sec. 3.5).
 
-    Readings: uniform priors pi(m) = 1/M and w_n = w0 (no confidence filtering);
-    a fixed number of iterations unless tol > 0, in which case EM stops once
+    Outlier weights and priors: w_n = w0 and pi(m) = 1/M, unless
+      eta     -- w0 = w_max (Sec. 3.2) at the initial sigma^2;
+      phi_x, phi_y -- confidences of the source and target points: confidence
+                 filtering (Sec. 3.3), pi(m) proportional to phi(y_m) and
+                 w_n = 1 - (1 - w0) phi(x_n);
+      cf_threshold -- points whose confidence is below it are dropped first
+                 (Sec. 3.3); normals, V and sigma^2_0 come from what is kept.
+    Readings: a fixed number of iterations unless tol > 0, in which case EM stops once
     |L_i - L_{i-1}| <= tol |L_i| for the negative log-likelihood L of Eq. (4);
     sigma^2 is floored at 1e-12 times the squared target box diagonal.
 
@@ -533,6 +603,14 @@ def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=50, tol=0.0,
     that returns (Columns, nll) for the same definitions (used for clouds too
     large for a dense M x N matrix).
     """
+    if cf_threshold > 0.0:
+        if phi_x is not None:
+            X, phi_x = truncate(X, phi_x, cf_threshold)
+        if phi_y is not None:
+            Y, phi_y = truncate(Y, phi_y, cf_threshold)
+    if estep_columns is not None and (eta is not None or phi_x is not None
+                                      or phi_y is not None):
+        raise ValueError("estep_columns takes uniform priors and a fixed w0 only")
     X = _f64(X)
     Y = _f64(Y)
     if target_normals is None:
@@ -545,11 +623,17 @@ def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=50, tol=0.0,
         V = working_volume(Y)
     s2 = sigma2_init(X, Y, R, t) if sigma2_0 is None else float(sigma2_0)
     floor = 1e-12 * bbox_diag(Y) ** 2
-    out = Registration(R=R, t=t, sigma2=s2, iters=0, normals=nrm, alpha=alpha, V=V)
+    out = Registration(R=R, t=t, sigma2=s2, iters=0, normals=nrm, alpha=alpha, V=V,
+                       N=X.shape[0], M=Y.shape[0])
+    pi, _ = confidence_priors(phi_y, None, w0)
+    if eta is not None:
+        w0 = outlier_weight_max(eta, V, pi, alpha, s2, exact_normalizer)
+    _, w = confidence_priors(None, phi_x, w0)
+    out.w0 = w0
     prev = None
     for it in range(max_iter):
         if estep_columns is None:
-            es = estep(X, Y, nrm, alpha, R, t, s2, w0=w0, V=V,
+            es = estep(X, Y, nrm, alpha, R, t, s2, w0=w0, V=V, pi=pi, w=w,
                        exact_normalizer=exact_normalizer)
             cols = columns(es.P, X, Y, nrm, alpha, R, t)
             nll = es.nll
