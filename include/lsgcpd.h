@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LSGCPD_ABI_VERSION 3
+#define LSGCPD_ABI_VERSION 4
 
 typedef struct lsgcpd_ctx lsgcpd_ctx;
 typedef void *lsgcpd_stream;  /* a hipStream_t */
@@ -177,6 +177,14 @@ typedef struct {
   double sigma2_init;    /* <= 0 => sum_mn |g0(x_n) - y_m|^2 / (3 M N)        */
   int32_t newton_max;    /* Newton steps per M step (>= 1)                     */
   uint32_t flags;        /* as for lsgcpd_estep                                 */
+  double eta;            /* outlier ratio (Sec. 3.2).  0 < eta < 1: w0 is set
+                            to w_max = eta V S / ((1 - eta) + eta V S),
+                            S = sum_m pi(m) c_m, with c_m the peak of the
+                            component density (Eq. 2) as the E step evaluates
+                            it -- (2 pi sigma2)^{-3/2}, times sqrt(1 + alpha_m)
+                            with LSGCPD_EXACT_NORMALIZER -- taken once, at the
+                            initial sigma2, and kept; the w0 field is then
+                            ignored.  <= 0: w0 as given                      */
 } lsgcpd_params;
 
 typedef struct {
@@ -186,10 +194,14 @@ typedef struct {
   double sigma2;         /* final sigma^2                                      */
   double nll_first, nll_last;
   double V;
+  double w0;             /* uniform outlier weight used (w_max when eta > 0)  */
+  int64_t n_used;        /* source / target points registered (after the     */
+  int64_t m_used;        /* truncation of lsgcpd_register_cf)                */
 } lsgcpd_report;
 
 /* Fills p with the defaults used by the examples: k=10, alpha_max=30,
- * lambda=0.2, w0=0.1, V=0, max_iter=50, tol=0, sigma2_init=0, newton_max=20. */
+ * lambda=0.2, w0=0.1, V=0, max_iter=50, tol=0, sigma2_init=0, newton_max=20,
+ * flags=0, eta=0. */
 void lsgcpd_params_default(lsgcpd_params *p);
 
 /* Registers X (N x 3) to Y (M x 3): normals from Y (lsgcpd_normals), then EM
@@ -212,14 +224,41 @@ lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const 
  * Results equal lsgcpd_register's up to the grouping of the sums (the work
  * items differ).  Requires 1 <= npairs <= 65536, sum of N[i] + M[i] at most
  * 2^27, k <= M[i], and the default pair kernel (LSGCPD_PAIRS_LDS / _MFMA give
- * LSGCPD_E_UNSUPPORTED for npairs > 1).  Synchronises `stream`.  (The
- * batched-registration row of the design: many pairs of uneven sizes per
- * launch.) */
+ * LSGCPD_E_UNSUPPORTED for npairs > 1).  Synchronises `stream`. */
 lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs, const float *const *X,
                                     const int64_t *N, const float *const *Y, const int64_t *M,
                                     const lsgcpd_params *p, const lsgcpd_pose *init,
                                     lsgcpd_pose *out, lsgcpd_report *reports,
                                     lsgcpd_stream stream);
+
+/* ---- confidence filtering (Sec. 3.3) ------------------------------------ */
+
+/* Measurement confidence of points seen by a depth sensor (Sec. 3.3):
+ * phi = e_min / e(z) with the error model e(z) = coef[0] + coef[1] z +
+ * coef[2] z^2 of the depth z = P[i][2] (points in the sensor frame), and
+ * phi = 1 where e(z) <= e_min (e_min: the smallest error over the sensor's
+ * range).  Evaluated in FP64, written as float32.  P: n x 3 float32 device
+ * array; phi: n float32 device array; coef: HOST array of 3 finite doubles;
+ * e_min > 0.  Asynchronous on `stream`. */
+lsgcpd_status lsgcpd_depth_confidence(lsgcpd_ctx *ctx, const float *P, int64_t n,
+                                      const double *coef, double e_min, float *phi,
+                                      lsgcpd_stream stream);
+
+/* lsgcpd_register with confidence filtering (Sec. 3.3).  phi_x (N) and
+ * phi_y (M) are float32 device arrays of confidences in (0, 1] (NULL => 1
+ * for that cloud; values are not checked).  If threshold > 0, the points of a
+ * cloud whose confidence is below it are dropped first (order kept; the
+ * normals, V and the initial sigma2 then come from the points kept, and
+ * report->n_used / m_used give their numbers).  Then EM runs with priors
+ * pi(m) = phi(y_m) / sum phi(y) and outlier weights
+ * w_n = 1 - (1 - w0) phi(x_n), w0 from p (or w_max with p->eta > 0).
+ * LSGCPD_E_INVALID if no point of a cloud, or fewer than k targets, remain.
+ * Synchronises `stream` (once more after the truncation). */
+lsgcpd_status lsgcpd_register_cf(lsgcpd_ctx *ctx, const float *X, const float *phi_x, int64_t N,
+                                 const float *Y, const float *phi_y, int64_t M, double threshold,
+                                 const lsgcpd_params *p, const lsgcpd_pose *init,
+                                 lsgcpd_pose *out, lsgcpd_report *report, double *nll_trace,
+                                 lsgcpd_stream stream);
 
 /* ---- kernel timing (benchmarks) ----------------------------------------- */
 

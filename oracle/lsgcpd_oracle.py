@@ -538,7 +538,10 @@ def depth_confidence(P, coef, e_min):
     z = _f64(P)[:, 2]
     c0, c1, c2 = (float(c) for c in coef)
     e = c0 + c1 * z + c2 * z * z
-    return np.minimum(1.0, float(e_min) / e)
+    out = np.ones_like(e)
+    far = e > float(e_min)
+    out[far] = float(e_min) / e[far]
+    return out
 
 
 def confidence_priors(phi_y, phi_x, w0):

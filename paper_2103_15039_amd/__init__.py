@@ -27,7 +27,9 @@ NSTATS = 86
 SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
            "lsgcpd_ctx_destroy", "lsgcpd_last_error", "lsgcpd_params_default",
            "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_register_batch",
+           "lsgcpd_depth_confidence", "lsgcpd_register_cf",
            "lsgcpd_profile_enable", "lsgcpd_profile_read")
+ABI_VERSION = 4
 
 
 class Pose(C.Structure):
@@ -46,13 +48,14 @@ class Params(C.Structure):
     _fields_ = [("k", C.c_int32), ("alpha_max", C.c_double), ("lambda_", C.c_double),
                 ("w0", C.c_double), ("V", C.c_double), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("sigma2_init", C.c_double), ("newton_max", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("eta", C.c_double)]
 
 
 class Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("gn_fallbacks", C.c_int32),
                 ("sigma2", C.c_double), ("nll_first", C.c_double), ("nll_last", C.c_double),
-                ("V", C.c_double)]
+                ("V", C.c_double), ("w0", C.c_double), ("n_used", C.c_int64),
+                ("m_used", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -85,6 +88,9 @@ def load_library(path=LIB_PATH):
     lib = C.CDLL(path)
     vp, i64, i32, u32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_double
     lib.lsgcpd_abi_version.restype = C.c_int
+    if lib.lsgcpd_abi_version() != ABI_VERSION:
+        raise ImportError(f"{path} has ABI version {lib.lsgcpd_abi_version()}, this binding "
+                          f"expects {ABI_VERSION}: rebuild it")
     lib.lsgcpd_status_string.restype = C.c_char_p
     lib.lsgcpd_status_string.argtypes = [C.c_int]
     lib.lsgcpd_ctx_create.restype = C.c_int
@@ -106,6 +112,12 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_register_batch.restype = C.c_int
     lib.lsgcpd_register_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Params),
                                           C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Report), vp]
+    lib.lsgcpd_depth_confidence.restype = C.c_int
+    lib.lsgcpd_depth_confidence.argtypes = [vp, vp, i64, C.POINTER(C.c_double), d, vp, vp]
+    lib.lsgcpd_register_cf.restype = C.c_int
+    lib.lsgcpd_register_cf.argtypes = [vp, vp, vp, i64, vp, vp, i64, d, C.POINTER(Params),
+                                       C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Report), vp,
+                                       vp]
     lib.lsgcpd_profile_enable.restype = C.c_int
     lib.lsgcpd_profile_enable.argtypes = [vp, C.c_int]
     lib.lsgcpd_profile_read.restype = C.c_int
@@ -265,6 +277,9 @@ class RegistrationResult:
     gn_fallbacks: int
     nll: np.ndarray
     V: float
+    w0: float = 0.0     # uniform outlier weight used
+    n_used: int = 0     # points registered (after truncation)
+    m_used: int = 0
 
 
 def default_params():
@@ -273,19 +288,38 @@ def default_params():
     return p
 
 
+def _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max, flags, eta):
+    return Params(k=int(k), alpha_max=float(alpha_max), lambda_=float(lam), w0=float(w0),
+                  V=float(V), max_iter=int(max_iter), tol=float(tol),
+                  sigma2_init=float(sigma2_init), newton_max=int(newton_max), flags=flags,
+                  eta=float(eta) if eta is not None else 0.0)
+
+
+def _result(out, rep, nll):
+    R, t = _pose_np(out)
+    return RegistrationResult(R=R, t=t, sigma2=rep.sigma2, iters=rep.iters,
+                              converged=bool(rep.converged), gn_fallbacks=rep.gn_fallbacks,
+                              nll=nll, V=rep.V, w0=rep.w0, n_used=rep.n_used,
+                              m_used=rep.m_used)
+
+
+def _init_pose(R0, t0):
+    if R0 is None and t0 is None:
+        return None
+    return _pose(np.eye(3) if R0 is None else R0, np.zeros(3) if t0 is None else t0)
+
+
 def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
-             sigma2_init=0.0, newton_max=20, exact=False, backend="scalar", R0=None, t0=None):
-    """Full LSG-CPD registration of X onto Y (lsgcpd_register)."""
+             sigma2_init=0.0, newton_max=20, exact=False, backend="scalar", R0=None, t0=None,
+             eta=None):
+    """Full LSG-CPD registration of X onto Y (lsgcpd_register).  eta: outlier
+    ratio; w0 is then w_max (Sec. 3.2)."""
     X = _dev_tensor(X, (3,), "X")
     dev = X.device.index
     Y = _dev_tensor(Y, (3,), "Y", dev)
-    p = Params(k=int(k), alpha_max=float(alpha_max), lambda_=float(lam), w0=float(w0),
-               V=float(V), max_iter=int(max_iter), tol=float(tol),
-               sigma2_init=float(sigma2_init), newton_max=int(newton_max),
-               flags=(EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend])
-    init = None
-    if R0 is not None or t0 is not None:
-        init = _pose(np.eye(3) if R0 is None else R0, np.zeros(3) if t0 is None else t0)
+    p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
+                (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend], eta)
+    init = _init_pose(R0, t0)
     out = Pose()
     rep = Report()
     trace = (C.c_double * max(int(max_iter), 1))()
@@ -295,15 +329,59 @@ def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, to
                                         C.byref(out), C.byref(rep), C.cast(trace, C.c_void_p),
                                         _stream(dev))
     _check(st, ctx)
-    R, t = _pose_np(out)
-    filled = rep.iters + rep.converged
-    return RegistrationResult(R=R, t=t, sigma2=rep.sigma2, iters=rep.iters,
-                              converged=bool(rep.converged), gn_fallbacks=rep.gn_fallbacks,
-                              nll=np.array(trace[:filled]), V=rep.V)
+    return _result(out, rep, np.array(trace[:rep.iters + rep.converged]))
+
+
+def depth_confidence(P, coef, e_min):
+    """Confidence phi = e_min / e(z) of depth-sensor points, e(z) = coef[0] +
+    coef[1] z + coef[2] z^2 (lsgcpd_depth_confidence); returns a float32 tensor."""
+    torch = _torch()
+    P = _dev_tensor(P, (3,), "P")
+    dev = P.device.index
+    phi = torch.empty((P.shape[0],), dtype=torch.float32, device=P.device)
+    c = (C.c_double * 3)(*[float(v) for v in coef])
+    ctx = context(dev)
+    st = load_library().lsgcpd_depth_confidence(ctx, _ptr(P), P.shape[0], c, float(e_min),
+                                                _ptr(phi), _stream(dev))
+    _check(st, ctx)
+    return phi
+
+
+def register_cf(X, Y, phi_x=None, phi_y=None, threshold=0.0, k=10, alpha_max=30.0, lam=0.2,
+                w0=0.1, V=0.0, max_iter=50, tol=0.0, sigma2_init=0.0, newton_max=20,
+                exact=False, dense=False, R0=None, t0=None, eta=None):
+    """Registration with confidence filtering (lsgcpd_register_cf): priors
+    from phi_y, outlier weights from phi_x, points below `threshold` dropped."""
+    X = _dev_tensor(X, (3,), "X")
+    dev = X.device.index
+    Y = _dev_tensor(Y, (3,), "Y", dev)
+    if phi_x is not None:
+        phi_x = _dev_tensor(phi_x, None, "phi_x", dev)
+        if phi_x.numel() != X.shape[0]:
+            raise ValueError("phi_x must have N entries")
+    if phi_y is not None:
+        phi_y = _dev_tensor(phi_y, None, "phi_y", dev)
+        if phi_y.numel() != Y.shape[0]:
+            raise ValueError("phi_y must have M entries")
+    p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
+                (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0), eta)
+    init = _init_pose(R0, t0)
+    out = Pose()
+    rep = Report()
+    trace = (C.c_double * max(int(max_iter), 1))()
+    ctx = context(dev)
+    st = load_library().lsgcpd_register_cf(ctx, _ptr(X), _ptr(phi_x), X.shape[0], _ptr(Y),
+                                           _ptr(phi_y), Y.shape[0], float(threshold), C.byref(p),
+                                           C.byref(init) if init is not None else None,
+                                           C.byref(out), C.byref(rep),
+                                           C.cast(trace, C.c_void_p), _stream(dev))
+    _check(st, ctx)
+    return _result(out, rep, np.array(trace[:rep.iters + rep.converged]))
 
 
 def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
-                   sigma2_init=0.0, newton_max=20, exact=False, dense=False, init=None):
+                   sigma2_init=0.0, newton_max=20, exact=False, dense=False, init=None,
+                   eta=None):
     """Registers every (X, Y) of `pairs` in one batched pipeline
     (lsgcpd_register_batch); returns one RegistrationResult per pair (its
     `nll` holds the first and the last value of Eq. 4 only)."""
@@ -317,10 +395,8 @@ def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter
         dev = X.device.index
         Xs.append(X)
         Ys.append(_dev_tensor(Y, (3,), "Y", dev))
-    p = Params(k=int(k), alpha_max=float(alpha_max), lambda_=float(lam), w0=float(w0),
-               V=float(V), max_iter=int(max_iter), tol=float(tol),
-               sigma2_init=float(sigma2_init), newton_max=int(newton_max),
-               flags=(EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0))
+    p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
+                (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0), eta)
     xp = (C.c_void_p * n)(*[_ptr(X) for X in Xs])
     yp = (C.c_void_p * n)(*[_ptr(Y) for Y in Ys])
     nn = (C.c_int64 * n)(*[X.shape[0] for X in Xs])
@@ -338,11 +414,7 @@ def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter
     _check(st, ctx)
     res = []
     for i in range(n):
-        R, t = _pose_np(out[i])
-        r = rep[i]
-        res.append(RegistrationResult(R=R, t=t, sigma2=r.sigma2, iters=r.iters,
-                                      converged=bool(r.converged), gn_fallbacks=r.gn_fallbacks,
-                                      nll=np.array([r.nll_first, r.nll_last]), V=r.V))
+        res.append(_result(out[i], rep[i], np.array([rep[i].nll_first, rep[i].nll_last])))
     return res
 
 

@@ -33,6 +33,10 @@ struct lsgcpd_ctx {
   std::string err;
   Buf knn, rec, pts, boxes, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
       trace, order, xperm, yperm, ys4, tables, states;
+  // confidence filtering: kept points and confidences of X and Y, selection
+  // workspace, sorted source confidences, source permutation, prior sums
+  Buf cfx, cfy, cfwork, xphi, xidx, prior;
+  uint32_t *hcount = nullptr;  // pinned: kept point counts
   DevState *dstate = nullptr;  // device states (ctx->states), one per problem of a batch
   DevState *hstate = nullptr;  // pinned host staging for hcap states
   size_t hcap = 0;
@@ -146,7 +150,10 @@ lsgcpd_status check_params(lsgcpd_ctx *ctx, const lsgcpd_params *p) {
   if (!(p->alpha_max >= 0.0) || !isfinite(p->alpha_max))
     return fail(ctx, LSGCPD_E_INVALID, "alpha_max must be finite and >= 0");
   if (!finite_pos(p->lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
-  if (!(p->w0 > 0.0 && p->w0 < 1.0)) return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
+  if (!(p->eta < 1.0) || !isfinite(p->eta))
+    return fail(ctx, LSGCPD_E_INVALID, "eta must be finite and < 1");
+  if (!(p->eta > 0.0) && !(p->w0 > 0.0 && p->w0 < 1.0))
+    return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
   if (!isfinite(p->V) || !isfinite(p->tol) || !isfinite(p->sigma2_init))
     return fail(ctx, LSGCPD_E_INVALID, "V, tol and sigma2_init must be finite");
   if (p->max_iter < 0 || p->max_iter > 100000)
@@ -165,7 +172,7 @@ lsgcpd_status set_device(lsgcpd_ctx *ctx) {
 }
 
 void fill_state(DevState *s, const lsgcpd_pose *g, double sigma2, double V, double w0,
-                double tol, int newton_max, int max_iter) {
+                double eta, double tol, int newton_max, int max_iter) {
   memset(s, 0, sizeof(DevState));
   if (g) {
     memcpy(s->R, g->R, sizeof s->R);
@@ -176,6 +183,9 @@ void fill_state(DevState *s, const lsgcpd_pose *g, double sigma2, double V, doub
   s->sigma2 = sigma2;
   s->V = V;
   s->w0 = w0;
+  s->eta = eta > 0.0 ? eta : 0.0;
+  s->pi_sum = 1.0;
+  s->pic = 1.0;
   s->tol = tol;
   s->newton_max = newton_max;
   s->max_iter = max_iter;
@@ -203,13 +213,22 @@ lsgcpd_status ensure_states(lsgcpd_ctx *ctx, int n) {
 // Problem p of a batch: target records (record i of the problem describes its
 // target yperm[i], or target i if yperm is null) and their tile boxes, then
 // moments of Y, X at the problem's pose, then init_state.
+// Target records, working volume, sigma^2 floor and initial sigma^2 of
+// problem p.  Priors: pi (raw priors) or phi (target confidences, normalised
+// on the device: Sec. 3.3), else uniform; with eta > 0 the state's w0 becomes
+// w_max (Sec. 3.2).
 lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, int p, const float *Y,
                             const float *normals, const float *alpha, const float *pi,
-                            const uint32_t *yperm, uint32_t flags, int v_auto, int s2_auto,
-                            hipStream_t st) {
+                            const float *phi, double eta, const uint32_t *yperm, uint32_t flags,
+                            int v_auto, int s2_auto, hipStream_t st) {
   const lsg::Slot &sl = pl.slots[p];
-  HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, pi, yperm, sl.M,
-                                  (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0,
+  const int exact = (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0;
+  if (phi || eta > 0.0)
+    HIPCHK(lsg::launch_prior_sums(phi, alpha, sl.M, exact, (double *)ctx->prior.p,
+                                  ctx->dstate + p, st));
+  HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, phi ? phi : pi,
+                                  phi ? &(ctx->dstate + p)->pi_sum : nullptr, yperm, sl.M,
+                                  exact,
                                   (lsg::TRec *)ctx->rec.p + sl.y_off + p,
                                   (lsg::TPt *)ctx->pts.p + sl.y_off,
                                   (lsg::TBox *)ctx->boxes.p + sl.t_off, st));
@@ -272,6 +291,7 @@ lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int npairs, const int64_t *N, con
   ENSURE(yperm, (size_t)mtot * sizeof(uint32_t));
   ENSURE(ys4, (size_t)mtot * sizeof(float4));
   ENSURE(knn, kb);
+  ENSURE(prior, (size_t)2 * lsg::prior_blocks(nmax) * sizeof(double));
   return LSGCPD_OK;
 }
 
@@ -367,8 +387,11 @@ lsgcpd_status upload_tables(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, hipStream
 
 // Registration of npairs problems that share the parameters: the E steps and
 // M steps of all problems run in the same launches.
+// phi_x / phi_y: null, or per-pair source / target confidences (entries may
+// be null) for confidence filtering (Sec. 3.3).
 lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const *X,
                                 const int64_t *N, const float *const *Y, const int64_t *M,
+                                const float *const *phi_x, const float *const *phi_y,
                                 const lsgcpd_params *p, const lsgcpd_pose *init,
                                 lsgcpd_pose *out, lsgcpd_report *reports, double *nll_trace,
                                 hipStream_t st) {
@@ -384,6 +407,16 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   const int stride = p->max_iter > 0 ? p->max_iter : 1;
   ENSURE(trace, (size_t)npairs * stride * sizeof(double));
   if (pl.cull) ENSURE(xperm, (size_t)pl.sources * 3 * sizeof(float));
+  bool any_phi_x = false;
+  int64_t nmax = 1;
+  for (int i = 0; i < npairs; ++i) {
+    any_phi_x = any_phi_x || (phi_x && phi_x[i]);
+    nmax = N[i] > nmax ? N[i] : nmax;
+  }
+  if (any_phi_x && pl.cull) {
+    ENSURE(xphi, (size_t)pl.sources * sizeof(float));
+    ENSURE(xidx, (size_t)nmax * sizeof(uint32_t));
+  }
   RETURN_IF(ensure_states(ctx, npairs));
   lsg::BatchDev bd;
   RETURN_IF(ensure_estep(ctx, pl));
@@ -402,28 +435,37 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   // and all targets, so the order changes only the rounding of the sums.
   for (int i = 0; i < npairs; ++i) {
     lsg::Slot &sl = pl.slots[i];
+    const float *phx = phi_x ? phi_x[i] : nullptr;
     sl.X = X[i];
     sl.w = nullptr;
+    sl.phi = phx;
     if (pl.cull && N[i] > 256) {
       float *xs = (float *)ctx->xperm.p + 3 * sl.x_off;
       double *xbox = (double *)ctx->mom.p + 32;
+      uint32_t *xi = phx ? (uint32_t *)ctx->xidx.p : nullptr;
       HIPCHK(lsg::launch_moments(X[i], N[i], nullptr, (double *)ctx->mom_part.p,
                                  lsg::moments_blocks(N[i]), xbox, st));
       HIPCHK(lsg::launch_morton_order(X[i], N[i], xbox, ctx->order.p, ctx->order.cap, xs,
-                                      nullptr, nullptr, st));
+                                      nullptr, xi, st));
       sl.X = xs;
+      if (phx) {  // confidences follow their points
+        float *ps = (float *)ctx->xphi.p + sl.x_off;
+        HIPCHK(lsg::launch_gather_f32(phx, xi, N[i], ps, st));
+        sl.phi = ps;
+      }
     }
   }
   RETURN_IF(upload_tables(ctx, pl, st, &bd));
   const int s2_auto = p->sigma2_init > 0.0 ? 0 : 1;
   for (int i = 0; i < npairs; ++i)
     fill_state(ctx->hstate + i, init ? init + i : nullptr, s2_auto ? 1.0 : p->sigma2_init,
-               p->V > 0.0 ? p->V : 0.0, p->w0, p->tol, p->newton_max, p->max_iter);
+               p->V > 0.0 ? p->V : 0.0, p->w0, p->eta, p->tol, p->newton_max, p->max_iter);
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, (size_t)npairs * sizeof(DevState),
                         hipMemcpyHostToDevice, st));
   for (int i = 0; i < npairs; ++i) {
     const int64_t yo = pl.slots[i].y_off;
     RETURN_IF(setup_problem(ctx, pl, i, Y[i], nrm + 3 * yo, alp + yo, nullptr,
+                            phi_y ? phi_y[i] : nullptr, p->eta,
                             pl.cull ? (const uint32_t *)ctx->yperm.p + yo : nullptr, p->flags,
                             p->V > 0.0 ? 0 : 1, s2_auto, st));
   }
@@ -459,6 +501,9 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
       r.V = s.V;
       r.nll_last = s.nll;
       r.nll_first = p->max_iter > 0 && filled > 0 ? tr[0] : s.nll;
+      r.w0 = s.w0;
+      r.n_used = N[i];
+      r.m_used = M[i];
     }
     if (i == 0 && nll_trace && p->max_iter > 0)
       memcpy(nll_trace, tr, (size_t)filled * sizeof(double));
@@ -512,11 +557,13 @@ LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   Buf *bufs[] = {&c->knn,   &c->rec,   &c->pts,        &c->boxes, &c->plan,  &c->partial,
                  &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm,  &c->kap,
                  &c->alp,   &c->trace, &c->order,      &c->xperm, &c->yperm, &c->ys4,
-                 &c->tables, &c->states};
+                 &c->tables, &c->states, &c->cfx, &c->cfy, &c->cfwork, &c->xphi,
+                 &c->xidx,  &c->prior};
   for (Buf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->hstate) (void)hipHostFree(c->hstate);
+  if (c->hcount) (void)hipHostFree(c->hcount);
   delete c;
 }
 
@@ -534,6 +581,7 @@ LSG_API void lsgcpd_params_default(lsgcpd_params *p) {
   p->sigma2_init = 0.0;
   p->newton_max = 20;
   p->flags = 0;
+  p->eta = 0.0;
 }
 
 LSG_API lsgcpd_status lsgcpd_normals(lsgcpd_ctx *ctx, const float *Y, int64_t M, int32_t k,
@@ -584,10 +632,10 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   ENSURE(colS, (size_t)N * sizeof(double));
   lsg::BatchDev bd;
   RETURN_IF(upload_tables(ctx, pl, st, &bd));
-  fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 20, 1);
+  fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 0.0, 20, 1);
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
-  RETURN_IF(setup_problem(ctx, pl, 0, Y, normals, alpha, pi, nullptr, flags, V > 0.0 ? 0 : 1, 0,
-                          st));
+  RETURN_IF(setup_problem(ctx, pl, 0, Y, normals, alpha, pi, nullptr, 0.0, nullptr, flags,
+                          V > 0.0 ? 0 : 1, 0, st));
   RETURN_IF(prof_reserve(ctx, 1));
   RETURN_IF(run_estep(ctx, pl, bd, (double *)ctx->colS.p, colstats, nullptr, 1, 0, st));
   if (P)
@@ -631,8 +679,8 @@ LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N
   RETURN_IF(check_params(ctx, p));
   if (init) RETURN_IF(check_pose(ctx, init));
   RETURN_IF(set_device(ctx));
-  return register_problems(ctx, 1, &X, &N, &Y, &M, p, init, out, report, nll_trace,
-                           (hipStream_t)stream);
+  return register_problems(ctx, 1, &X, &N, &Y, &M, nullptr, nullptr, p, init, out, report,
+                           nll_trace, (hipStream_t)stream);
 }
 
 LSG_API lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs,
@@ -661,8 +709,89 @@ LSG_API lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs,
   }
   if (total > kMaxPoints) return fail(ctx, LSGCPD_E_INVALID, "batch holds more than 2^27 points");
   RETURN_IF(set_device(ctx));
-  return register_problems(ctx, npairs, X, N, Y, M, p, init, out, reports, nullptr,
-                           (hipStream_t)stream);
+  return register_problems(ctx, npairs, X, N, Y, M, nullptr, nullptr, p, init, out, reports,
+                           nullptr, (hipStream_t)stream);
+}
+
+LSG_API lsgcpd_status lsgcpd_depth_confidence(lsgcpd_ctx *ctx, const float *P, int64_t n,
+                                              const double *coef, double e_min, float *phi,
+                                              lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!P || !coef || !phi) return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  if (n < 1 || n > kMaxPoints) return fail(ctx, LSGCPD_E_INVALID, "n = %lld out of range", (long long)n);
+  if (!finite_pos(e_min)) return fail(ctx, LSGCPD_E_INVALID, "e_min must be finite and > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(coef[i])) return fail(ctx, LSGCPD_E_INVALID, "error model coefficients must be finite");
+  RETURN_IF(set_device(ctx));
+  HIPCHK(lsg::launch_depth_confidence(P, n, coef, e_min, phi, (hipStream_t)stream));
+  return LSGCPD_OK;
+}
+
+LSG_API lsgcpd_status lsgcpd_register_cf(lsgcpd_ctx *ctx, const float *X, const float *phi_x,
+                                         int64_t N, const float *Y, const float *phi_y, int64_t M,
+                                         double threshold, const lsgcpd_params *p,
+                                         const lsgcpd_pose *init, lsgcpd_pose *out,
+                                         lsgcpd_report *report, double *nll_trace,
+                                         lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!X || !Y || !p || !out) return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  if (N < 1 || M < 1 || N > kMaxPoints || M > kMaxPoints)
+    return fail(ctx, LSGCPD_E_INVALID, "M = %lld, N = %lld out of range", (long long)M,
+                (long long)N);
+  if (!isfinite(threshold)) return fail(ctx, LSGCPD_E_INVALID, "threshold must be finite");
+  RETURN_IF(check_params(ctx, p));
+  if (init) RETURN_IF(check_pose(ctx, init));
+  RETURN_IF(set_device(ctx));
+  hipStream_t st = (hipStream_t)stream;
+  const float *Xu = X, *Yu = Y, *px = phi_x, *py = phi_y;
+  int64_t Nu = N, Mu = M;
+  if (threshold > 0.0 && (phi_x || phi_y)) {
+    // Sec. 3.3: drop the points whose confidence is below the threshold
+    if (!ctx->hcount && hipHostMalloc((void **)&ctx->hcount, 2 * sizeof(uint32_t),
+                                      hipHostMallocDefault) != hipSuccess) {
+      ctx->hcount = nullptr;
+      (void)hipGetLastError();
+      return fail(ctx, LSGCPD_E_NOMEM, "pinned count allocation failed");
+    }
+    const size_t wx = lsg::select_workspace_bytes(N), wy = lsg::select_workspace_bytes(M);
+    ENSURE(cfwork, (wx > wy ? wx : wy) + 256);
+    uint32_t *dcount = (uint32_t *)((char *)ctx->cfwork.p + ctx->cfwork.cap - 256);
+    const size_t wbytes = ctx->cfwork.cap - 256;
+    if (phi_x) {
+      ENSURE(cfx, (size_t)N * 4 * sizeof(float));
+      float *xs = (float *)ctx->cfx.p;
+      HIPCHK(lsg::launch_select_confident(X, phi_x, N, threshold, ctx->cfwork.p, wbytes, xs,
+                                          xs + 3 * N, dcount, st));
+      HIPCHK(hipMemcpyAsync(ctx->hcount, dcount, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    }
+    if (phi_y) {
+      ENSURE(cfy, (size_t)M * 4 * sizeof(float));
+      float *ys = (float *)ctx->cfy.p;
+      HIPCHK(lsg::launch_select_confident(Y, phi_y, M, threshold, ctx->cfwork.p, wbytes, ys,
+                                          ys + 3 * M, dcount + 1, st));
+      HIPCHK(hipMemcpyAsync(ctx->hcount + 1, dcount + 1, sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (phi_x) {
+      Nu = ctx->hcount[0];
+      Xu = (const float *)ctx->cfx.p;
+      px = Xu + 3 * N;
+    }
+    if (phi_y) {
+      Mu = ctx->hcount[1];
+      Yu = (const float *)ctx->cfy.p;
+      py = Yu + 3 * M;
+    }
+    if (Nu < 1 || Mu < 1)
+      return fail(ctx, LSGCPD_E_INVALID, "no point of %s has confidence >= %g",
+                  Nu < 1 ? "X" : "Y", threshold);
+  }
+  if (p->k > Mu)
+    return fail(ctx, LSGCPD_E_INVALID, "k = %d exceeds the %lld target points kept", p->k,
+                (long long)Mu);
+  return register_problems(ctx, 1, &Xu, &Nu, &Yu, &Mu, &px, &py, p, init, out, report,
+                           nll_trace, st);
 }
 
 LSG_API lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on) {

@@ -579,6 +579,7 @@ __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
   const int N = sl.N;
   const float *X = sl.X;
   const float *w = sl.w;
+  const float *phi = sl.phi;
   const int fb = blockIdx.x - sl.fin_off;
   const int l = threadIdx.x & (kFinBlock - 1);
   const int part = threadIdx.x / kFinBlock;  // 0 without ITEMS
@@ -627,7 +628,8 @@ __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
       for (int c = 0; c < kFeatUsed; ++c) T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
   }
   if (part == 0 && n < N) {
-    const double wn = w ? (double)w[n] : st->w0;
+    // Sec. 3.3: w_n = 1 - (1 - w0) phi(x_n) under confidence filtering
+    const double wn = w ? (double)w[n] : phi ? 1.0 - (1.0 - st->w0) * (double)phi[n] : st->w0;
     const double rho = (1.0 - wn) / wn;
     const double gam = gamma_of(st);
     const double den = rho * T[0];
@@ -720,6 +722,7 @@ __global__ void dump_P(const float *__restrict__ X, int N, const TRec *__restric
 // ----------------------------------------------------------- target records
 __global__ void prep_targets(const float *__restrict__ Y, const float *__restrict__ nrm,
                              const float *__restrict__ alpha, const float *__restrict__ pi,
+                             const double *__restrict__ pi_sum,
                              const uint32_t *__restrict__ perm, int64_t M, int exact,
                              TRec *__restrict__ rec, TPt *__restrict__ pts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -728,7 +731,7 @@ __global__ void prep_targets(const float *__restrict__ Y, const float *__restric
   const double y0 = Y[3 * m], y1 = Y[3 * m + 1], y2 = Y[3 * m + 2];
   const double n0 = nrm[3 * m], n1 = nrm[3 * m + 1], n2 = nrm[3 * m + 2];
   const double al = alpha[m];
-  const double pm = pi ? (double)pi[m] : 1.0 / (double)M;
+  const double pm = !pi ? 1.0 / (double)M : pi_sum ? (double)pi[m] / *pi_sum : (double)pi[m];
   double l = log2(pm);
   if (exact) l += 0.5 * log2(1.0 + al);
   const double sa = sqrt(al);
@@ -1108,10 +1111,11 @@ hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, 
 }
 
 hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
-                               const float *pi, const uint32_t *perm, int64_t M, int exact,
-                               TRec *rec, TPt *pts, TBox *boxes, hipStream_t st) {
+                               const float *pi, const double *pi_sum, const uint32_t *perm,
+                               int64_t M, int exact, TRec *rec, TPt *pts, TBox *boxes,
+                               hipStream_t st) {
   hipLaunchKernelGGL(prep_targets, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, Y,
-                     normals, alpha, pi, perm, M, exact, rec, pts);
+                     normals, alpha, pi, pi_sum, perm, M, exact, rec, pts);
   const int64_t ntiles = (M + kCullTile - 1) / kCullTile;
   hipLaunchKernelGGL(tile_boxes, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, pts, M,
                      boxes);

@@ -65,6 +65,11 @@ struct DevState {
   double pd;          // sum P d at the E-step pose
   double nll;         // Eq. 4 at the E-step pose
   double gamma;
+  // outlier weight from the outlier ratio (eta > 0: w0 = w_max at the initial
+  // sigma^2) and the target sums it and the confidence priors use
+  double eta;
+  double pi_sum;      // sum_m phi(y_m) (prior normaliser)
+  double pic;         // sum_m pi(m) c_m (2 pi sigma^2)^{3/2}
   int64_t evaluated_pairs;  // pairs the pair kernel evaluated (scalar back end)
   int32_t iter;       // M steps taken
   int32_t done;       // 1 once tol stopped EM (later kernels return at once)
@@ -110,10 +115,28 @@ hipError_t launch_morton_order(const float *P, int64_t n, const double *box, voi
 // Target records.
 // Record i describes target perm[i] (perm may be null); rec[M] is a sentinel
 // whose exponent is -inf (rec holds M + 1 records); boxes gets one TBox per
-// tile of kCullTile records.
+// tile of kCullTile records.  Priors: pi null => 1/M; else pi[m], divided by
+// *pi_sum when pi_sum (device) is not null.
 hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
-                               const float *pi, const uint32_t *perm, int64_t M, int exact,
-                               TRec *rec, TPt *pts, TBox *boxes, hipStream_t st);
+                               const float *pi, const double *pi_sum, const uint32_t *perm,
+                               int64_t M, int exact, TRec *rec, TPt *pts, TBox *boxes,
+                               hipStream_t st);
+
+// Confidence filtering (confidence.hip).  phi of depth-sensor points from the
+// error model coef[0] + coef[1] z + coef[2] z^2; truncation to phi >= threshold
+// (order kept; *count on the device); the target sums pi_sum and pic of a
+// state (phi null => 1); a float gather dst[i] = src[perm[i]].
+hipError_t launch_depth_confidence(const float *P, int64_t n, const double coef[3], double e_min,
+                                   float *phi, hipStream_t st);
+size_t select_workspace_bytes(int64_t n);
+hipError_t launch_select_confident(const float *P, const float *phi, int64_t n, double threshold,
+                                   void *work, size_t work_bytes, float *Pout, float *phiout,
+                                   uint32_t *count, hipStream_t st);
+int prior_blocks(int64_t M);
+hipError_t launch_prior_sums(const float *phi, const float *alpha, int64_t M, int exact,
+                             double *partials, DevState *s, hipStream_t st);
+hipError_t launch_gather_f32(const float *src, const uint32_t *perm, int64_t n, float *dst,
+                             hipStream_t st);
 
 // E step: fused exponent + accumulation (over live target tiles in balanced
 // work items, or over target chunks), then per-source finalisation + lift to
@@ -127,7 +150,8 @@ constexpr int kPairS = 2;          // sources per thread in the LDS back end
 // device memory; the single-pair calls are batches of one).
 struct Slot {
   const float *X;   // sources, N x 3 (Morton order when culled)
-  const float *w;   // per-source weights, or null (then w0 of the state)
+  const float *w;   // per-source weights, or null (then phi, else w0 of the state)
+  const float *phi; // per-source confidences (order of X): w_n = 1 - (1 - w0) phi_n
   int64_t x_off;    // first source in the batch numbering (colS, colstats)
   int64_t y_off;    // first target in the packed positions; records start at y_off + slot
   int64_t list_off; // live-tile lists of the problem: ngroups x ntiles ints

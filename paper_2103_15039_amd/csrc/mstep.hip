@@ -433,6 +433,12 @@ __global__ void init_state(DevState *__restrict__ s, const double *__restrict__ 
     const double tot = (double)M * xmom[3] + (double)N * ymom[3] - 2.0 * dot;
     s->sigma2 = tot / (3.0 * (double)M * (double)N);
   }
+  if (s->eta > 0.0) {
+    // Sec. 3.2: w_max = eta V S / ((1 - eta) + eta V S), S = sum_m pi(m) c_m
+    // with the component bound c_m at the initial sigma^2
+    const double a = s->eta * s->V * s->pic * pow(kTwoPi * s->sigma2, -1.5);
+    s->w0 = a / ((1.0 - s->eta) + a);
+  }
 }
 
 }  // namespace

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
                          text=True).stdout
     exported = set(re.findall(r" T (lsgcpd_\w+)", out))
     assert exported == set(names)
-    assert lib.lsgcpd_abi_version() == 3
+    assert lib.lsgcpd_abi_version() == L.ABI_VERSION == 4
     assert lib.lsgcpd_status_string(3) == b"LSGCPD_E_NOMEM"
 
 
@@ -43,11 +43,13 @@ def test_header_compiles_and_layout_matches(cc, ext):
 #include <stdio.h>
 #include "lsgcpd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lsgcpd_pose),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lsgcpd_pose),
          sizeof(lsgcpd_estep_out), offsetof(lsgcpd_estep_out, stats),
          offsetof(lsgcpd_estep_out, newton_iters), sizeof(lsgcpd_params),
          offsetof(lsgcpd_params, tol), sizeof(lsgcpd_report), offsetof(lsgcpd_report, sigma2),
-         sizeof(lsgcpd_profile), offsetof(lsgcpd_profile, evaluated_pairs));
+         sizeof(lsgcpd_profile), offsetof(lsgcpd_profile, evaluated_pairs),
+         offsetof(lsgcpd_params, eta), offsetof(lsgcpd_report, w0),
+         offsetof(lsgcpd_report, m_used));
   return 0;
 }
 '''
@@ -61,13 +63,15 @@ int main(void) {
     want = [C.sizeof(L.Pose), C.sizeof(L.EstepOut), L.EstepOut.stats.offset,
             L.EstepOut.newton_iters.offset, C.sizeof(L.Params), L.Params.tol.offset,
             C.sizeof(L.Report), L.Report.sigma2.offset, C.sizeof(L.Profile),
-            L.Profile.evaluated_pairs.offset]
+            L.Profile.evaluated_pairs.offset, L.Params.eta.offset, L.Report.w0.offset,
+            L.Report.m_used.offset]
     assert got == want
 
 
 def test_params_default():
     p = L.default_params()
     assert (p.k, p.alpha_max, p.lambda_, p.w0, p.max_iter, p.newton_max) == (10, 30.0, 0.2, 0.1, 50, 20)
+    assert (p.flags, p.eta, p.V, p.tol, p.sigma2_init) == (0, 0.0, 0.0, 0.0, 0.0)
 
 
 def test_context_without_device_fails_cleanly():
