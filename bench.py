@@ -43,9 +43,11 @@ def parse():
                     help="pair-kernel back end (dense: scalar, every pair evaluated)")
     ap.add_argument("--workload", default="rgbd_20000x20000",
                     choices=["rgbd_20000x20000", "lidar_100000x50000", "range_scanner_2000x2000",
-                             "batch256"],
+                             "batch256", "batch256_small", "depth_cf_20000x20000"],
                     help="synthetic pair (the default is the benchmark's workload); batch256: "
-                         "256 scene pairs of 1,000-30,000 points registered as one batch")
+                         "256 scene pairs of 1,000-30,000 points registered as one batch; "
+                         "batch256_small: 256 pairs of 500-3,000 points; depth_cf: a depth-camera "
+                         "pair registered with confidence filtering and truncation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pair-kernel launch "
@@ -104,9 +106,9 @@ def cpu_baseline(p, nrm, alpha):
                       f"per-source sums) of the benchmark pair, {dt:.2f} s"}
 
 
-def batch_main(a):
+def batch_main(a, nmin=1000, nmax=30000):
     """256 pairs of box/sphere/plane scenes, M and N log-uniform in
-    [1000, 30000], rotations up to 60 deg: pairs registered per second by
+    [nmin, nmax], rotations up to 60 deg: pairs registered per second by
     lsgcpd_register_batch (the timed steps) next to the same pairs registered
     one by one with lsgcpd_register (one untimed-for-value pass), and the
     success rate (rotation error < 1 deg) of both."""
@@ -116,7 +118,7 @@ def batch_main(a):
     import paper_2103_15039_amd as L
     from oracle import lsgcpd_oracle as O
 
-    pairs = datagen.batch_pairs(256, trial=0)
+    pairs = datagen.batch_pairs(256, trial=0, nmin=nmin, nmax=nmax)
     args = [(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.Y).cuda()) for p in pairs]
     kw = dict(k=10, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS)
     torch.cuda.synchronize()
@@ -157,7 +159,8 @@ def batch_main(a):
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "batch256", "pairs": len(pairs), "points": "1000-30000 log-uniform",
+        "config": {"workload": a.workload, "pairs": len(pairs),
+                   "points": f"{nmin}-{nmax} log-uniform",
                    "em_iters": EM_ITERS, "knn": 10, "sum_MN": mn},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None},
@@ -166,6 +169,76 @@ def batch_main(a):
         "batched": {"success_rate": ok(res), "speedup_vs_plain": value * dt_single / len(pairs),
                     "estep_pair_evals_per_s": mn * EM_ITERS * a.steps / dt,
                     "pair_kernel_ms": k_ms, "evaluated_frac": evaluated / mn},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cf_main(a):
+    """Confidence filtering (Sec. 3.3) on a depth-camera pair (20,000 x 20,000
+    points, depth noise growing with the square of the depth): registrations
+    per second and rotation error against the ground truth of the plain
+    method (w0 = 0.1), of w0 from the outlier ratio (eta = 0.02), of confidence
+    filtering without truncation (w0 = 0.1, and w0 from eta), and with
+    truncation at several confidence
+    thresholds.  The timed steps (value) are confidence filtering with
+    truncation at the middle threshold; every variant is timed the same way."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2103_15039_amd as L
+
+    trials = [datagen.depth_pair(trial=t) for t in range(3)]
+    dev = [(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.Y).cuda()) for p in trials]
+    conf = [(L.depth_confidence(X, datagen.DEPTH_ERROR, datagen.DEPTH_ERROR_MIN),
+             L.depth_confidence(Y, datagen.DEPTH_ERROR, datagen.DEPTH_ERROR_MIN)) for X, Y in dev]
+    kw = dict(k=20, alpha_max=30.0, lam=0.2, max_iter=EM_ITERS)
+    variants = [("plain", dict(w0=0.1), None), ("eta", dict(eta=0.02), None),
+                ("cf_w0", dict(w0=0.1), 0.0), ("cf", dict(eta=0.02), 0.0)] + \
+               [(f"cf_trunc_{t}", dict(eta=0.02), t) for t in (0.03, 0.05, 0.08)]
+
+    def run(i, extra, thr):
+        X, Y = dev[i]
+        if thr is None:
+            return L.register(X, Y, **kw, **extra)
+        return L.register_cf(X, Y, conf[i][0], conf[i][1], threshold=thr, **kw, **extra)
+
+    out_var = {}
+    for name, extra, thr in variants:
+        for _ in range(a.warmup):
+            run(0, extra, thr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            for i in range(len(dev)):
+                r = run(i, extra, thr)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (a.steps * len(dev))
+        errs = [float(np.degrees(np.arccos(np.clip((np.trace(p.R_gt.T @ run(i, extra, thr).R) - 1)
+                                                   / 2, -1, 1)))) for i, p in enumerate(trials)]
+        last = run(0, extra, thr)
+        out_var[name] = {"ms": dt * 1e3, "registrations_per_s": 1.0 / dt,
+                         "rot_err_deg": errs, "rot_err_mean": float(np.mean(errs)),
+                         "points_kept": [int(last.n_used), int(last.m_used)], "w0": last.w0}
+        print(f"# {name}: {dt * 1e3:.2f} ms, rot err {np.mean(errs):.3f} deg", file=sys.stderr,
+              flush=True)
+    main_v = out_var["cf_trunc_0.05"]
+    out = {
+        "metric": "registrations/s",
+        "value": main_v["registrations_per_s"],
+        "unit": "registrations/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": main_v["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "M": 20000, "N": 20000, "em_iters": EM_ITERS,
+                   "knn": 20, "eta": 0.02, "threshold": 0.05, "depth_error": datagen.DEPTH_ERROR,
+                   "trials": len(trials)},
+        "variants": out_var,
     }
     print(json.dumps(out), flush=True)
 
@@ -181,6 +254,12 @@ def main():
         sys.exit(2)
     if a.workload == "batch256":
         batch_main(a)
+        return
+    if a.workload == "batch256_small":
+        batch_main(a, 500, 3000)
+        return
+    if a.workload.startswith("depth_cf"):
+        cf_main(a)
         return
     import numpy as np
     import torch

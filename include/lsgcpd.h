@@ -231,6 +231,23 @@ lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs, const float
                                     lsgcpd_pose *out, lsgcpd_report *reports,
                                     lsgcpd_stream stream);
 
+/* ---- tuning --------------------------------------------------------------- */
+
+/* Picks the work-item count of the default pair kernel by measurement: runs
+ * the registration lsgcpd_register(X, Y, p) would run (outputs discarded)
+ * with each of 1024, 2048, 4096, 8192, 16384 and 32768 work items per E step
+ * (twice each; the second run is timed with HIP events on `stream`) and keeps
+ * the fastest for the size class of the pair (floor(log2(M N))) in ctx:
+ * later lsgcpd_estep / lsgcpd_register / lsgcpd_register_cf calls and batches
+ * whose sum of M N falls in that class use it (default: 8192, or the
+ * LSGCPD_WORK_ITEMS environment variable).  The count changes how the pair
+ * sums are grouped, so results differ at the rounding level only.  *items_out
+ * (may be NULL) receives the choice.  Argument rules as lsgcpd_register.
+ * Synchronises `stream`. */
+lsgcpd_status lsgcpd_autotune(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
+                              int64_t M, const lsgcpd_params *p, int32_t *items_out,
+                              lsgcpd_stream stream);
+
 /* ---- confidence filtering (Sec. 3.3) ------------------------------------ */
 
 /* Measurement confidence of points seen by a depth sensor (Sec. 3.3):

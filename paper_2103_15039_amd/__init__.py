@@ -27,7 +27,7 @@ NSTATS = 86
 SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
            "lsgcpd_ctx_destroy", "lsgcpd_last_error", "lsgcpd_params_default",
            "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_register_batch",
-           "lsgcpd_depth_confidence", "lsgcpd_register_cf",
+           "lsgcpd_depth_confidence", "lsgcpd_register_cf", "lsgcpd_autotune",
            "lsgcpd_profile_enable", "lsgcpd_profile_read")
 ABI_VERSION = 4
 
@@ -118,6 +118,8 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_register_cf.argtypes = [vp, vp, vp, i64, vp, vp, i64, d, C.POINTER(Params),
                                        C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Report), vp,
                                        vp]
+    lib.lsgcpd_autotune.restype = C.c_int
+    lib.lsgcpd_autotune.argtypes = [vp, vp, i64, vp, i64, C.POINTER(Params), C.POINTER(i32), vp]
     lib.lsgcpd_profile_enable.restype = C.c_int
     lib.lsgcpd_profile_enable.argtypes = [vp, C.c_int]
     lib.lsgcpd_profile_read.restype = C.c_int
@@ -330,6 +332,24 @@ def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, to
                                         _stream(dev))
     _check(st, ctx)
     return _result(out, rep, np.array(trace[:rep.iters + rep.converged]))
+
+
+def autotune(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
+             sigma2_init=0.0, newton_max=20, exact=False, eta=None):
+    """Measures the registration of X onto Y with several work-item counts
+    and keeps the fastest for pairs of this size (lsgcpd_autotune); returns
+    the count chosen."""
+    X = _dev_tensor(X, (3,), "X")
+    dev = X.device.index
+    Y = _dev_tensor(Y, (3,), "Y", dev)
+    p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
+                EXACT_NORMALIZER if exact else 0, eta)
+    best = C.c_int32(0)
+    ctx = context(dev)
+    st = load_library().lsgcpd_autotune(ctx, _ptr(X), X.shape[0], _ptr(Y), Y.shape[0],
+                                        C.byref(p), C.byref(best), _stream(dev))
+    _check(st, ctx)
+    return best.value
 
 
 def depth_confidence(P, coef, e_min):

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,10 @@ struct lsgcpd_ctx {
   // workspace, sorted source confidences, source permutation, prior sums
   Buf cfx, cfy, cfwork, xphi, xidx, prior;
   uint32_t *hcount = nullptr;  // pinned: kept point counts
+  // work-item targets chosen by lsgcpd_autotune, per size class
+  // (floor(log2(sum of M N))); forced_items > 0 overrides while tuning
+  std::map<int, int> tuned_items;
+  int forced_items = 0;
   DevState *dstate = nullptr;  // device states (ctx->states), one per problem of a batch
   DevState *hstate = nullptr;  // pinned host staging for hcap states
   size_t hcap = 0;
@@ -114,6 +119,22 @@ int work_items() {
   const char *e = getenv("LSGCPD_WORK_ITEMS");
   const int v = e ? atoi(e) : 0;
   return v >= 64 && v <= (1 << 20) ? v : 8192;
+}
+
+int size_class(int npairs, const int64_t *N, const int64_t *M) {
+  uint64_t mn = 1;
+  for (int i = 0; i < npairs; ++i) mn += (uint64_t)N[i] * (uint64_t)M[i];
+  int c = 0;
+  while (mn >>= 1) ++c;
+  return c;
+}
+
+// Work-item target of an E step over these sizes: the one lsgcpd_autotune
+// measured fastest for their size class, else work_items().
+int items_for(const lsgcpd_ctx *ctx, int npairs, const int64_t *N, const int64_t *M) {
+  if (ctx->forced_items > 0) return ctx->forced_items;
+  auto it = ctx->tuned_items.find(size_class(npairs, N, M));
+  return it != ctx->tuned_items.end() ? it->second : work_items();
 }
 
 int backend_of(uint32_t flags) {
@@ -399,7 +420,8 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   if (npairs > 1 && backend != lsg::kBackendScalar)
     return fail(ctx, LSGCPD_E_UNSUPPORTED, "batches use the default pair kernel only");
   lsg::BatchPlan pl =
-      lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1, work_items());
+      lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1,
+                      items_for(ctx, npairs, N, M));
   RETURN_IF(ensure_geometry(ctx, npairs, N, M, pl.targets, p->k));
   ENSURE(nrm, (size_t)pl.targets * 3 * sizeof(float));
   ENSURE(kap, (size_t)pl.targets * sizeof(float));
@@ -624,7 +646,8 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
   lsg::BatchPlan pl =
-      lsg::batch_plan(1, &N, &M, backend_of(flags), (flags & LSGCPD_DENSE) ? 0 : 1, work_items());
+      lsg::batch_plan(1, &N, &M, backend_of(flags), (flags & LSGCPD_DENSE) ? 0 : 1,
+                      items_for(ctx, 1, &N, &M));
   pl.slots[0].X = X;
   pl.slots[0].w = w;
   RETURN_IF(ensure_states(ctx, 1));
@@ -792,6 +815,63 @@ LSG_API lsgcpd_status lsgcpd_register_cf(lsgcpd_ctx *ctx, const float *X, const 
                 (long long)Mu);
   return register_problems(ctx, 1, &Xu, &Nu, &Yu, &Mu, &px, &py, p, init, out, report,
                            nll_trace, st);
+}
+
+LSG_API lsgcpd_status lsgcpd_autotune(lsgcpd_ctx *ctx, const float *X, int64_t N,
+                                      const float *Y, int64_t M, const lsgcpd_params *p,
+                                      int32_t *items_out, lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!X || !Y || !p) return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  if (N < 1 || M < 1 || N > kMaxPoints || M > kMaxPoints)
+    return fail(ctx, LSGCPD_E_INVALID, "M = %lld, N = %lld out of range", (long long)M,
+                (long long)N);
+  if (p->k > M)
+    return fail(ctx, LSGCPD_E_INVALID, "k = %d must satisfy 1 <= k <= min(M, 32)", p->k);
+  RETURN_IF(check_params(ctx, p));
+  RETURN_IF(set_device(ctx));
+  hipStream_t st = (hipStream_t)stream;
+  static const int kCandidates[] = {1024, 2048, 4096, 8192, 16384, 32768};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ctx, LSGCPD_E_HIP, "hipEventCreate failed");
+  }
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  lsgcpd_status status = LSGCPD_OK;
+  int best = 0;
+  float best_ms = 0.f;
+  for (int c : kCandidates) {
+    ctx->forced_items = c;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && status == LSGCPD_OK; ++rep) {  // the first warms up
+      lsgcpd_pose out;
+      float t = 0.f;
+      if (hipEventRecord(e0, st) != hipSuccess) status = fail(ctx, LSGCPD_E_HIP, "hipEventRecord failed");
+      if (status == LSGCPD_OK)
+        status = register_problems(ctx, 1, &X, &N, &Y, &M, nullptr, nullptr, p, nullptr, &out,
+                                   nullptr, nullptr, st);
+      if (status == LSGCPD_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                                  hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        status = fail(ctx, LSGCPD_E_HIP, "event timing failed");
+      ms = t;
+    }
+    if (status != LSGCPD_OK) break;
+    if (best == 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  ctx->forced_items = 0;
+  ctx->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != LSGCPD_OK) return status;
+  ctx->tuned_items[size_class(1, &N, &M)] = best;
+  if (items_out) *items_out = best;
+  return LSGCPD_OK;
 }
 
 LSG_API lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on) {

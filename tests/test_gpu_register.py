@@ -121,3 +121,12 @@ def test_register_nll_monotone_and_recovery():
     assert np.all(np.diff(g.nll) <= 1e-7 * np.abs(g.nll[1:]))
     assert O.rotation_error_deg(g.R, Rg) < 1e-3
     assert O.translation_error(g.t, tg) < 1e-5 * O.bbox_diag(Y)
+
+
+def test_autotune_picks_a_candidate_and_keeps_parity():
+    p = datagen.range_scanner_pair(trial=6, M=2000, N=1800, angle_deg=20.0)
+    best = L.autotune(dev(p.X), dev(p.Y), k=10, max_iter=20)
+    assert best in (1024, 2048, 4096, 8192, 16384, 32768)
+    g, _ = _reg_pair(p, 10, 20)
+    again = L.register(dev(p.X), dev(p.Y), k=10, max_iter=20)
+    assert np.array_equal(again.R, g.R) and np.array_equal(again.nll, g.nll)
