@@ -66,6 +66,12 @@ typedef enum {
                                        dropped terms are exact zeros, so the
                                        results differ only in the rounding order
                                        of the sums */
+#define LSGCPD_GRAPH 16u            /* lsgcpd_register* only: record the EM
+                                       iterations once as a HIP graph and
+                                       replay it; the recording is kept in the
+                                       context and replayed by later calls of
+                                       the same sizes and parameters (ignored
+                                       while kernel timing is on) */
 
 typedef struct {
   double R[9]; /* row-major rotation */

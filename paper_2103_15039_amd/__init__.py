@@ -21,6 +21,7 @@ EXACT_NORMALIZER = 1
 PAIRS_LDS = 2
 PAIRS_MFMA = 4
 DENSE = 8
+GRAPH = 16
 _BACKENDS = {"scalar": 0, "lds": PAIRS_LDS, "mfma": PAIRS_MFMA, "dense": DENSE}
 NSTATS = 86
 
@@ -313,14 +314,16 @@ def _init_pose(R0, t0):
 
 def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
              sigma2_init=0.0, newton_max=20, exact=False, backend="scalar", R0=None, t0=None,
-             eta=None):
+             eta=None, graph=False):
     """Full LSG-CPD registration of X onto Y (lsgcpd_register).  eta: outlier
-    ratio; w0 is then w_max (Sec. 3.2)."""
+    ratio; w0 is then w_max (Sec. 3.2).  graph: replay the EM loop from a HIP
+    graph recording (LSGCPD_GRAPH)."""
     X = _dev_tensor(X, (3,), "X")
     dev = X.device.index
     Y = _dev_tensor(Y, (3,), "Y", dev)
     p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
-                (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend], eta)
+                (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend] | (GRAPH if graph else 0),
+                eta)
     init = _init_pose(R0, t0)
     out = Pose()
     rep = Report()
@@ -369,7 +372,7 @@ def depth_confidence(P, coef, e_min):
 
 def register_cf(X, Y, phi_x=None, phi_y=None, threshold=0.0, k=10, alpha_max=30.0, lam=0.2,
                 w0=0.1, V=0.0, max_iter=50, tol=0.0, sigma2_init=0.0, newton_max=20,
-                exact=False, dense=False, R0=None, t0=None, eta=None):
+                exact=False, dense=False, R0=None, t0=None, eta=None, graph=False):
     """Registration with confidence filtering (lsgcpd_register_cf): priors
     from phi_y, outlier weights from phi_x, points below `threshold` dropped."""
     X = _dev_tensor(X, (3,), "X")
@@ -384,7 +387,8 @@ def register_cf(X, Y, phi_x=None, phi_y=None, threshold=0.0, k=10, alpha_max=30.
         if phi_y.numel() != Y.shape[0]:
             raise ValueError("phi_y must have M entries")
     p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
-                (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0), eta)
+                (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0) |
+                (GRAPH if graph else 0), eta)
     init = _init_pose(R0, t0)
     out = Pose()
     rep = Report()
@@ -401,7 +405,7 @@ def register_cf(X, Y, phi_x=None, phi_y=None, threshold=0.0, k=10, alpha_max=30.
 
 def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
                    sigma2_init=0.0, newton_max=20, exact=False, dense=False, init=None,
-                   eta=None):
+                   eta=None, graph=False):
     """Registers every (X, Y) of `pairs` in one batched pipeline
     (lsgcpd_register_batch); returns one RegistrationResult per pair (its
     `nll` holds the first and the last value of Eq. 4 only)."""
@@ -416,7 +420,8 @@ def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter
         Xs.append(X)
         Ys.append(_dev_tensor(Y, (3,), "Y", dev))
     p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
-                (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0), eta)
+                (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0) |
+                (GRAPH if graph else 0), eta)
     xp = (C.c_void_p * n)(*[_ptr(X) for X in Xs])
     yp = (C.c_void_p * n)(*[_ptr(Y) for Y in Ys])
     nn = (C.c_int64 * n)(*[X.shape[0] for X in Xs])

@@ -42,6 +42,13 @@ struct lsgcpd_ctx {
   // (floor(log2(sum of M N))); forced_items > 0 overrides while tuning
   std::map<int, int> tuned_items;
   int forced_items = 0;
+  // the recorded EM loop (LSGCPD_GRAPH), the stream it is recorded and
+  // replayed on, and what it was recorded for
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gsig;
   DevState *dstate = nullptr;  // device states (ctx->states), one per problem of a batch
   DevState *hstate = nullptr;  // pinned host staging for hcap states
   size_t hcap = 0;
@@ -109,8 +116,8 @@ lsgcpd_status ensure(lsgcpd_ctx *ctx, Buf &b, size_t bytes) {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
-constexpr uint32_t kKnownFlags =
-    LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA | LSGCPD_DENSE;
+constexpr uint32_t kKnownFlags = LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA |
+                                 LSGCPD_DENSE | LSGCPD_GRAPH;
 
 // About this many work items per E step for the scalar back end (the
 // fastest measured on MI355X for the 20k x 20k and 100k x 50k workloads);
@@ -378,6 +385,63 @@ lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Ba
   return LSGCPD_OK;
 }
 
+// max_iter EM iterations of every problem, launched one by one, or (graph)
+// replayed from a recording of all of them.  Every kernel of the loop takes
+// only context buffers and the plan's sizes as arguments (the problems'
+// clouds are reached through the tables uploaded before), so a recording
+// stays valid while the sizes, parameters and buffers it was made with do.
+// It is made and replayed on a stream of the context, ordered after `st`
+// and before the rest of `st` by events.
+lsgcpd_status run_em(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::BatchDev &bd,
+                     int max_iter, int stride, bool graph, hipStream_t st) {
+  if (!graph || ctx->prof || max_iter < 1) {
+    for (int it = 0; it < max_iter; ++it)
+      RETURN_IF(run_estep(ctx, pl, bd, nullptr, nullptr, (double *)ctx->trace.p, stride, 1, st));
+    return LSGCPD_OK;
+  }
+  if (!ctx->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+    for (hipEvent_t &e : ctx->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  std::vector<int64_t> sig = {pl.npairs, pl.backend, pl.cull, pl.groups, pl.tiles, pl.items,
+                              pl.fins, pl.list_ints, max_iter, stride};
+  for (const lsg::Slot &sl : pl.slots) {
+    sig.push_back(sl.N);
+    sig.push_back(sl.M);
+  }
+  for (const Buf *b : {&ctx->plan, &ctx->partial, &ctx->blockstats, &ctx->rec, &ctx->pts,
+                       &ctx->boxes, &ctx->states, &ctx->trace, &ctx->tables})
+    sig.push_back((int64_t)(intptr_t)b->p);
+  hipStream_t gs = ctx->gstream;
+  HIPCHK(hipEventRecord(ctx->gev[0], st));
+  HIPCHK(hipStreamWaitEvent(gs, ctx->gev[0], 0));
+  if (!ctx->gexec || sig != ctx->gsig) {
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+    ctx->gsig.clear();
+    HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    lsgcpd_status s = LSGCPD_OK;
+    for (int it = 0; it < max_iter && s == LSGCPD_OK; ++it)
+      s = run_estep(ctx, pl, bd, nullptr, nullptr, (double *)ctx->trace.p, stride, 1, gs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(gs, &g);
+    if (s != LSGCPD_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return s != LSGCPD_OK ? s
+                            : fail(ctx, LSGCPD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    ctx->graph = g;
+    HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    ctx->gsig = sig;
+  }
+  HIPCHK(hipGraphLaunch(ctx->gexec, gs));
+  HIPCHK(hipEventRecord(ctx->gev[1], gs));
+  HIPCHK(hipStreamWaitEvent(st, ctx->gev[1], 0));
+  return LSGCPD_OK;
+}
+
 // E-step workspace and the tables of the plan (uploaded on `st`).
 lsgcpd_status ensure_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl) {
   ENSURE(plan, lsg::estep_plan_bytes(pl));
@@ -492,8 +556,7 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
                             p->V > 0.0 ? 0 : 1, s2_auto, st));
   }
   RETURN_IF(prof_reserve(ctx, p->max_iter));
-  for (int it = 0; it < p->max_iter; ++it)
-    RETURN_IF(run_estep(ctx, pl, bd, nullptr, nullptr, (double *)ctx->trace.p, stride, 1, st));
+  RETURN_IF(run_em(ctx, pl, bd, p->max_iter, stride, (p->flags & LSGCPD_GRAPH) != 0, st));
   HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, (size_t)npairs * sizeof(DevState),
                         hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -586,6 +649,11 @@ LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->hstate) (void)hipHostFree(c->hstate);
   if (c->hcount) (void)hipHostFree(c->hcount);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (hipEvent_t e : c->gev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   delete c;
 }
 
