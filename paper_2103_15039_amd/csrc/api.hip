@@ -53,6 +53,8 @@ struct lsgcpd_ctx {
   DevState *hstate = nullptr;  // pinned host staging for hcap states
   size_t hcap = 0;
   std::vector<char> htables;   // host copy of the batch tables
+  char *htab_pinned = nullptr; // pinned staging of that copy (an asynchronous upload)
+  size_t htab_cap = 0;
   std::vector<double> htrace;
   // E-step timing: 4 events per E step (start, before and after the pair
   // kernel, end)
@@ -464,8 +466,22 @@ lsgcpd_status ensure_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl) {
 lsgcpd_status upload_tables(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, hipStream_t st,
                             lsg::BatchDev *bd) {
   lsg::batch_tables_pack(pl, ctx->htables);
-  HIPCHK(hipMemcpyAsync(ctx->tables.p, ctx->htables.data(), ctx->htables.size(),
-                        hipMemcpyHostToDevice, st));
+  const size_t n = ctx->htables.size();
+  if (ctx->htab_cap < n) {
+    // the previous upload from the staging buffer has completed: every call
+    // synchronises its stream before returning
+    if (ctx->htab_pinned) (void)hipHostFree(ctx->htab_pinned);
+    ctx->htab_pinned = nullptr;
+    ctx->htab_cap = 0;
+    if (hipHostMalloc((void **)&ctx->htab_pinned, n, hipHostMallocDefault) != hipSuccess) {
+      ctx->htab_pinned = nullptr;
+      (void)hipGetLastError();
+      return fail(ctx, LSGCPD_E_NOMEM, "pinned staging of %zu bytes failed", n);
+    }
+    ctx->htab_cap = n;
+  }
+  memcpy(ctx->htab_pinned, ctx->htables.data(), n);
+  HIPCHK(hipMemcpyAsync(ctx->tables.p, ctx->htab_pinned, n, hipMemcpyHostToDevice, st));
   *bd = lsg::batch_tables_view(pl, ctx->tables.p);
   return LSGCPD_OK;
 }
@@ -649,6 +665,7 @@ LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->hstate) (void)hipHostFree(c->hstate);
   if (c->hcount) (void)hipHostFree(c->hcount);
+  if (c->htab_pinned) (void)hipHostFree(c->htab_pinned);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (hipEvent_t e : c->gev)
