@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 40          # FP64 flops per evaluated (m, n) pair
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
+PEAK_FP32 = 157.3e12         # MI355X FP32 vector (packed), FLOP/s
+CREDIT_FP32 = 38             # flops per (m, n) pair of the method in FP32 accounting
 EM_ITERS = 50
 
 
@@ -87,6 +89,32 @@ def copy_kernel(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_kernel_bytes_read": n * 4, "copy_kernel_bytes_written": n * 4,
                       "launches": 3}), flush=True)
+
+
+def gpu_clock():
+    """Shader and memory clocks as rocm-smi reports them (best effort; None if
+    rocm-smi is unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=30)
+        j = json.loads(r.stdout)
+        card = j[sorted(j)[0]]
+        return {k: v for k, v in card.items() if "sclk" in k.lower() or "mclk" in k.lower()}
+    except Exception:
+        return None
+
+
+def launch_stats(us, per_step):
+    """Median, p10 and p90 of per-E-step times over EM iterations 2..50 of
+    every timed registration (the first E step of each is left out)."""
+    import numpy as np
+    us = np.asarray(us)
+    keep = us[np.arange(len(us)) % per_step != 0] if len(us) else us
+    if len(keep) == 0:
+        return None
+    return {"median": float(np.median(keep)), "p10": float(np.percentile(keep, 10)),
+            "p90": float(np.percentile(keep, 90)), "n": int(len(keep))}
 
 
 def cpu_baseline(p, nrm, alpha):
@@ -301,8 +329,11 @@ def main():
         L.register(X, Y, **kw)
     torch.cuda.synchronize()
     dt_prof = time.perf_counter() - t1
+    pair_us, estep_us = L.profile_launches()
     prof = L.profile_read(reset=True)
     L.profile_enable(False)
+    est = launch_stats(estep_us, EM_ITERS)
+    pst = launch_stats(pair_us, EM_ITERS)
 
     pairs_per_step = M * N * EM_ITERS
     value = pairs_per_step * a.steps / dt
@@ -333,6 +364,11 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic},
         "estep": {"pair_kernel_ms": k_ms, "estep_ms": e_ms,
                   "ms_per_step_with_events": dt_prof / a.steps * 1e3,
+                  "estep_us_iters_2_50": est, "pair_kernel_us_iters_2_50": pst,
+                  "m1_pair_evals_per_s": M * N / (est["median"] * 1e-6) if est else None,
+                  "m1_credited_fp32_frac":
+                      M * N / (est["median"] * 1e-6) * CREDIT_FP32 / PEAK_FP32 if est else None,
+                  "gpu_clock": gpu_clock(),
                   "evaluated_frac": evaluated / (M * N),
                   "pair_kernel_pair_evals_per_s": M * N / (k_ms * 1e-3),
                   "estep_pair_evals_per_s": M * N / (e_ms * 1e-3),

@@ -301,8 +301,15 @@ typedef struct {
 } lsgcpd_profile;
 
 lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on);
-/* Copies the totals into *out (may be NULL) and, if reset != 0, zeroes them. */
+/* Copies the totals into *out (may be NULL) and, if reset != 0, zeroes them
+ * and forgets the per-launch times below. */
 lsgcpd_status lsgcpd_profile_read(lsgcpd_ctx *ctx, lsgcpd_profile *out, int reset);
+/* The times (a) and (b), in microseconds, of every timed E step since the
+ * last reset, in launch order: the first min(cap, *count) go to the HOST
+ * arrays pair_us and estep_us; *count (may be NULL) receives how many there
+ * are. */
+lsgcpd_status lsgcpd_profile_launches(lsgcpd_ctx *ctx, double *pair_us, double *estep_us,
+                                      int64_t cap, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
            "lsgcpd_ctx_destroy", "lsgcpd_last_error", "lsgcpd_params_default",
            "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_register_batch",
            "lsgcpd_depth_confidence", "lsgcpd_register_cf", "lsgcpd_autotune",
-           "lsgcpd_profile_enable", "lsgcpd_profile_read")
+           "lsgcpd_profile_enable", "lsgcpd_profile_read", "lsgcpd_profile_launches")
 ABI_VERSION = 4
 
 
@@ -125,6 +125,9 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_profile_enable.argtypes = [vp, C.c_int]
     lib.lsgcpd_profile_read.restype = C.c_int
     lib.lsgcpd_profile_read.argtypes = [vp, C.POINTER(Profile), C.c_int]
+    lib.lsgcpd_profile_launches.restype = C.c_int
+    lib.lsgcpd_profile_launches.argtypes = [vp, C.POINTER(d), C.POINTER(d), i64,
+                                            C.POINTER(i64)]
     _lib = lib
     return lib
 
@@ -457,3 +460,17 @@ def profile_read(reset=True, device=0):
     _check(load_library().lsgcpd_profile_read(ctx, C.byref(p), 1 if reset else 0), ctx)
     return {"launches": p.launches, "pairs": p.pairs, "pair_kernel_ms": p.pair_kernel_ms,
             "estep_ms": p.estep_ms, "evaluated_pairs": p.evaluated_pairs}
+
+
+def profile_launches(device=0):
+    """Per-E-step times since the last reset, in launch order: two numpy
+    arrays (pair kernel, whole E step) in microseconds
+    (lsgcpd_profile_launches).  Read them before profile_read(reset=True)."""
+    ctx = context(device)
+    lib = load_library()
+    n = C.c_int64(0)
+    _check(lib.lsgcpd_profile_launches(ctx, None, None, 0, C.byref(n)), ctx)
+    a = (C.c_double * max(n.value, 1))()
+    b = (C.c_double * max(n.value, 1))()
+    _check(lib.lsgcpd_profile_launches(ctx, a, b, n.value, C.byref(n)), ctx)
+    return np.array(a[:n.value]), np.array(b[:n.value])

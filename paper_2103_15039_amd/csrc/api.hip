@@ -63,6 +63,7 @@ struct lsgcpd_ctx {
   int ev_used = 0;
   int64_t prof_pairs_pending = 0;
   lsgcpd_profile totals = {0, 0, 0.0, 0.0, 0};
+  std::vector<double> launch_pair_us, launch_estep_us;  // per timed E step, in order
 };
 
 namespace {
@@ -354,6 +355,8 @@ lsgcpd_status prof_collect(lsgcpd_ctx *ctx, int64_t evaluated) {
     HIPCHK(hipEventElapsedTime(&b, ctx->events[i], ctx->events[i + 3]));
     ctx->totals.pair_kernel_ms += a;
     ctx->totals.estep_ms += b;
+    ctx->launch_pair_us.push_back(1e3 * a);
+    ctx->launch_estep_us.push_back(1e3 * b);
     ctx->totals.launches += 1;
   }
   ctx->totals.pairs += ctx->prof_pairs_pending;
@@ -970,6 +973,25 @@ LSG_API lsgcpd_status lsgcpd_profile_enable(lsgcpd_ctx *ctx, int on) {
 LSG_API lsgcpd_status lsgcpd_profile_read(lsgcpd_ctx *ctx, lsgcpd_profile *out, int reset) {
   if (!ctx) return LSGCPD_E_INVALID;
   if (out) *out = ctx->totals;
-  if (reset) ctx->totals = lsgcpd_profile{0, 0, 0.0, 0.0, 0};
+  if (reset) {
+    ctx->totals = lsgcpd_profile{0, 0, 0.0, 0.0, 0};
+    ctx->launch_pair_us.clear();
+    ctx->launch_estep_us.clear();
+  }
+  return LSGCPD_OK;
+}
+
+LSG_API lsgcpd_status lsgcpd_profile_launches(lsgcpd_ctx *ctx, double *pair_us, double *estep_us,
+                                              int64_t cap, int64_t *count) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (cap < 0 || (cap > 0 && (!pair_us || !estep_us)))
+    return fail(ctx, LSGCPD_E_INVALID, "NULL output arrays");
+  const int64_t n = (int64_t)ctx->launch_pair_us.size();
+  const int64_t k = n < cap ? n : cap;
+  for (int64_t i = 0; i < k; ++i) {
+    pair_us[i] = ctx->launch_pair_us[i];
+    estep_us[i] = ctx->launch_estep_us[i];
+  }
+  if (count) *count = n;
   return LSGCPD_OK;
 }
