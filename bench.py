@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch workloads: skip the one-by-one registrations")
+    ap.add_argument("--cpu-report", action="store_true",
+                    help="only time the FP64 C oracle's E step on the three single-pair "
+                         "workloads (all host cores and one) and a full 2,000-point "
+                         "registration; no GPU")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pair-kernel launch "
                          "(default: profiles/estep_pairs_<workload>_traffic.json)")
@@ -281,8 +285,69 @@ def cf_main(a):
     print(json.dumps(out), flush=True)
 
 
+def cpu_report():
+    """The oracle on the host: one full FP64 E step of each single-pair
+    workload with all cores (the LiDAR pair: 3 E steps), the RGB-D E step on
+    one core (a 2,000-source slice, scaled), and the full 2,000 x 2,000
+    registration (50 iterations, C E step)."""
+    import platform
+    import numpy as np
+    import datagen
+    from oracle import c_oracle as CO
+    from oracle import lsgcpd_oracle as O
+    CO.build()
+    model = platform.processor()
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                 if l.startswith("model name")][0]
+    except Exception:
+        pass
+    allc = CO.threads()
+    out = {"cpu_model": model, "threads": allc, "nproc": os.cpu_count(), "estep": {}}
+    rng = np.random.default_rng(0)
+    for name in ("range_scanner_2000x2000", "rgbd_20000x20000", "lidar_100000x50000"):
+        p = datagen.WORKLOADS[name](trial=0)
+        M, N = len(p.Y), len(p.X)
+        nrm = rng.normal(size=(M, 3))
+        nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+        al = rng.uniform(0.0, 30.0, size=M).astype(np.float32)
+        R, t = np.eye(3), np.zeros(3)
+        s2 = CO.sigma2_init(p.X, p.Y, R, t)
+        V = O.working_volume(p.Y)
+        reps = 3 if name.startswith("lidar") else 1
+        CO.set_threads(allc)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            CO.estep_columns(p.X, p.Y, nrm, al, R, t, s2, w0=0.1, V=V)
+        dt = (time.perf_counter() - t0) / reps
+        rec = {"pairs": M * N, "seconds": dt, "pair_evals_per_s_all_cores": M * N / dt}
+        if name.startswith("rgbd"):
+            CO.set_threads(1)
+            Xs = p.X[:2000]
+            t0 = time.perf_counter()
+            CO.estep_columns(Xs, p.Y, nrm, al, R, t, s2, w0=0.1, V=V)
+            d1 = time.perf_counter() - t0
+            rec["pair_evals_per_s_one_core"] = M * len(Xs) / d1
+            CO.set_threads(allc)
+        out["estep"][name] = rec
+        print(f"# {name}: {rec}", file=sys.stderr, flush=True)
+    p = datagen.range_scanner_pair(trial=0)
+    t0 = time.perf_counter()
+    nrm, _, al = O.normals(p.Y, 10, 30.0, 0.2)
+    fn = CO.register_columns_fn(p.X, p.Y, nrm.astype(np.float32), al.astype(np.float32), 0.1,
+                                O.working_volume(p.Y))
+    r = O.register(p.X, p.Y, k=10, max_iter=EM_ITERS, target_normals=nrm, target_alpha=al,
+                   estep_columns=fn)
+    out["register_range_scanner_2000x2000_s"] = time.perf_counter() - t0
+    out["register_rot_err_deg"] = float(O.rotation_error_deg(r.R, p.R_gt))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
+    if a.cpu_report:
+        cpu_report()
+        return
     if a.copy_kernel:
         copy_kernel(a.copy_kernel)
         return

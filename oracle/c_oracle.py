@@ -40,6 +40,8 @@ def lib():
         L.oracle_knn.restype = None
         L.oracle_knn.argtypes = [vp, i64, C.c_int, vp, i64, vp]
         L.oracle_threads.restype = C.c_int
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -50,6 +52,11 @@ def _p(a):
 
 def threads():
     return lib().oracle_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of the later calls (for timing runs)."""
+    lib().oracle_set_threads(int(n))
 
 
 def estep_columns(X, Y, normals, alpha, R, t, sigma2, w0=0.1, V=None, pi=None, w=None,

@@ -35,6 +35,15 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Threads of the later calls (timing runs: all cores, or one). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static double dmah(const double *x, const float *y, const float *nrm, double a) {
   const double r0 = x[0] - (double)y[0], r1 = x[1] - (double)y[1], r2 = x[2] - (double)y[2];
   const double p = (double)nrm[0] * r0 + (double)nrm[1] * r1 + (double)nrm[2] * r2;

@@ -223,3 +223,42 @@ def test_estep_invalid_arguments():
     with pytest.raises(L.LsgcpdError) as ei:
         L.estep(*args, 2.0 * np.eye(3), np.zeros(3), 1e-3)
     assert ei.value.status == L.E_INVALID
+
+
+def test_size_limits_rejected_before_any_device_access():
+    # sizes above the limits (2^27 points, 65,536 pairs) or below 1 are
+    # refused by the argument checks, before the library touches the arrays
+    import ctypes as C
+    lib = L.load_library()
+    ctx = L.context(0)
+    X, Y = dev(np.zeros((4, 3))), dev(np.zeros((4, 3)))
+    p = L.default_params()
+    p.k = 3
+    out, rep = L.Pose(), L.Report()
+    st = L._stream(0)
+    big = (1 << 27) + 1
+    for n, m in ((big, 4), (4, big), (0, 4), (4, 0)):
+        s = lib.lsgcpd_register(ctx, L._ptr(X), n, L._ptr(Y), m, C.byref(p), None,
+                                C.byref(out), C.byref(rep), None, st)
+        assert s == L.E_INVALID, (n, m)
+    eo = L.EstepOut()
+    pose = L._pose(np.eye(3), np.zeros(3))
+    s = lib.lsgcpd_estep(ctx, L._ptr(X), big, L._ptr(Y), L._ptr(Y), L._ptr(Y), 4, None, None,
+                         0.1, 0.0, C.byref(pose), 1e-3, 0, C.byref(eo), None, None, st)
+    assert s == L.E_INVALID
+    # batches: pair count and total size
+    xs = (C.c_void_p * 2)(L._ptr(X), L._ptr(X))
+    ys = (C.c_void_p * 2)(L._ptr(Y), L._ptr(Y))
+    outs, reps = (L.Pose * 2)(), (L.Report * 2)()
+    for npairs, nn, mm in ((0, [4, 4], [4, 4]), (65537, [4, 4], [4, 4]),
+                           (2, [1 << 26, 1 << 26], [4, 4])):
+        na = (C.c_int64 * 2)(*nn)
+        ma = (C.c_int64 * 2)(*mm)
+        s = lib.lsgcpd_register_batch(ctx, npairs, C.cast(xs, C.c_void_p), C.cast(na, C.c_void_p),
+                                      C.cast(ys, C.c_void_p), C.cast(ma, C.c_void_p), C.byref(p),
+                                      None, outs, reps, st)
+        assert s == L.E_INVALID, npairs
+    # the library still works afterwards
+    r = L.register(X + dev(np.random.default_rng(0).normal(size=(4, 3))),
+                   Y + dev(np.random.default_rng(1).normal(size=(4, 3))), k=3, max_iter=3)
+    assert np.isfinite(r.sigma2)
