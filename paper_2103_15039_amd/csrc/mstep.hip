@@ -14,8 +14,9 @@
 // the pose, sigma^2 = D(G_new) / (3 N_P) (Sec. 3.5, last paragraph).
 // reduce_stats sums the block statistics with one block per statistic and
 // problem; reduce_mstep runs the Newton iteration of each problem of a batch
-// in one block, whose threads share the 12 x 12 products while thread 0 does
-// the 6 x 6 Cholesky solve and the exponential map.
+// in one block, whose threads share the 12 x 12 products and the entries of
+// the gradient and Hessian while thread 0 does the 6 x 6 Cholesky solve and
+// the exponential map.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -38,9 +39,12 @@ __device__ void se3_exp(const double xi[6], double Rx[3][3], double tx[3]) {
     B = 0.5 - th2 / 24.0;
     C = 1.0 / 6.0 - th2 / 120.0;
   } else {
-    A = sin(th) / th;
-    B = (1.0 - cos(th)) / th2;
-    C = (th - sin(th)) / (th2 * th);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double it = 1.0 / th, it2 = it * it;
+    A = sn * it;
+    B = (1.0 - cs) * it2;
+    C = (th - sn) * (it2 * it);
   }
   const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
   double W2[3][3];
@@ -71,9 +75,11 @@ __device__ void compose(const double *g, const double xi[6], double *gout) {
   }
 }
 
-// Cholesky solve of the 6x6 system A x = -g; false if A is not positive definite.
+// Cholesky solve of the 6x6 system A x = -g; false if A is not positive
+// definite.  One reciprocal per column: the divisions are the long-latency
+// steps of this serial code.
 __device__ bool chol_solve6(const double A[6][6], const double g[6], double x[6]) {
-  double L[6][6];
+  double L[6][6], inv[6];
   for (int i = 0; i < 6; ++i)
     for (int j = 0; j < 6; ++j) L[i][j] = 0.0;
   for (int j = 0; j < 6; ++j) {
@@ -81,22 +87,23 @@ __device__ bool chol_solve6(const double A[6][6], const double g[6], double x[6]
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
     if (!(d > 0.0)) return false;
     L[j][j] = sqrt(d);
+    inv[j] = 1.0 / L[j][j];
     for (int i = j + 1; i < 6; ++i) {
       double s = A[i][j];
       for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-      L[i][j] = s / L[j][j];
+      L[i][j] = s * inv[j];
     }
   }
   double y[6];
   for (int i = 0; i < 6; ++i) {
     double s = -g[i];
     for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-    y[i] = s / L[i][i];
+    y[i] = s * inv[i];
   }
   for (int i = 5; i >= 0; --i) {
     double s = y[i];
     for (int k = i + 1; k < 6; ++k) s -= L[k][i] * x[k];
-    x[i] = s / L[i][i];
+    x[i] = s * inv[i];
   }
   return true;
 }
@@ -112,6 +119,8 @@ struct MSh {
   double HJ[6][12];
   double Hg[12];
   double GN[6][6];
+  double Q[3][3], w[3];   // R^T (H g - b), split as the second-order term uses it
+  double Hs[6][6], Hgn[6][6], grad[6];
   double xi[6];
   double cur, val, step;
   int go;             // 1 while Newton continues
@@ -186,15 +195,29 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
                                                     int mode) {
   const int pidx = blockIdx.x;
   DevState *s = states + pidx;
-  if (s->done) return;
+  const int tid = threadIdx.x;
+  // every value of the state this kernel reads, loaded together (the done
+  // flag included) before the first write to the state, which would order
+  // later loads after it: one round trip instead of a chain of them
+  const int done = s->done;
   const int N = slots[pidx].N;
+  const double sigma2 = s->sigma2, V = s->V, tol = s->tol, nll_prev = s->nll_prev;
+  const double sigma2_floor = s->sigma2_floor;
+  const int it0 = s->iter, newton_max = s->newton_max;
+  const double stat = tid < kStats ? s->stats[tid] : 0.0;
+  double g0 = 0.0;
+  if (tid < 12) {
+    const int a = tid >> 2, j = tid & 3;
+    g0 = j < 3 ? s->R[3 * a + j] : s->t[a];
+  }
+  const unsigned long long evc = evcounts && tid == 0 ? evcounts[pidx] : 0ull;
+  if (done) return;
   double *trace = traces ? traces + (size_t)pidx * trace_stride : nullptr;
-  if (evcounts && threadIdx.x == 0) s->evaluated_pairs += (int64_t)evcounts[pidx];
+  if (evcounts && tid == 0) s->evaluated_pairs += (int64_t)evc;
   __shared__ double S[kStats];
   __shared__ MSh m;
   __shared__ double rowbuf[12];
-  const int tid = threadIdx.x;
-  if (tid < kStats) S[tid] = s->stats[tid];
+  if (tid < kStats) S[tid] = stat;
   __syncthreads();
   // the quadratic and the pose
   for (int e = tid; e < 144; e += blockDim.x) {
@@ -206,27 +229,25 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
   }
   if (tid < 12) {
     m.b[tid] = S[70 + tid];
-    const int a = tid >> 2, j = tid & 3;
-    m.g[tid] = j < 3 ? s->R[3 * a + j] : s->t[a];
+    m.g[tid] = g0;
   }
   if (tid == 0) m.c = S[82];
   __syncthreads();
 
-  const double sigma2 = s->sigma2;
   const double inv_s2 = 1.0 / sigma2;
   const double Np = S[9];
   const double nll = -(S[85] + S[83] - 1.5 * (double)N * log(kTwoPi * sigma2));
   double cur = block_quad(m, m.g, rowbuf);
   if (tid == 0) {
-    s->gamma = pow(kTwoPi * sigma2, 1.5) / s->V;
+    s->gamma = pow(kTwoPi * sigma2, 1.5) / V;
     s->nll = nll;
     s->pd = cur;
     m.cur = cur;
     m.go = Np > 0.0 ? 1 : 0;
     if (mode == 1) {
-      const int it = s->iter;
+      const int it = it0;
       if (trace) trace[it] = nll;
-      if (s->tol > 0.0 && it > 0 && fabs(nll - s->nll_prev) <= s->tol * fabs(nll)) {
+      if (tol > 0.0 && it > 0 && fabs(nll - nll_prev) <= tol * fabs(nll)) {
         s->done = 1;
         s->converged = 1;
         m.go = -1;
@@ -243,7 +264,7 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
   if (m.go < 0) return;  // EM stopped by the tolerance (uniform)
 
   int iters = 0, gnf = 0;
-  for (int itn = 0; itn < s->newton_max && m.go == 1; ++itn) {
+  for (int itn = 0; itn < newton_max && m.go == 1; ++itn) {
     ++iters;
     // generators J_i = vec(G E_i): rotation i -> [R [e_i]x | 0], translation i -> [0 | R e_i]
     if (tid < 72) {
@@ -276,56 +297,62 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
       double acc = 0.0;
       for (int r = 0; r < 12; ++r) acc = fma(m.J[i][r], m.HJ[j][r], acc);
       m.GN[i][j] = acc;
+    } else if (tid >= 64 && tid < 76) {
+      // V = H g - b;  Q = R^T V[:, 0:3],  w = R^T V[:, 3]
+      const int e = tid - 64;
+      if (e < 9) {
+        const int l = e / 3, k = e % 3;
+        m.Q[l][k] = m.g[l] * (m.Hg[k] - m.b[k]) + m.g[4 + l] * (m.Hg[4 + k] - m.b[4 + k]) +
+                    m.g[8 + l] * (m.Hg[8 + k] - m.b[8 + k]);
+      } else {
+        const int l = e - 9;
+        m.w[l] = m.g[l] * (m.Hg[3] - m.b[3]) + m.g[4 + l] * (m.Hg[7] - m.b[7]) +
+                 m.g[8 + l] * (m.Hg[11] - m.b[11]);
+      }
+    }
+    __syncthreads();
+    // gradient and symmetrised Hessian, one entry per thread.  Second-order
+    // term 2 <V, G (E_i E_j + E_j E_i)/2>: rot-rot Q_ij + Q_ji - 2 delta_ij tr Q,
+    // rot i / trans j  w . (e_i x e_j)
+    if (tid < 36) {
+      const int i = tid / 6, j = tid % 6;
+      double t2 = 0.0;
+      if (i < 3 && j < 3) {
+        const double trQ = m.Q[0][0] + m.Q[1][1] + m.Q[2][2];
+        t2 = m.Q[i][j] + m.Q[j][i] - (i == j ? 2.0 * trQ : 0.0);
+      } else if ((i < 3) != (j < 3)) {
+        const int ir = i < 3 ? i : j, jt = (i < 3 ? j : i) - 3;
+        if (ir != jt) {
+          const int k = 3 - ir - jt;
+          t2 = ((jt - ir + 3) % 3 == 1 ? 1.0 : -1.0) * m.w[k];
+        }
+      }
+      const double gn = 0.5 * (m.GN[i][j] + m.GN[j][i]);
+      m.Hgn[i][j] = 2.0 * gn * inv_s2;
+      m.Hs[i][j] = (2.0 * gn + t2) * inv_s2;
+    } else if (tid >= 64 && tid < 70) {
+      const int i = tid - 64;
+      m.grad[i] = i < 3 ? 2.0 * (m.Q[(i + 2) % 3][(i + 1) % 3] - m.Q[(i + 1) % 3][(i + 2) % 3]) *
+                              inv_s2
+                        : 2.0 * m.w[i - 3] * inv_s2;
     }
     __syncthreads();
     if (tid == 0) {
-      // V = H g - b;  Q = R^T V[:, 0:3],  w = R^T V[:, 3]
-      double V[12], Q[3][3], w[3];
-      for (int r = 0; r < 12; ++r) V[r] = m.Hg[r] - m.b[r];
-      for (int l = 0; l < 3; ++l) {
-        for (int k = 0; k < 3; ++k)
-          Q[l][k] = m.g[l] * V[k] + m.g[4 + l] * V[4 + k] + m.g[8 + l] * V[8 + k];
-        w[l] = m.g[l] * V[3] + m.g[4 + l] * V[7] + m.g[8 + l] * V[11];
-      }
-      double grad[6], Hs[6][6], Hg[6][6];
-      grad[0] = 2.0 * (Q[2][1] - Q[1][2]) * inv_s2;
-      grad[1] = 2.0 * (Q[0][2] - Q[2][0]) * inv_s2;
-      grad[2] = 2.0 * (Q[1][0] - Q[0][1]) * inv_s2;
-      for (int i = 0; i < 3; ++i) grad[3 + i] = 2.0 * w[i] * inv_s2;
-      // second-order term 2 <V, G (E_i E_j + E_j E_i)/2>:
-      //   rot-rot Q_ij + Q_ji - 2 delta_ij tr Q,  rot i / trans j  w . (e_i x e_j)
-      const double trQ = Q[0][0] + Q[1][1] + Q[2][2];
-      for (int i = 0; i < 6; ++i)
-        for (int j = 0; j < 6; ++j) {
-          double t2 = 0.0;
-          if (i < 3 && j < 3) {
-            t2 = Q[i][j] + Q[j][i] - (i == j ? 2.0 * trQ : 0.0);
-          } else if ((i < 3) != (j < 3)) {
-            const int ir = i < 3 ? i : j, jt = (i < 3 ? j : i) - 3;
-            if (ir != jt) {
-              const int k = 3 - ir - jt;
-              t2 = ((jt - ir + 3) % 3 == 1 ? 1.0 : -1.0) * w[k];
-            }
-          }
-          const double gn = 0.5 * (m.GN[i][j] + m.GN[j][i]);
-          Hg[i][j] = 2.0 * gn * inv_s2;
-          Hs[i][j] = (2.0 * gn + t2) * inv_s2;
-        }
       if (itn == 0 && mode == 0) {
-        for (int i = 0; i < 6; ++i) s->grad[i] = grad[i];
+        for (int i = 0; i < 6; ++i) s->grad[i] = m.grad[i];
         for (int i = 0; i < 6; ++i)
-          for (int j = 0; j < 6; ++j) s->hess[6 * i + j] = Hs[i][j];
+          for (int j = 0; j < 6; ++j) s->hess[6 * i + j] = m.Hs[i][j];
       }
       double xi[6];
-      bool ok = chol_solve6(Hs, grad, xi);
+      bool ok = chol_solve6(m.Hs, m.grad, xi);
       if (!ok) {
         ++gnf;
-        ok = chol_solve6(Hg, grad, xi);
+        ok = chol_solve6(m.Hgn, m.grad, xi);
         if (!ok) {
           double mx = 0.0;
-          for (int i = 0; i < 6; ++i) mx = fmax(mx, Hg[i][i]);
-          for (int i = 0; i < 6; ++i) Hg[i][i] += 1e-10 * mx + 1e-300;
-          ok = chol_solve6(Hg, grad, xi);
+          for (int i = 0; i < 6; ++i) mx = fmax(mx, m.Hgn[i][i]);
+          for (int i = 0; i < 6; ++i) m.Hgn[i][i] += 1e-10 * mx + 1e-300;
+          ok = chol_solve6(m.Hgn, m.grad, xi);
         }
       }
       for (int i = 0; i < 6; ++i) m.xi[i] = ok ? xi[i] : 0.0;
@@ -380,7 +407,7 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
   }
   if (tid != 0) return;
   cur = m.cur;
-  const double s2n = Np > 0.0 ? fmax(cur / (3.0 * Np), s->sigma2_floor) : sigma2;
+  const double s2n = Np > 0.0 ? fmax(cur / (3.0 * Np), sigma2_floor) : sigma2;
   bool finite = isfinite(s2n);
   for (int r = 0; r < 12; ++r) finite = finite && isfinite(m.g[r]);
   s->newton_iters = iters;
