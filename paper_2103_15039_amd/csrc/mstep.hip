@@ -154,6 +154,11 @@ __device__ double block_quad(MSh &m, const double *v, double *rowbuf) {
   return tot;
 }
 
+// Problems with at most this many finalisation blocks (64 sources each) are
+// summed by reduce_mstep itself: for them a kernel of its own costs more in
+// launch latency than the sums.
+constexpr int kFewBlocks = 64;
+
 // Sum of row i of a problem's stat-major block statistics (one block per
 // statistic and problem, so that the reads are spread over many CUs): thread
 // t adds the partials t, t + 256, ... in order, then a fixed tree adds the
@@ -163,8 +168,8 @@ __global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slo
                                                      DevState *__restrict__ states) {
   const int p = blockIdx.x / kStats, i = blockIdx.x % kStats, tid = threadIdx.x;
   DevState *s = states + p;
-  if (s->done) return;
   const int nblk = slots[p].nfin;
+  if (s->done || nblk <= kFewBlocks) return;  // reduce_mstep sums those itself
   const double *row = blockstats + (size_t)kStats * slots[p].fin_off + (size_t)i * nblk;
   double a = 0.0;
   for (int c0 = 0; c0 < nblk; c0 += 8 * 256) {
@@ -189,6 +194,7 @@ __global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slo
 
 // The M step from the 86 statistics in s->stats.
 __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slots,
+                                                    const double *__restrict__ blockstats,
                                                     DevState *__restrict__ states,
                                                     double *__restrict__ traces, int trace_stride,
                                                     const unsigned long long *__restrict__ evcounts,
@@ -200,11 +206,26 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
   // flag included) before the first write to the state, which would order
   // later loads after it: one round trip instead of a chain of them
   const int done = s->done;
-  const int N = slots[pidx].N;
+  const int N = slots[pidx].N, nfin = slots[pidx].nfin, fin_off = slots[pidx].fin_off;
   const double sigma2 = s->sigma2, V = s->V, tol = s->tol, nll_prev = s->nll_prev;
   const double sigma2_floor = s->sigma2_floor;
   const int it0 = s->iter, newton_max = s->newton_max;
-  const double stat = tid < kStats ? s->stats[tid] : 0.0;
+  double stat = 0.0;
+  if (tid < kStats) {
+    if (nfin <= kFewBlocks) {
+      // the block partials of statistic tid, in order, the loads of 8 in flight
+      const double *row = blockstats + (size_t)kStats * fin_off + (size_t)tid * nfin;
+      for (int b0 = 0; b0 < nfin; b0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = b0 + k < nfin ? row[b0 + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) stat += v[k];
+      }
+    } else {
+      stat = s->stats[tid];
+    }
+  }
   double g0 = 0.0;
   if (tid < 12) {
     const int a = tid >> 2, j = tid & 3;
@@ -217,7 +238,10 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
   __shared__ double S[kStats];
   __shared__ MSh m;
   __shared__ double rowbuf[12];
-  if (tid < kStats) S[tid] = stat;
+  if (tid < kStats) {
+    S[tid] = stat;
+    if (nfin <= kFewBlocks) s->stats[tid] = stat;
+  }
   __syncthreads();
   // the quadratic and the pose
   for (int e = tid; e < 144; e += blockDim.x) {
@@ -473,9 +497,13 @@ __global__ void init_state(DevState *__restrict__ s, const double *__restrict__ 
 hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *blockstats,
                                DevState *s, double *nll_trace, int trace_stride,
                                const unsigned long long *evcounts, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_stats, dim3((unsigned)(kStats * pl.npairs)), dim3(256), 0, st,
-                     bd.slots, blockstats, s);
-  hipLaunchKernelGGL(reduce_mstep, dim3((unsigned)pl.npairs), dim3(256), 0, st, bd.slots, s,
+  bool many = false;
+  for (const Slot &sl : pl.slots) many = many || sl.nfin > kFewBlocks;
+  if (many)
+    hipLaunchKernelGGL(reduce_stats, dim3((unsigned)(kStats * pl.npairs)), dim3(256), 0, st,
+                       bd.slots, blockstats, s);
+  hipLaunchKernelGGL(reduce_mstep, dim3((unsigned)pl.npairs), dim3(256), 0, st, bd.slots,
+                     (const double *)blockstats, s,
                      nll_trace, trace_stride, evcounts, mode);
   return hipGetLastError();
 }

@@ -104,7 +104,9 @@ def test_register_tol_stop_and_backends():
     # spatially, which changes only the rounding of the sums
     d = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7, backend="dense")
     assert d.iters == g.iters and O.rotation_error_deg(d.R, g.R) < 1e-7
-    np.testing.assert_allclose(d.nll, g.nll, rtol=1e-12)
+    # the two sum the same terms in different groupings; over ~40 EM
+    # iterations that leaves the NLL traces ~1e-12 apart
+    np.testing.assert_allclose(d.nll, g.nll, rtol=1e-11)
     for backend in ("lds", "mfma"):
         v = L.register(dev(p.X), dev(p.Y), k=10, max_iter=60, tol=1e-7, backend=backend)
         assert v.iters == g.iters
