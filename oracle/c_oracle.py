@@ -84,16 +84,17 @@ def estep_columns(X, Y, normals, alpha, R, t, sigma2, w0=0.1, V=None, pi=None, w
     return cols, out[:, 0]
 
 
-def register_columns_fn(X, Y, normals, alpha, w0, V, exact_normalizer=False):
+def register_columns_fn(X, Y, normals, alpha, w0, V, exact_normalizer=False, pi=None, w=None):
     """An `estep_columns` callback for lsgcpd_oracle.register: the C E step
-    plus the negative log-likelihood of Eq. (4)."""
-    N = len(X)
+    plus the negative log-likelihood of Eq. (4).  pi / w: per-point priors and
+    outlier weights (None: 1/M and w0)."""
+    logw = np.log(w0) if w is None else np.log(np.asarray(w, np.float64))
 
     def fn(R, t, s2):
-        cols, ksum = estep_columns(X, Y, normals, alpha, R, t, s2, w0=w0, V=V,
+        cols, ksum = estep_columns(X, Y, normals, alpha, R, t, s2, w0=w0, V=V, pi=pi, w=w,
                                    exact_normalizer=exact_normalizer)
         gamma = (2.0 * np.pi * s2) ** 1.5 / V
-        nll = -float(np.sum(np.log(w0) + np.log(ksum + gamma) - 1.5 * np.log(2 * np.pi * s2)))
+        nll = -float(np.sum(logw + np.log(ksum + gamma) - 1.5 * np.log(2 * np.pi * s2)))
         return cols, nll
     return fn
 

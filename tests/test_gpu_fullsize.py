@@ -119,3 +119,36 @@ def test_register_full_size(name, iters):
     assert O.translation_error(g.t, o.t) <= 1e-5 * diag
     np.testing.assert_allclose(g.nll, o.nll, rtol=1e-6)
     assert g.sigma2 == pytest.approx(o.sigma2, rel=1e-4)
+
+
+def test_register_cf_full_size():
+    """Confidence filtering with truncation and w0 from the outlier ratio on
+    a full-size depth-camera pair (20,000 x 20,000 before truncation): the
+    kept points, w0 and 10 EM iterations against the oracle driven by the C E
+    step with the same priors and outlier weights."""
+    p = datagen.depth_pair(trial=0)
+    conf = lambda P: O.depth_confidence(P, datagen.DEPTH_ERROR,
+                                        datagen.DEPTH_ERROR_MIN).astype(np.float32)
+    phx, phy = conf(p.X), conf(p.Y)
+    thr, eta, iters, k = 0.05, 0.1, 10, 20
+    g = L.register_cf(dev(p.X), dev(p.Y), dev(phx), dev(phy), threshold=thr, k=k,
+                      max_iter=iters, eta=eta)
+    Xk, fx = O.truncate(p.X, phx, thr)
+    Yk, fy = O.truncate(p.Y, phy, thr)
+    assert (g.n_used, g.m_used) == (len(Xk), len(Yk))
+    n, a = _oracle_normals(Yk, k)
+    V = O.working_volume(Yk)
+    s20 = CO.sigma2_init(Xk, Yk, np.eye(3), np.zeros(3))
+    pi, _ = O.confidence_priors(fy, None, 0.1)
+    w0 = O.outlier_weight_max(eta, V, pi, a, s20)
+    _, w = O.confidence_priors(None, fx, w0)
+    o = O.register(Xk, Yk, max_iter=iters, target_normals=n, target_alpha=a, V=V,
+                   sigma2_0=s20,
+                   estep_columns=CO.register_columns_fn(Xk, Yk, n, a, w0, V, pi=pi, w=w))
+    diag = O.bbox_diag(Yk)
+    assert g.w0 == pytest.approx(w0, rel=1e-9)
+    assert g.iters == o.iters == iters
+    assert O.rotation_error_deg(g.R, o.R) <= 1e-3
+    assert O.translation_error(g.t, o.t) <= 1e-5 * diag
+    np.testing.assert_allclose(g.nll, o.nll, rtol=1e-6)
+    assert g.sigma2 == pytest.approx(o.sigma2, rel=1e-4)

@@ -65,3 +65,22 @@ def test_register_with_c_estep_equals_dense():
                    estep_columns=CO.register_columns_fn(p.X, p.Y, n, a, 0.1, V))
     assert O.rotation_error_deg(c.R, d.R) < 1e-9
     np.testing.assert_allclose(c.nll, d.nll, rtol=1e-11)
+
+
+def test_register_with_c_estep_and_confidences_equals_dense():
+    # confidence filtering through the C E step (per-point priors and outlier
+    # weights) against the NumPy oracle's own confidence filtering
+    p = datagen.depth_pair(trial=5, M=260, N=240)
+    phx = O.depth_confidence(p.X, datagen.DEPTH_ERROR, datagen.DEPTH_ERROR_MIN).astype(np.float32)
+    phy = O.depth_confidence(p.Y, datagen.DEPTH_ERROR, datagen.DEPTH_ERROR_MIN).astype(np.float32)
+    o = O.register(p.X, p.Y, k=10, max_iter=8, eta=0.1, phi_x=phx, phi_y=phy)
+    pi, _ = O.confidence_priors(phy, None, 0.1)
+    w0 = O.outlier_weight_max(0.1, o.V, pi, o.alpha, O.sigma2_init(p.X, p.Y, np.eye(3), np.zeros(3)))
+    _, w = O.confidence_priors(None, phx, w0)
+    n32, a32 = o.normals.astype(np.float32), o.alpha.astype(np.float32)
+    fn = CO.register_columns_fn(p.X, p.Y, n32, a32, w0, o.V, pi=pi, w=w)
+    c = O.register(p.X, p.Y, max_iter=8, target_normals=n32, target_alpha=a32, V=o.V,
+                   estep_columns=fn)
+    assert o.w0 == w0
+    assert O.rotation_error_deg(c.R, o.R) < 1e-6
+    np.testing.assert_allclose(c.nll, o.nll, rtol=1e-7)
