@@ -129,6 +129,15 @@ __device__ __forceinline__ void accumulate(const Src (&x)[S], const TRec &t, dou
   }
 }
 
+// Adds one target's contribution to one source of this lane.
+__device__ __forceinline__ void accumulate1(const Src &x, const TRec &t, double negsc,
+                                            double (&acc)[kFeatUsed]) {
+  const double e = rec_exp(x, t, negsc);
+  acc[0] += e;
+#pragma unroll
+  for (int c = 1; c < kFeatUsed; ++c) acc[c] = fma(e, t.f[c - 1], acc[c]);
+}
+
 // Exact culling.  For sources whose scaled positions lie in the box
 // [blo, bhi] and targets whose positions lie in [lo, hi] with log-priors
 // <= lmax, every pair has |r|^2 >= d2 = sum_a gap_a^2 (gap_a = distance between
@@ -175,6 +184,9 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 // groups to balance, more waves per SIMD) and than 1 on both benchmark pairs
 constexpr int kSrcPerLane = 2;
 constexpr int kGroup = 64 * kSrcPerLane;
+// Per source group: the boxes of its two halves of 64 sources (the sources
+// of slot 0 and slot 1 of the pair kernel's lanes), lo and hi each.
+constexpr int kGBox = 16;
 
 // Scaled-coordinate bounding box of each source group (kept for the pair
 // kernel), then the live tiles in increasing order.  One block per group of
@@ -223,21 +235,25 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
       bx[wave][3 + a] = hi[a];
     }
   __syncthreads();
+  // waves 0 and 1 hold the two halves (waves 2 and 3 hold no sources); a
+  // half without sources has an empty box, which no tile or target passes
+  double lo0[3], hi0[3], lo1[3], hi1[3];
   for (int a = 0; a < 3; ++a) {
-    lo[a] = fmin(fmin(bx[0][a], bx[1][a]), fmin(bx[2][a], bx[3][a]));
-    hi[a] = fmax(fmax(bx[0][3 + a], bx[1][3 + a]), fmax(bx[2][3 + a], bx[3][3 + a]));
+    lo0[a] = bx[0][a];
+    hi0[a] = bx[0][3 + a];
+    lo1[a] = bx[1][a];
+    hi1[a] = bx[1][3 + a];
   }
-  if (threadIdx.x == 0)
-    for (int a = 0; a < 3; ++a) {
-      gbox[b * 8 + a] = lo[a];
-      gbox[b * 8 + 3 + a] = hi[a];
-    }
+  if (threadIdx.x < 12) {
+    const int h = threadIdx.x / 6, c = threadIdx.x % 6;
+    gbox[(int64_t)b * kGBox + threadIdx.x] = bx[h][c];
+  }
   int *out = list + sl.list_off + (int64_t)g * ntiles;
   int base = 0;
   for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
     const int ti = t0 + threadIdx.x;
-    const bool live =
-        ti < ntiles && box_live(bx_t[ti].lo, bx_t[ti].hi, bx_t[ti].lmax, lo, hi, sc);
+    const bool live = ti < ntiles && (box_live(bx_t[ti].lo, bx_t[ti].hi, bx_t[ti].lmax, lo0, hi0, sc) ||
+                                      box_live(bx_t[ti].lo, bx_t[ti].hi, bx_t[ti].lmax, lo1, hi1, sc));
     const uint64_t bal = __ballot(live);
     if (lane == 0) wc[wave] = __popcll(bal);
     __syncthreads();
@@ -347,7 +363,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   const int cnt = CULL ? counts[sl.g_off + g] : ntiles;
   const int kn = cnt - k0 < L ? cnt - k0 : L;
   const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
-  const double *gbox = gboxes + (int64_t)(sl.g_off + g) * 8;
+  const double *gbox = gboxes + (int64_t)(sl.g_off + g) * kGBox;
   double R[9], t[3];
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
@@ -361,18 +377,21 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int c = 0; c < kFeatUsed; ++c) acc[s][c] = 0.0;
-  double blo[3], bhi[3];
+  double blo0[3], bhi0[3], blo1[3], bhi1[3];
   if constexpr (CULL)
     for (int a = 0; a < 3; ++a) {
-      blo[a] = gbox[a];
-      bhi[a] = gbox[3 + a];
+      blo0[a] = gbox[a];
+      bhi0[a] = gbox[3 + a];
+      blo1[a] = gbox[6 + a];
+      bhi1[a] = gbox[9 + a];
     }
   const int Mi = (int)M;  // M < 2^27: 32-bit scalar loop arithmetic
   // the wave's tiles are j = wave, wave + 4, ...; their indices are fetched 64
   // at a time, one per lane, and read back with readlane
   const int nt = kn > wave ? (kn - wave + 3) / 4 : 0;
   int tv = 0;
-  int done = 0;  // targets this wave evaluated
+  int done = 0;   // targets this wave evaluated (for every source of the group)
+  int done0 = 0, done1 = 0;  // the same for each half of the group (culled)
   if constexpr (CULL) {
     for (int q = 0; q < nt; ++q) {
       if ((q & 63) == 0) {
@@ -381,27 +400,28 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
       }
       const int ti = __builtin_amdgcn_readlane(tv, q & 63);
       const int n1 = Mi - ti * kCullTile < kCullTile ? Mi - ti * kCullTile : kCullTile;
-      // the tile's targets that the group box cannot rule out: one lane per
-      // target tests it, the ballot is the (wave-uniform) mask
-      bool on = false;
+      // the tile's targets that the boxes of the group's two halves cannot
+      // rule out: one lane per target tests it against both, and the two
+      // ballots are (wave-uniform) masks; each half of the lanes' sources
+      // takes only its own targets
+      bool on0 = false, on1 = false;
       if (lane < n1) {
         const TPt &p = pts[(int64_t)ti * kCullTile + lane];
-        on = box_live(p.y, p.y, p.l, blo, bhi, sc);
+        on0 = box_live(p.y, p.y, p.l, blo0, bhi0, sc);
+        on1 = box_live(p.y, p.y, p.l, blo1, bhi1, sc);
       }
-      uint64_t mk = __ballot(on);
-      done += __popcll(mk);
+      const uint64_t m0 = __ballot(on0), m1 = __ballot(on1);
+      done0 += __popcll(m0);
+      done1 += __popcll(m1);
       const TRec *tr = rec + (int64_t)ti * kCullTile;
-      // an empty mask visits the sentinel record rec[M] (exponent -inf, all
-      // features 0), which adds exact zeros; so the walk over the set bits is
-      // a do-while and one set of accumulators flows through it
-      if (mk == 0) {
-        mk = 1;
-        tr = rec + M;
-      }
-      do {
-        accumulate<S>(x, tr[__builtin_ctzll(mk)], negsc, acc);
-        mk &= mk - 1;
-      } while (mk);
+      // targets live for both halves go through the interleaved two-source
+      // path (its independent chains keep the FP64 pipeline full), the others
+      // through one source each
+      for (uint64_t mk = m0 & m1; mk; mk &= mk - 1) accumulate<S>(x, tr[__builtin_ctzll(mk)], negsc, acc);
+      for (uint64_t mk = m0 & ~m1; mk; mk &= mk - 1)
+        accumulate1(x[0], tr[__builtin_ctzll(mk)], negsc, acc[0]);
+      for (uint64_t mk = m1 & ~m0; mk; mk &= mk - 1)
+        accumulate1(x[1], tr[__builtin_ctzll(mk)], negsc, acc[1]);
     }
   } else {
     for (int q = 0; q < nt; ++q) {
@@ -417,8 +437,12 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
       } while (++m < n1);
     }
   }
-  __shared__ int wdone[4];
-  if (lane == 0) wdone[wave] = done;
+  __shared__ int wdone[3][4];
+  if (lane == 0) {
+    wdone[0][wave] = done;
+    wdone[1][wave] = done0;
+    wdone[2][wave] = done1;
+  }
   __shared__ double red[3][kFeatUsed][64];
   double *dst = partial + (size_t)b * kFeatUsed * kGroup;
 #pragma unroll
@@ -436,10 +460,15 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const unsigned long long nv =
-        (unsigned long long)(N - g * kGroup < kGroup ? N - g * kGroup : kGroup);
-    atomicAdd(evcounts + p,
-              nv * (unsigned long long)(wdone[0] + wdone[1] + wdone[2] + wdone[3]));
+    const int rest = N - g * kGroup;  // sources of the group: halves of nv0 and nv1
+    const unsigned long long nv = (unsigned long long)(rest < kGroup ? rest : kGroup);
+    const unsigned long long nv0 = (unsigned long long)(rest < 64 ? rest : 64);
+    const unsigned long long nv1 = (unsigned long long)(rest <= 64 ? 0 : rest < kGroup ? rest - 64 : 64);
+    const unsigned long long ev =
+        CULL ? nv0 * (unsigned long long)(wdone[1][0] + wdone[1][1] + wdone[1][2] + wdone[1][3]) +
+                   nv1 * (unsigned long long)(wdone[2][0] + wdone[2][1] + wdone[2][2] + wdone[2][3])
+             : nv * (unsigned long long)(wdone[0][0] + wdone[0][1] + wdone[0][2] + wdone[0][3]);
+    atomicAdd(evcounts + p, ev);
   }
 }
 
@@ -1022,7 +1051,7 @@ PlanPtrs plan_ptrs(const BatchPlan &pl, void *ws) {
   q.map = (int *)p;
   p += align256((size_t)pl.items * sizeof(int));
   q.gbox = (double *)p;
-  p += align256((size_t)pl.groups * 8 * sizeof(double));
+  p += align256((size_t)pl.groups * kGBox * sizeof(double));
   q.list = (int *)p;
   return q;
 }
@@ -1035,7 +1064,7 @@ size_t estep_plan_bytes(const BatchPlan &pl) {
          align256((size_t)pl.groups * sizeof(int)) +
          align256((size_t)(pl.groups + pl.npairs) * sizeof(int)) +
          align256((size_t)pl.items * sizeof(int)) +
-         align256((size_t)pl.groups * 8 * sizeof(double)) + (size_t)pl.list_ints * sizeof(int);
+         align256((size_t)pl.groups * kGBox * sizeof(double)) + (size_t)pl.list_ints * sizeof(int);
 }
 
 unsigned long long *estep_plan_counter(const BatchPlan &pl, void *plan_ws) {
