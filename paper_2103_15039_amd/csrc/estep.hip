@@ -339,15 +339,23 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
     const TPt *__restrict__ ptss, const CullHdr *__restrict__ hdrs,
     const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
     const int *__restrict__ list, const double *__restrict__ gboxes,
-    unsigned long long *__restrict__ evcounts, double *__restrict__ partial) {
+    unsigned long long *__restrict__ evcounts, double *__restrict__ partial, int xcd_remap) {
   constexpr int S = kSrcPerLane;
-  const int b = blockIdx.x;
-  const int p = item_slot[b];
+  const int p = item_slot[blockIdx.x];
   const DevState *st = states + p;
   if (st->done) return;
   const Slot &sl = slots[p];
-  const int item = b - sl.item_off;
-  if (item >= hdrs[p].items) return;
+  const int nitems = hdrs[p].items;
+  int item = blockIdx.x - sl.item_off;
+  if (item >= nitems) return;
+  if (xcd_remap) {
+    // one problem: blocks go to the 8 XCDs in turn, so block i runs on XCD
+    // i % 8; give each XCD a contiguous run of items (neighbouring sources
+    // and targets, whose records its own L2 then holds) instead of every 8th
+    const int x = item % 8, q = nitems / 8, r = nitems % 8;
+    item = x * q + (x < r ? x : r) + item / 8;
+  }
+  const int b = sl.item_off + item;
   // the wave index is wave-uniform; readfirstlane tells the compiler so, which
   // keeps the tile loop (and so the record loads) scalar
   const int lane = threadIdx.x & 63;
@@ -1095,11 +1103,11 @@ hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRe
     if (pl.cull)
       hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                          bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
-                         q.list, q.gbox, q.evcount, partial);
+                         q.list, q.gbox, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
     else
       hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                          bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
-                         q.list, q.gbox, q.evcount, partial);
+                         q.list, q.gbox, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
     return hipGetLastError();
   }
   // one problem: its records start at rec + 0
