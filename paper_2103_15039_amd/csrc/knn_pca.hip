@@ -131,29 +131,35 @@ __device__ __forceinline__ int tile_count(int M, int u) {
   return M - u * kKnnTileW < kKnnTileW ? M - u * kKnnTileW : kKnnTileW;
 }
 
-// Pass 1, wave (query tile t, split s of S).  After the own tile and its two
-// Morton neighbours every query has a current k-th distance tau.  Queries
-// whose tau is far above the wave's 75th percentile (isolated points such as
-// outliers) are "hard": they are listed for pass 2 and left out of the
-// culling, so that they do not widen the search of the whole wave; if the
-// other queries would still need more than kLiveCap * S tiles, the queries
-// with the largest tau are moved to the hard list, 4 at a time.  Every other
-// tile is scanned unless its box lies farther from the box of the wave's easy
-// queries than their largest tau, which is exact for those queries.  The S
-// waves of a query tile take every S-th live tile and write S partial lists.
+// Pass 1a, one wave per query tile t.  The own tile and its two Morton
+// neighbours give every query a first list and its current k-th distance
+// tau; the list is written as list 0.  Queries whose tau is far above the
+// wave's 75th percentile (isolated points such as outliers) are "hard": they
+// are listed for pass 2 and left out of the culling, so that they do not
+// widen the search of the whole wave; if the other queries would still need
+// more than kLiveCap * S tiles, the queries with the largest tau are moved to
+// the hard list, 4 at a time.  The box of the remaining ("easy") queries, the
+// largest tau among them (r20) and the mask of easy lanes are kept for pass 1b.
 constexpr int kLiveCap = 32;
 
+struct TileMeta {
+  TBoxF own;       // box of the easy queries
+  double r20;      // largest current k-th distance of the easy queries
+  uint64_t easy;   // lane mask of the easy queries
+};
+
 template <int KM>
-__global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict__ Ys, int M,
-                                                       int k, const TBoxF *__restrict__ boxes,
-                                                       int ntiles, int S,
-                                                       uint64_t *__restrict__ out,
-                                                       uint32_t *__restrict__ hard,
-                                                       unsigned int *__restrict__ nhard) {
+__global__ __launch_bounds__(kKnnBlock) void knn_seed(const float4 *__restrict__ Ys, int M,
+                                                      int k, const TBoxF *__restrict__ boxes,
+                                                      int ntiles, int S,
+                                                      uint64_t *__restrict__ out,
+                                                      TileMeta *__restrict__ meta,
+                                                      float *__restrict__ taus,
+                                                      uint32_t *__restrict__ hard,
+                                                      unsigned int *__restrict__ nhard) {
   const int lane = threadIdx.x & 63;
   const int t =
       __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kKnnBlock / 64) + (threadIdx.x >> 6)));
-  const int split = blockIdx.y;
   if (t >= ntiles) return;  // wave-uniform
   const int q = t * kKnnTileW + lane;
   const bool valid = q < M;
@@ -166,7 +172,6 @@ __global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict_
   }
   TopK<KM> top;
   top.init(k, make_key(INFINITY, kNoIndex));
-  // own tile and its two neighbours in Morton order give the first bounds
   {
     const float4 p0 = load_tile(Ys, M, t);
     const float4 pm = t > 0 ? load_tile(Ys, M, t - 1) : p0;
@@ -185,10 +190,6 @@ __global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict_
   }
   const uint64_t at = __ballot(valid && rank == (3 * nvalid) / 4);
   const float p75 = at ? lanef(tau, (int)__builtin_ctzll(at)) : INFINITY;
-  // the other S - 1 waves start again from sentinels at tau (no query's
-  // answer has a key above (tau, any index)), so that every candidate enters
-  // exactly one of the S lists
-  if (split != 0) top.init(k, make_key(tau, kNoIndex));
   // easy lanes: rank < h
   int h = __popcll(__ballot(valid && !(tau > 16.0f * p75)));
   TBoxF own;
@@ -224,14 +225,76 @@ __global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict_
     h -= 4;
   }
   const bool easy = valid && rank < h;
-  // scan: the live tiles other than the first three, every S-th to this wave.
-  // Which tiles are live, and so which wave owns which, is decided with the
-  // bound r20 after the first three tiles, which all S waves share; a wave
-  // also skips an owned tile beyond the largest current k-th distance of its
-  // own lists (those are never below the merged ones, so this is exact too).
   double r20 = easy ? (double)tau : -INFINITY;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) r20 = fmax(r20, __shfl_xor(r20, o, 64));
+  const uint64_t em = __ballot(easy);
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < k) out[(size_t)j * M + q] = top.key[j];
+    taus[q] = tau;
+  }
+  if (lane == 0) {
+    TileMeta mt;
+    mt.own = own;
+    mt.own.pad[0] = mt.own.pad[1] = 0.f;
+    mt.r20 = r20;
+    mt.easy = em;
+    meta[t] = mt;
+  }
+  if (valid && !easy) hard[atomicAdd(nhard, 1u)] = (uint32_t)q;
+}
+
+// Pass 1b, wave (query tile t, split s of S): every tile other than the first
+// three whose box does not lie farther from the box of the wave's easy queries
+// than their largest tau after pass 1a (r20, shared by all S waves, so that
+// the S waves agree on which tiles are live and which wave owns which) is
+// scanned by one of the S waves, every S-th in turn; a wave also skips an
+// owned tile beyond the largest current k-th distance of its own lists
+// (those are never below the merged ones, so this is exact too).  Split 0
+// continues the list of pass 1a; the other S - 1 start from sentinels at tau
+// (no query's answer has a key above (tau, any index)), so that every
+// candidate enters exactly one of the S lists.  Split s writes list s.
+template <int KM>
+__global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict__ Ys, int M,
+                                                       int k, const TBoxF *__restrict__ boxes,
+                                                       int ntiles, int S,
+                                                       const TileMeta *__restrict__ meta,
+                                                       const float *__restrict__ taus,
+                                                       uint64_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int t =
+      __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kKnnBlock / 64) + (threadIdx.x >> 6)));
+  const int split = blockIdx.y;
+  if (t >= ntiles) return;  // wave-uniform
+  const int q = t * kKnnTileW + lane;
+  const bool valid = q < M;
+  const TileMeta mt = meta[t];
+  const TBoxF own = mt.own;
+  const double r20 = mt.r20;
+  const bool easy = valid && ((mt.easy >> lane) & 1ull);
+  float qx = 0.f, qy = 0.f, qz = 0.f;
+  TopK<KM> top;
+  top.init(k, make_key(INFINITY, kNoIndex));
+  if (valid) {
+    const float4 p = Ys[q];
+    qx = p.x;
+    qy = p.y;
+    qz = p.z;
+    if (split == 0) {
+      uint64_t v[KM];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) v[j] = j < k ? out[(size_t)j * M + q] : make_key(INFINITY, kNoIndex);
+#pragma unroll
+      for (int j = 0; j < KM; ++j) top.key[j] = v[j];
+      top.worst = v[0];
+#pragma unroll
+      for (int j = 1; j < KM; ++j) top.worst = (j == k - 1) ? v[j] : top.worst;
+    } else {
+      top.init(k, make_key(taus[q], kNoIndex));
+    }
+  }
   int ord = 0;
   for (int c0 = 0; c0 < ntiles; c0 += 64) {
     double r2 = easy ? (double)key_dist(top.worst) : -INFINITY;
@@ -275,7 +338,6 @@ __global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict_
     for (int j = 0; j < KM; ++j)
       if (j < k) out[((size_t)split * k + j) * M + q] = top.key[j];
   }
-  if (split == 0 && valid && !easy) hard[atomicAdd(nhard, 1u)] = (uint32_t)q;
 }
 
 // Merge of the S partial lists of every query into list 0 (each list is
@@ -525,10 +587,12 @@ int knn_splits(int64_t M, int k) {
   return (int)S;
 }
 
-// Workspace: keys[S][k][M], tile boxes, hard list[M], hard counter.
+// Workspace: keys[S][k][M], tile metadata, tile boxes, tau[M], hard list[M],
+// hard counter.
 size_t knn_workspace_bytes(int64_t M, int k) {
   const size_t ntiles = (size_t)((M + kKnnTileW - 1) / kKnnTileW);
-  return (size_t)knn_splits(M, k) * k * (size_t)M * sizeof(uint64_t) + ntiles * sizeof(TBoxF) +
+  return (size_t)knn_splits(M, k) * k * (size_t)M * sizeof(uint64_t) +
+         ntiles * sizeof(TileMeta) + ntiles * sizeof(TBoxF) + (size_t)M * sizeof(float) +
          (size_t)M * sizeof(uint32_t) + 256;
 }
 
@@ -540,18 +604,23 @@ hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uin
   const int ntiles = (int)((M + kKnnTileW - 1) / kKnnTileW);
   const int S = knn_splits(M, k);
   uint64_t *keys = (uint64_t *)work;
-  TBoxF *boxes = (TBoxF *)(keys + (size_t)S * k * M);
-  uint32_t *hard = (uint32_t *)(boxes + ntiles);
+  TileMeta *meta = (TileMeta *)(keys + (size_t)S * k * M);
+  TBoxF *boxes = (TBoxF *)(meta + ntiles);
+  float *taus = (float *)(boxes + ntiles);
+  uint32_t *hard = (uint32_t *)(taus + M);
   unsigned int *nhard = (unsigned int *)(hard + M);
   hipLaunchKernelGGL(knn_boxes, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, Ys, Mi,
                      ntiles, boxes, nhard);
+  const dim3 g0((unsigned)((ntiles + kKnnBlock / 64 - 1) / (kKnnBlock / 64)));
   const dim3 g1((unsigned)((ntiles + kKnnBlock / 64 - 1) / (kKnnBlock / 64)), (unsigned)S);
   const dim3 gh(512);
   const dim3 g2((unsigned)((M + 255) / 256));
 #define LSG_KNN(KM_)                                                                            \
   do {                                                                                          \
+    hipLaunchKernelGGL(knn_seed<KM_>, g0, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles, S,  \
+                       keys, meta, taus, hard, nhard);                                          \
     hipLaunchKernelGGL(knn_tiles<KM_>, g1, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles, S, \
-                       keys, hard, nhard);                                                      \
+                       meta, taus, keys);                                                       \
     hipLaunchKernelGGL(knn_merge<KM_>, g2, dim3(256), 0, st, Mi, k, S, keys);                   \
     hipLaunchKernelGGL(knn_hard<KM_>, gh, dim3(kKnnBlock), 0, st, Ys, Mi, k, hard, nhard,       \
                        keys);                                                                   \
