@@ -55,6 +55,8 @@ struct lsgcpd_ctx {
   std::vector<char> htables;   // host copy of the batch tables
   char *htab_pinned = nullptr; // pinned staging of that copy (an asynchronous upload)
   size_t htab_cap = 0;
+  double *htr_pinned = nullptr;  // pinned copy of the NLL traces (read back with the states)
+  size_t htr_cap = 0;
   std::vector<double> htrace;
   // E-step timing: 4 events per E step (start, before and after the pair
   // kernel, end)
@@ -576,12 +578,25 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   }
   RETURN_IF(prof_reserve(ctx, p->max_iter));
   RETURN_IF(run_em(ctx, pl, bd, p->max_iter, stride, (p->flags & LSGCPD_GRAPH) != 0, st));
+  const size_t ntr = (size_t)npairs * stride;
+  if (ctx->htr_cap < ntr) {
+    if (ctx->htr_pinned) (void)hipHostFree(ctx->htr_pinned);
+    ctx->htr_pinned = nullptr;
+    ctx->htr_cap = 0;
+    if (hipHostMalloc((void **)&ctx->htr_pinned, ntr * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+      ctx->htr_pinned = nullptr;
+      (void)hipGetLastError();
+      return fail(ctx, LSGCPD_E_NOMEM, "pinned trace of %zu doubles failed", ntr);
+    }
+    ctx->htr_cap = ntr;
+  }
   HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, (size_t)npairs * sizeof(DevState),
                         hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ctx->htr_pinned, ctx->trace.p, ntr * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  ctx->htrace.resize((size_t)npairs * stride);
-  HIPCHK(hipMemcpy(ctx->htrace.data(), ctx->trace.p, ctx->htrace.size() * sizeof(double),
-                   hipMemcpyDeviceToHost));
+  ctx->htrace.assign(ctx->htr_pinned, ctx->htr_pinned + ntr);
   int64_t evaluated = 0;
   for (int i = 0; i < npairs; ++i) {
     const DevState &s = ctx->hstate[i];
@@ -669,6 +684,7 @@ LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   if (c->hstate) (void)hipHostFree(c->hstate);
   if (c->hcount) (void)hipHostFree(c->hcount);
   if (c->htab_pinned) (void)hipHostFree(c->htab_pinned);
+  if (c->htr_pinned) (void)hipHostFree(c->htr_pinned);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (hipEvent_t e : c->gev)

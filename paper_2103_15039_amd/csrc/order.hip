@@ -87,16 +87,14 @@ hipError_t launch_morton_order(const float *P, int64_t n, const double *box, voi
                      idx_in);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, code_in, code_out, idx_in, idx_out, (unsigned)n,
+  // the sorted indices go straight to perm when the caller wants them
+  uint32_t *sorted = perm ? perm : idx_out;
+  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, code_in, code_out, idx_in, sorted, (unsigned)n,
                                 0, 30, st);
   if (e != hipSuccess) return e;
   if (out3 || out4)
-    hipLaunchKernelGGL(gather_points, dim3(blocks), dim3(256), 0, st, P, (int)n, idx_out, out3,
+    hipLaunchKernelGGL(gather_points, dim3(blocks), dim3(256), 0, st, P, (int)n, sorted, out3,
                        out4);
-  if (perm) {
-    e = hipMemcpyAsync(perm, idx_out, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
-  }
   return hipGetLastError();
 }
 
