@@ -366,14 +366,19 @@ __global__ __launch_bounds__(256) void knn_merge(int M, int k, int S,
     if (j < k) keys[(size_t)j * M + q] = top.key[j];
 }
 
-// Pass 2: one wave per hard query; lane l keeps the k best of the points
-// l, l + 64, ... (loaded 8 at a time), then k rounds of a wave minimum merge
-// the 64 lists (keys are unique, so exactly one lane pops per round).  Hard
-// queries are taken in list order by a grid-stride loop that every wave
-// leaves.  Writes list 0.
+// Pass 2: one wave per hard query.  Its merged list from pass 1 holds k real
+// candidates, so its k-th key bounds the answer: tiles whose box lies farther
+// from the query than that distance (the same conservative FP64 gap as pass
+// 1) hold no answer and are skipped, 64 tile boxes tested at a time.  Lane l
+// takes point l of every other tile into a list of its own that starts from
+// sentinels at the bound; k rounds of a wave minimum then merge the 64 lists
+// (keys are unique, so exactly one lane pops per round).  Hard queries are
+// taken in list order by a grid-stride loop that every wave leaves.  Writes
+// list 0.
 template <int KM>
 __global__ __launch_bounds__(kKnnBlock) void knn_hard(const float4 *__restrict__ Ys, int M,
-                                                      int k, const uint32_t *__restrict__ hard,
+                                                      int k, const TBoxF *__restrict__ boxes,
+                                                      int ntiles, const uint32_t *__restrict__ hard,
                                                       const unsigned int *__restrict__ nhard,
                                                       uint64_t *__restrict__ out) {
   const int lane = threadIdx.x & 63;
@@ -383,19 +388,36 @@ __global__ __launch_bounds__(kKnnBlock) void knn_hard(const float4 *__restrict__
   for (int h = w0; h < nh; h += nw) {
     const int q = (int)hard[h];
     const float4 qp = Ys[q];
+    const float bound = key_dist(out[(size_t)(k - 1) * M + q]);
+    TBoxF qb;
+    qb.lo[0] = qb.hi[0] = qp.x;
+    qb.lo[1] = qb.hi[1] = qp.y;
+    qb.lo[2] = qb.hi[2] = qp.z;
     TopK<KM> top;
-    top.init(k, make_key(INFINITY, kNoIndex));
-    for (int j0 = 0; j0 < M; j0 += 8 * 64) {
-      float4 p[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int j = j0 + i * 64 + lane;
-        p[i] = j < M ? Ys[j] : make_float4(NAN, NAN, NAN, 0.f);
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float d = dist2_f32(qp.x, qp.y, qp.z, p[i].x, p[i].y, p[i].z);
-        if (d <= key_dist(top.worst)) top.offer(make_key(d, __float_as_uint(p[i].w)));
+    top.init(k, make_key(bound, kNoIndex));
+    for (int c0 = 0; c0 < ntiles; c0 += 64) {
+      const int u = c0 + lane;
+      uint64_t mk = __ballot(u < ntiles && !(box_gap2(qb, boxes[u]) > (double)bound));
+      // walk the live tiles, loading the next point while the current one is used
+      if (mk) {
+        int b = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        const int j0 = (c0 + b) * kKnnTileW + lane;
+        float4 cur = j0 < M ? Ys[j0] : make_float4(NAN, NAN, NAN, 0.f);
+        for (;;) {
+          const bool more = mk != 0;
+          float4 nxt = cur;
+          if (more) {
+            const int bn = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const int j1 = (c0 + bn) * kKnnTileW + lane;
+            nxt = j1 < M ? Ys[j1] : make_float4(NAN, NAN, NAN, 0.f);
+          }
+          const float d = dist2_f32(qp.x, qp.y, qp.z, cur.x, cur.y, cur.z);
+          if (d <= key_dist(top.worst)) top.offer(make_key(d, __float_as_uint(cur.w)));
+          if (!more) break;
+          cur = nxt;
+        }
       }
     }
     for (int r = 0; r < k; ++r) {
@@ -622,8 +644,8 @@ hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uin
     hipLaunchKernelGGL(knn_tiles<KM_>, g1, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles, S, \
                        meta, taus, keys);                                                       \
     hipLaunchKernelGGL(knn_merge<KM_>, g2, dim3(256), 0, st, Mi, k, S, keys);                   \
-    hipLaunchKernelGGL(knn_hard<KM_>, gh, dim3(kKnnBlock), 0, st, Ys, Mi, k, hard, nhard,       \
-                       keys);                                                                   \
+    hipLaunchKernelGGL(knn_hard<KM_>, gh, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles,    \
+                       hard, nhard, keys);                                                      \
     hipLaunchKernelGGL(knn_pca<KM_>, g2, dim3(256), 0, st, Y, Mi, k, keys, perm, alpha_max,     \
                        lambda, normals, kappa, alpha);                                          \
   } while (0)
