@@ -340,30 +340,48 @@ __global__ __launch_bounds__(kKnnBlock) void knn_tiles(const float4 *__restrict_
   }
 }
 
-// Merge of the S partial lists of every query into list 0 (each list is
-// sorted, so a list is left at its first key that cannot enter; the
-// sentinels of lists 1..S-1 never can, since list 0 holds k real keys that
-// are not above them).
+// Merge of the S partial lists of every query into list 0.  Four lanes per
+// query: lane j keeps the k smallest keys of lists j, j + 4, ..., then k
+// rounds of a minimum over the four lanes pop the answer in order.  Every real
+// candidate is in one list only, and list 0 holds k real keys below every
+// sentinel of the others, so the k keys popped are real and distinct (one
+// lane pops per round).
+constexpr int kMergeLanes = 4;
+
 template <int KM>
 __global__ __launch_bounds__(256) void knn_merge(int M, int k, int S,
                                                  uint64_t *__restrict__ keys) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= M || S == 1) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = gid / kMergeLanes, part = gid % kMergeLanes;  // a query's lanes share a wave
+  const bool valid = q < M;
   TopK<KM> top;
   top.init(k, ~(uint64_t)0);
-  for (int s = 0; s < S; ++s) {
-    // the whole list at once (k loads in flight), then in order until a key
-    // cannot enter
-    uint64_t v[KM];
+  if (valid)
+    for (int s = part; s < S; s += kMergeLanes) {
+      // the whole list at once (k loads in flight)
+      uint64_t v[KM];
 #pragma unroll
-    for (int j = 0; j < KM; ++j) v[j] = j < k ? keys[((size_t)s * k + j) * M + q] : ~(uint64_t)0;
+      for (int j = 0; j < KM; ++j) v[j] = j < k ? keys[((size_t)s * k + j) * M + q] : ~(uint64_t)0;
 #pragma unroll
-    for (int j = 0; j < KM; ++j)
-      if (j < k && v[j] < top.worst) top.insert(v[j]);
+      for (int j = 0; j < KM; ++j)
+        if (j < k && v[j] < top.worst) top.insert(v[j]);
+    }
+  for (int r = 0; r < k; ++r) {
+    uint64_t m = top.key[0];
+#pragma unroll
+    for (int o = 1; o < kMergeLanes; o <<= 1) {
+      const uint32_t mh = (uint32_t)__shfl_xor((int)(uint32_t)(m >> 32), o, 64);
+      const uint32_t ml = (uint32_t)__shfl_xor((int)(uint32_t)m, o, 64);
+      const uint64_t v = ((uint64_t)mh << 32) | ml;
+      m = v < m ? v : m;
+    }
+    if (valid && part == 0) keys[(size_t)r * M + q] = m;
+    if (top.key[0] == m) {  // pop the head
+#pragma unroll
+      for (int j = 0; j + 1 < KM; ++j) top.key[j] = top.key[j + 1];
+      top.key[KM - 1] = ~(uint64_t)0;
+    }
   }
-#pragma unroll
-  for (int j = 0; j < KM; ++j)
-    if (j < k) keys[(size_t)j * M + q] = top.key[j];
 }
 
 // Pass 2: one wave per hard query.  Its merged list from pass 1 holds k real
@@ -637,13 +655,15 @@ hipError_t launch_normals(const float *Y, int64_t M, const float4 *Ys, const uin
   const dim3 g1((unsigned)((ntiles + kKnnBlock / 64 - 1) / (kKnnBlock / 64)), (unsigned)S);
   const dim3 gh(512);
   const dim3 g2((unsigned)((M + 255) / 256));
+  const dim3 gm((unsigned)((M * kMergeLanes + 255) / 256));
 #define LSG_KNN(KM_)                                                                            \
   do {                                                                                          \
     hipLaunchKernelGGL(knn_seed<KM_>, g0, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles, S,  \
                        keys, meta, taus, hard, nhard);                                          \
     hipLaunchKernelGGL(knn_tiles<KM_>, g1, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles, S, \
                        meta, taus, keys);                                                       \
-    hipLaunchKernelGGL(knn_merge<KM_>, g2, dim3(256), 0, st, Mi, k, S, keys);                   \
+    if (S > 1)                                                                                  \
+      hipLaunchKernelGGL(knn_merge<KM_>, gm, dim3(256), 0, st, Mi, k, S, keys);                 \
     hipLaunchKernelGGL(knn_hard<KM_>, gh, dim3(kKnnBlock), 0, st, Ys, Mi, k, boxes, ntiles,    \
                        hard, nhard, keys);                                                      \
     hipLaunchKernelGGL(knn_pca<KM_>, g2, dim3(256), 0, st, Y, Mi, k, keys, perm, alpha_max,     \
