@@ -8,9 +8,10 @@
  * surface variation (Eq. 3), plus a uniform outlier component (Eq. 1).
  *
  * Conventions shared by every call:
- *  - Arrays named X, Y, normals, kappa, alpha, pi, w, P, colstats are DEVICE
- *    pointers owned by the caller (hipMalloc'd or torch CUDA tensors), row-major
- *    and contiguous.  Point clouds are float32 [n][3].  Structs (poses,
+ *  - Arrays named X, Y, P (points), normals, kappa, alpha, pi, w, phi, phi_x,
+ *    phi_y and colstats are DEVICE pointers owned by the caller (hipMalloc'd or
+ *    torch CUDA tensors), row-major and contiguous (lsgcpd_register_batch takes
+ *    host arrays of such pointers).  Point clouds are float32 [n][3].  Structs (poses,
  *    parameters, results, reports) are HOST memory owned by the caller.
  *  - The library owns only the workspace inside an lsgcpd_ctx; it grows on
  *    demand, is reused across calls and is released by lsgcpd_ctx_destroy.
@@ -18,9 +19,10 @@
  *  - Every call returns an lsgcpd_status; nothing throws across the ABI.  On
  *    a non-OK status the outputs are unspecified and lsgcpd_last_error(ctx)
  *    holds a message.  Invalid arguments are rejected before any GPU work.
- *  - `stream` is a hipStream_t (NULL = the default stream).  lsgcpd_normals is
- *    asynchronous on it; lsgcpd_estep and lsgcpd_register synchronise it before
- *    filling their host outputs.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  lsgcpd_normals and
+ *    lsgcpd_depth_confidence are asynchronous on it; the calls with host outputs
+ *    (lsgcpd_estep, lsgcpd_register*, lsgcpd_autotune) synchronise it before
+ *    filling them.
  *  - A context is not thread-safe: use one context per host thread.
  *  - The pose g = (R, t) maps the source into the target frame,
  *    g(x) = R x + t, with R row-major.
