@@ -152,3 +152,27 @@ def test_register_cf_full_size():
     assert O.translation_error(g.t, o.t) <= 1e-5 * diag
     np.testing.assert_allclose(g.nll, o.nll, rtol=1e-6)
     assert g.sigma2 == pytest.approx(o.sigma2, rel=1e-4)
+
+
+def test_estep_million_points():
+    """Ten times the benchmark's size in each cloud (10^12 pairs per E step):
+    the column identity for every source, and 64 sampled sources against the C
+    oracle's columns over all 10^6 targets."""
+    p = datagen.scene_pair(datagen.rng_for(14, 0), 1_000_000, 1_000_000, max_angle_deg=10.0)
+    M, N = len(p.Y), len(p.X)
+    n32, a32 = _geometry(M, 3)
+    s2 = 1e-4
+    V = O.working_volume(p.Y)
+    g = L.estep(dev(p.X), dev(p.Y), dev(n32), dev(a32), p.R_gt, p.t_gt, s2, w0=0.1,
+                colstats=True)
+    cs = g.colstats.cpu().numpy()
+    np.testing.assert_allclose(cs[:, 2] + cs[:, 14], 1.0, rtol=0, atol=1e-12)
+    assert g.sumP + g.outlier_mass == pytest.approx(N, rel=1e-12)
+    smp = np.sort(np.random.default_rng(4).choice(N, size=64, replace=False))
+    cc, ks = CO.estep_columns(p.X, p.Y, n32, a32, p.R_gt, p.t_gt, s2, w0=0.1, V=V, sources=smp)
+    gamma = (2 * np.pi * s2) ** 1.5 / V
+    assert np.all(np.abs(cs[smp, 1] - ks) <= 1e-5 * (ks + gamma))
+    np.testing.assert_allclose(cs[smp, 2], cc.p, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(cs[smp, 9:12], cc.B, rtol=1e-5,
+                               atol=1e-5 * np.abs(cc.B).max() + 1e-12)
+    np.testing.assert_allclose(cs[smp, 12], cc.C, rtol=1e-5, atol=1e-12)
