@@ -247,8 +247,9 @@ lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs, const float
  * (twice each; the second run is timed with HIP events on `stream`) and keeps
  * the fastest for the size class of the pair (floor(log2(M N))) in ctx:
  * later lsgcpd_estep / lsgcpd_register / lsgcpd_register_cf calls and batches
- * whose sum of M N falls in that class use it (default: 8192, or the
- * LSGCPD_WORK_ITEMS environment variable).  The count changes how the pair
+ * whose sum of M N falls in that class use it (default: 1024 up to 1.6e8
+ * pairs, 4096 up to 1.6e9, 8192 above; or the LSGCPD_WORK_ITEMS environment
+ * variable).  The count changes how the pair
  * sums are grouped, so results differ at the rounding level only.  *items_out
  * (may be NULL) receives the choice.  Argument rules as lsgcpd_register.
  * Synchronises `stream`. */

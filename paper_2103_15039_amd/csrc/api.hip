@@ -124,13 +124,16 @@ bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 constexpr uint32_t kKnownFlags = LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA |
                                  LSGCPD_DENSE | LSGCPD_GRAPH;
 
-// About this many work items per E step for the scalar back end (the
-// fastest measured on MI355X for the 20k x 20k and 100k x 50k workloads);
-// LSGCPD_WORK_ITEMS overrides it for tuning sweeps.
-int work_items() {
+// About this many work items per E step for the scalar back end, by the
+// number of pairs of the E step (whole registrations measured on MI355X: 1024
+// was fastest at 6.4e7 pairs, 4096 and 8192 tie at 4e8, 8192 at 2.5e9 and
+// 5e9; the thresholds sit between those sizes); LSGCPD_WORK_ITEMS overrides
+// it for tuning sweeps.
+int work_items(uint64_t pairs) {
   const char *e = getenv("LSGCPD_WORK_ITEMS");
   const int v = e ? atoi(e) : 0;
-  return v >= 64 && v <= (1 << 20) ? v : 8192;
+  if (v >= 64 && v <= (1 << 20)) return v;
+  return pairs <= 160000000ull ? 1024 : pairs <= 1600000000ull ? 4096 : 8192;
 }
 
 int size_class(int npairs, const int64_t *N, const int64_t *M) {
@@ -142,11 +145,14 @@ int size_class(int npairs, const int64_t *N, const int64_t *M) {
 }
 
 // Work-item target of an E step over these sizes: the one lsgcpd_autotune
-// measured fastest for their size class, else work_items().
+// measured fastest for their size class, else work_items(sum of M N).
 int items_for(const lsgcpd_ctx *ctx, int npairs, const int64_t *N, const int64_t *M) {
   if (ctx->forced_items > 0) return ctx->forced_items;
   auto it = ctx->tuned_items.find(size_class(npairs, N, M));
-  return it != ctx->tuned_items.end() ? it->second : work_items();
+  if (it != ctx->tuned_items.end()) return it->second;
+  uint64_t mn = 0;
+  for (int i = 0; i < npairs; ++i) mn += (uint64_t)N[i] * (uint64_t)M[i];
+  return work_items(mn);
 }
 
 int backend_of(uint32_t flags) {
