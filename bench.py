@@ -68,16 +68,20 @@ def parse():
 
 def measured_traffic(path):
     """HBM bytes per pair-kernel launch from the committed counter summary, or
-    None when there is none or the kernel source changed since it was taken."""
+    None when there is none or a source it depends on (the kernel, and the
+    host code that sizes its work items) changed since it was taken."""
     import hashlib
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, rec.get("source", ""))
-    if not os.path.exists(src):
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
-        return None
+    srcs = rec.get("sources") or [{"path": rec.get("source", ""),
+                                   "sha256": rec.get("source_sha256")}]
+    for s in srcs:
+        f = os.path.join(ROOT, s.get("path", ""))
+        if not os.path.exists(f):
+            return None
+        if hashlib.sha256(open(f, "rb").read()).hexdigest() != s.get("sha256"):
+            return None
     return rec.get("bytes_per_launch")
 
 
