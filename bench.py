@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pair-kernel launch "
                          "(default: profiles/estep_pairs_<workload>_traffic.json)")
+    ap.add_argument("--no-gpu-clock", action="store_true",
+                    help="skip the rocm-smi clock query (under a profiler: rocm-smi starts a "
+                         "second interpreter through its launcher)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -68,8 +71,9 @@ def parse():
 
 def measured_traffic(path):
     """HBM bytes per pair-kernel launch from the committed counter summary, or
-    None when there is none or a source it depends on (the kernel, and the
-    host code that sizes its work items) changed since it was taken."""
+    None when there is none or a source it depends on (the kernel, the host
+    code that sizes its work items, and the point order that shapes its
+    groups and tiles) changed since it was taken."""
     import hashlib
     if not os.path.exists(path):
         return None
@@ -83,6 +87,16 @@ def measured_traffic(path):
         if hashlib.sha256(open(f, "rb").read()).hexdigest() != s.get("sha256"):
             return None
     return rec.get("bytes_per_launch")
+
+
+def rot_err_deg(R, R_gt):
+    """Angle of R_gt^T R in degrees, by atan2 of its sine and cosine (accurate
+    near 0, where arccos of the trace is not)."""
+    import numpy as np
+    A = np.asarray(R_gt, dtype=np.float64).T @ np.asarray(R, dtype=np.float64)
+    s = 0.5 * np.linalg.norm([A[2, 1] - A[1, 2], A[0, 2] - A[2, 0], A[1, 0] - A[0, 1]])
+    c = 0.5 * (np.trace(A) - 1.0)
+    return float(np.degrees(np.arctan2(s, c)))
 
 
 def copy_kernel(mib):
@@ -155,7 +169,6 @@ def batch_main(a, nmin=1000, nmax=30000):
     import torch
     import datagen
     import paper_2103_15039_amd as L
-    from oracle import lsgcpd_oracle as O
 
     pairs = datagen.batch_pairs(256, trial=0, nmin=nmin, nmax=nmax)
     args = [(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.Y).cuda()) for p in pairs]
@@ -184,7 +197,7 @@ def batch_main(a, nmin=1000, nmax=30000):
         dt_single = time.perf_counter() - t1
 
     def ok(rs):
-        return float(np.mean([O.rotation_error_deg(r.R, p.R_gt) < 1.0 for r, p in zip(rs, pairs)]))
+        return float(np.mean([rot_err_deg(r.R, p.R_gt) < 1.0 for r, p in zip(rs, pairs)]))
     k_ms = prof["pair_kernel_ms"] / max(prof["launches"], 1)
     evaluated = prof["evaluated_pairs"] / max(prof["launches"], 1)
     achieved = FLOPS_PER_PAIR * evaluated / (k_ms * 1e-3)
@@ -210,8 +223,10 @@ def batch_main(a, nmin=1000, nmax=30000):
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None},
         "plain": None if single is None else {
             "pairs_per_s": len(pairs) / dt_single, "ms": dt_single * 1e3,
-            "success_rate": ok(single)},
+            "success_rate": ok(single),
+            "successful_pairs_per_s": ok(single) * len(pairs) / dt_single},
         "batched": {"success_rate": ok(res),
+                    "successful_pairs_per_s": ok(res) * value,
                     "speedup_vs_plain": None if single is None else value * dt_single / len(pairs),
                     "estep_pair_evals_per_s": mn * EM_ITERS * a.steps / dt,
                     "pair_kernel_ms": k_ms, "evaluated_frac": evaluated / mn},
@@ -259,8 +274,7 @@ def cf_main(a):
                 r = run(i, extra, thr)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / (a.steps * len(dev))
-        errs = [float(np.degrees(np.arccos(np.clip((np.trace(p.R_gt.T @ run(i, extra, thr).R) - 1)
-                                                   / 2, -1, 1)))) for i, p in enumerate(trials)]
+        errs = [rot_err_deg(run(i, extra, thr).R, p.R_gt) for i, p in enumerate(trials)]
         last = run(0, extra, thr)
         out_var[name] = {"ms": dt * 1e3, "registrations_per_s": 1.0 / dt,
                          "rot_err_deg": errs, "rot_err_mean": float(np.mean(errs)),
@@ -412,7 +426,7 @@ def main():
     achieved = FLOPS_PER_PAIR * evaluated / (k_ms * 1e-3)
     traffic = measured_traffic(a.traffic or os.path.join(
         ROOT, "profiles", f"estep_pairs_{a.workload}_traffic.json"))
-    rot_err = float(np.degrees(np.arccos(np.clip((np.trace(p.R_gt.T @ r.R) - 1) / 2, -1, 1))))
+    rot_err = rot_err_deg(r.R, p.R_gt)
     out = {
         "metric": "E-step pair-evals/s",
         "value": value,
@@ -437,7 +451,7 @@ def main():
                   "m1_pair_evals_per_s": M * N / (est["median"] * 1e-6) if est else None,
                   "m1_credited_fp32_frac":
                       M * N / (est["median"] * 1e-6) * CREDIT_FP32 / PEAK_FP32 if est else None,
-                  "gpu_clock": gpu_clock(),
+                  "gpu_clock": None if a.no_gpu_clock else gpu_clock(),
                   "evaluated_frac": evaluated / (M * N),
                   "pair_kernel_pair_evals_per_s": M * N / (k_ms * 1e-3),
                   "estep_pair_evals_per_s": M * N / (e_ms * 1e-3),

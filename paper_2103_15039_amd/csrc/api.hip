@@ -282,15 +282,15 @@ lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, int p, co
   return LSGCPD_OK;
 }
 
-// Y (M points) in Morton order into ys4 + off (x, y, z, index within Y) and
+// Y (M points) in Hilbert order into ys4 + off (x, y, z, index within Y) and
 // yperm + off.
 lsgcpd_status sort_targets(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t off,
                            hipStream_t st) {
   const int nb = lsg::moments_blocks(M);
   double *box = (double *)ctx->mom.p + 32;
   HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, nb, box, st));
-  HIPCHK(lsg::launch_morton_order(Y, M, box, ctx->order.p, ctx->order.cap, nullptr,
-                                  (float4 *)ctx->ys4.p + off, (uint32_t *)ctx->yperm.p + off, st));
+  HIPCHK(lsg::launch_curve_order(Y, M, box, ctx->order.p, ctx->order.cap, nullptr,
+                                 (float4 *)ctx->ys4.p + off, (uint32_t *)ctx->yperm.p + off, st));
   return LSGCPD_OK;
 }
 
@@ -303,7 +303,7 @@ lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t
   return LSGCPD_OK;
 }
 
-// Workspace of the Morton sorts and moments of the npairs clouds of N[i]
+// Workspace of the Hilbert-order sorts and moments of the npairs clouds of N[i]
 // sources (N may be null) and M[i] targets, of the neighbour search (k
 // neighbours) over each target cloud, and the sorted copies of `mtot`
 // targets.  The sort and search workspaces are maxima over the clouds, not
@@ -315,8 +315,8 @@ lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int npairs, const int64_t *N, con
   int64_t nmax = 1;
   for (int i = 0; i < npairs; ++i) {
     const int64_t n = N ? N[i] : 0;
-    const size_t a = lsg::morton_workspace_bytes(M[i]);
-    const size_t b = n > 0 ? lsg::morton_workspace_bytes(n) : 0;
+    const size_t a = lsg::curve_order_workspace_bytes(M[i]);
+    const size_t b = n > 0 ? lsg::curve_order_workspace_bytes(n) : 0;
     const size_t c = lsg::knn_workspace_bytes(M[i], k);
     ob = a > ob ? a : ob;
     ob = b > ob ? b : ob;
@@ -535,15 +535,15 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   RETURN_IF(ensure_estep(ctx, pl));
 
   float *nrm = (float *)ctx->nrm.p, *kap = (float *)ctx->kap.p, *alp = (float *)ctx->alp.p;
-  // target geometry: neighbours over each Y in Morton order
+  // target geometry: neighbours over each Y in Hilbert order
   for (int i = 0; i < npairs; ++i) {
     const int64_t yo = pl.slots[i].y_off;
     RETURN_IF(sort_targets(ctx, Y[i], M[i], yo, st));
     RETURN_IF(normals_sorted(ctx, Y[i], M[i], yo, p->k, p->alpha_max, p->lambda, nrm + 3 * yo,
                              kap + yo, alp + yo, st));
   }
-  // With culling the target records follow the Morton order of Y and the
-  // sources are put in Morton order too, so that a source group's and a target
+  // With culling the target records follow the Hilbert order of Y and the
+  // sources are put in Hilbert order too, so that a source group's and a target
   // tile's points are neighbours.  Every statistic is a sum over all sources
   // and all targets, so the order changes only the rounding of the sums.
   for (int i = 0; i < npairs; ++i) {
@@ -558,8 +558,8 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
       uint32_t *xi = phx ? (uint32_t *)ctx->xidx.p : nullptr;
       HIPCHK(lsg::launch_moments(X[i], N[i], nullptr, (double *)ctx->mom_part.p,
                                  lsg::moments_blocks(N[i]), xbox, st));
-      HIPCHK(lsg::launch_morton_order(X[i], N[i], xbox, ctx->order.p, ctx->order.cap, xs,
-                                      nullptr, xi, st));
+      HIPCHK(lsg::launch_curve_order(X[i], N[i], xbox, ctx->order.p, ctx->order.cap, xs,
+                                     nullptr, xi, st));
       sl.X = xs;
       if (phx) {  // confidences follow their points
         float *ps = (float *)ctx->xphi.p + sl.x_off;

@@ -2,7 +2,7 @@
 // nearest neighbours, FP64 3x3 PCA of each neighbourhood, surface variation
 // kappa and the penalty alpha.
 //
-// The caller puts the cloud in Morton order (order.hip) and passes the sorted
+// The caller puts the cloud in Hilbert order (order.hip) and passes the sorted
 // copy Ys (x, y, z, original index).  Pass 1 (knn_tiles): S waves per tile of
 // 64 sorted queries keep the k best (distance, original index) keys of each
 // query in registers.  Each scans the own tile and the two next to it first;
@@ -133,7 +133,7 @@ __device__ __forceinline__ int tile_count(int M, int u) {
   return M - u * kKnnTileW < kKnnTileW ? M - u * kKnnTileW : kKnnTileW;
 }
 
-// Pass 1a, one wave per query tile t.  The own tile and its two Morton
+// Pass 1a, one wave per query tile t.  The own tile and its two Hilbert-order
 // neighbours give every query a first list and its current k-th distance
 // tau; the list is written as list 0.  Queries whose tau is far above the
 // wave's 75th percentile (isolated points such as outliers) are "hard": they

@@ -84,7 +84,7 @@ struct DevState {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the hipError_t of the launch.
 
-// Normals: k nearest neighbours over the Morton-sorted copy Ys (x, y, z,
+// Normals: k nearest neighbours over the Hilbert-sorted copy Ys (x, y, z,
 // original index bits; perm[i] = original index of Ys[i]) + PCA + alpha,
 // written in the original order of Y.
 size_t knn_workspace_bytes(int64_t M, int k);
@@ -103,14 +103,14 @@ int moments_blocks(int64_t n);
 hipError_t launch_init_state(DevState *s, const double *ymom, const double *xmom, int64_t M,
                              int64_t N, int v_auto, int s2_auto, hipStream_t st);
 
-// Points sorted by a Morton code of their position (box = moments of the
+// Points sorted by their index along a Hilbert curve (box = moments of the
 // cloud): writes the permuted cloud to out3 (x, y, z) and/or out4 (x, y, z,
 // original index bits), and the permutation (sorted position -> original
 // index) to perm; any of them may be null.
-size_t morton_workspace_bytes(int64_t n);
-hipError_t launch_morton_order(const float *P, int64_t n, const double *box, void *work,
-                               size_t work_bytes, float *out3, float4 *out4, uint32_t *perm,
-                               hipStream_t st);
+size_t curve_order_workspace_bytes(int64_t n);
+hipError_t launch_curve_order(const float *P, int64_t n, const double *box, void *work,
+                              size_t work_bytes, float *out3, float4 *out4, uint32_t *perm,
+                              hipStream_t st);
 
 // Target records.
 // Record i describes target perm[i] (perm may be null); rec[M] is a sentinel
@@ -149,7 +149,7 @@ constexpr int kPairS = 2;          // sources per thread in the LDS back end
 // One registration problem of a batch, as the kernels see it (a table in
 // device memory; the single-pair calls are batches of one).
 struct Slot {
-  const float *X;   // sources, N x 3 (Morton order when culled)
+  const float *X;   // sources, N x 3 (Hilbert order when culled)
   const float *w;   // per-source weights, or null (then phi, else w0 of the state)
   const float *phi; // per-source confidences (order of X): w_n = 1 - (1 - w0) phi_n
   int64_t x_off;    // first source in the batch numbering (colS, colstats)
