@@ -232,7 +232,11 @@ lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const 
  * Results equal lsgcpd_register's up to the grouping of the sums (the work
  * items differ).  Requires 1 <= npairs <= 65536, sum of N[i] + M[i] at most
  * 2^27, k <= M[i], and the default pair kernel (LSGCPD_PAIRS_LDS / _MFMA give
- * LSGCPD_E_UNSUPPORTED for npairs > 1).  Synchronises `stream`. */
+ * LSGCPD_E_UNSUPPORTED for npairs > 1).  The set-up of the clouds (sorting,
+ * neighbours, records) of pair i runs on `stream` when i % 4 == 0 and else
+ * on one of three streams of the context, which start after the work queued
+ * on `stream` and which `stream` waits for (events) before the EM loop.
+ * Synchronises `stream`. */
 lsgcpd_status lsgcpd_register_batch(lsgcpd_ctx *ctx, int32_t npairs, const float *const *X,
                                     const int64_t *N, const float *const *Y, const int64_t *M,
                                     const lsgcpd_params *p, const lsgcpd_pose *init,

@@ -21,6 +21,9 @@ namespace {
 
 constexpr int64_t kMaxPoints = (int64_t)1 << 27;
 constexpr int kMaxBatch = 1 << 16;
+// The set-up of a batch (sorting, neighbour search and records of every
+// cloud: a few small kernels per cloud) runs on this many streams at once.
+constexpr int kSetupLanes = 4;
 
 struct Buf {
   void *p = nullptr;
@@ -37,6 +40,16 @@ struct lsgcpd_ctx {
   // confidence filtering: kept points and confidences of X and Y, selection
   // workspace, sorted source confidences, source permutation, prior sums
   Buf cfx, cfy, cfwork, xphi, xidx, prior;
+  // set-up lanes 1 .. kSetupLanes - 1 of a batch: a stream each and their own
+  // copies of the set-up scratch (lane 0 is the caller's stream with the
+  // buffers above)
+  struct LaneBufs {
+    Buf order, knn, mom_part, mom, prior, xidx;
+  };
+  LaneBufs lane[kSetupLanes - 1];
+  hipStream_t lstream[kSetupLanes - 1] = {};
+  hipEvent_t lfork = nullptr;
+  hipEvent_t ljoin[kSetupLanes - 1] = {};
   uint32_t *hcount = nullptr;  // pinned: kept point counts
   // work-item targets chosen by lsgcpd_autotune, per size class
   // (floor(log2(sum of M N))); forced_items > 0 overrides while tuning
@@ -249,6 +262,47 @@ lsgcpd_status ensure_states(lsgcpd_ctx *ctx, int n) {
   return LSGCPD_OK;
 }
 
+// The stream and set-up scratch of lane q (0: the caller's stream st).
+struct Lane {
+  hipStream_t st;
+  Buf *order, *knn, *mom_part, *mom, *prior, *xidx;
+};
+
+Lane lane_of(lsgcpd_ctx *ctx, int q, hipStream_t st) {
+  if (q == 0) return {st, &ctx->order, &ctx->knn, &ctx->mom_part, &ctx->mom, &ctx->prior, &ctx->xidx};
+  lsgcpd_ctx::LaneBufs &b = ctx->lane[q - 1];
+  return {ctx->lstream[q - 1], &b.order, &b.knn, &b.mom_part, &b.mom, &b.prior, &b.xidx};
+}
+
+// Streams and events of lanes 1 .. n - 1 (created once, default priority).
+lsgcpd_status ensure_lanes(lsgcpd_ctx *ctx, int n) {
+  if (n > 1 && !ctx->lfork) HIPCHK(hipEventCreateWithFlags(&ctx->lfork, hipEventDisableTiming));
+  for (int q = 1; q < n; ++q) {
+    if (!ctx->lstream[q - 1])
+      HIPCHK(hipStreamCreateWithFlags(&ctx->lstream[q - 1], hipStreamNonBlocking));
+    if (!ctx->ljoin[q - 1])
+      HIPCHK(hipEventCreateWithFlags(&ctx->ljoin[q - 1], hipEventDisableTiming));
+  }
+  return LSGCPD_OK;
+}
+
+// Lanes 1 .. n - 1 start after the work queued on st so far ...
+lsgcpd_status fork_lanes(lsgcpd_ctx *ctx, int n, hipStream_t st) {
+  if (n <= 1) return LSGCPD_OK;
+  HIPCHK(hipEventRecord(ctx->lfork, st));
+  for (int q = 1; q < n; ++q) HIPCHK(hipStreamWaitEvent(ctx->lstream[q - 1], ctx->lfork, 0));
+  return LSGCPD_OK;
+}
+
+// ... and st continues after all of their work.
+lsgcpd_status join_lanes(lsgcpd_ctx *ctx, int n, hipStream_t st) {
+  for (int q = 1; q < n; ++q) {
+    HIPCHK(hipEventRecord(ctx->ljoin[q - 1], ctx->lstream[q - 1]));
+    HIPCHK(hipStreamWaitEvent(st, ctx->ljoin[q - 1], 0));
+  }
+  return LSGCPD_OK;
+}
+
 // Problem p of a batch: target records (record i of the problem describes its
 // target yperm[i], or target i if yperm is null) and their tile boxes, then
 // moments of Y, X at the problem's pose, then init_state.
@@ -256,14 +310,15 @@ lsgcpd_status ensure_states(lsgcpd_ctx *ctx, int n) {
 // problem p.  Priors: pi (raw priors) or phi (target confidences, normalised
 // on the device: Sec. 3.3), else uniform; with eta > 0 the state's w0 becomes
 // w_max (Sec. 3.2).
-lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, int p, const float *Y,
-                            const float *normals, const float *alpha, const float *pi,
-                            const float *phi, double eta, const uint32_t *yperm, uint32_t flags,
-                            int v_auto, int s2_auto, hipStream_t st) {
+lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const Lane &ln, const lsg::BatchPlan &pl, int p,
+                            const float *Y, const float *normals, const float *alpha,
+                            const float *pi, const float *phi, double eta,
+                            const uint32_t *yperm, uint32_t flags, int v_auto, int s2_auto) {
+  const hipStream_t st = ln.st;
   const lsg::Slot &sl = pl.slots[p];
   const int exact = (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0;
   if (phi || eta > 0.0)
-    HIPCHK(lsg::launch_prior_sums(phi, alpha, sl.M, exact, (double *)ctx->prior.p,
+    HIPCHK(lsg::launch_prior_sums(phi, alpha, sl.M, exact, (double *)ln.prior->p,
                                   ctx->dstate + p, st));
   HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, phi ? phi : pi,
                                   phi ? &(ctx->dstate + p)->pi_sum : nullptr, yperm, sl.M,
@@ -271,12 +326,12 @@ lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, int p, co
                                   (lsg::TRec *)ctx->rec.p + sl.y_off + p,
                                   (lsg::TPt *)ctx->pts.p + sl.y_off,
                                   (lsg::TBox *)ctx->boxes.p + sl.t_off, st));
-  double *ymom = (double *)ctx->mom.p;
+  double *ymom = (double *)ln.mom->p;
   double *xmom = ymom + 16;
-  HIPCHK(lsg::launch_moments(Y, sl.M, nullptr, (double *)ctx->mom_part.p,
+  HIPCHK(lsg::launch_moments(Y, sl.M, nullptr, (double *)ln.mom_part->p,
                              lsg::moments_blocks(sl.M), ymom, st));
   if (s2_auto)
-    HIPCHK(lsg::launch_moments(sl.X, sl.N, ctx->dstate + p, (double *)ctx->mom_part.p,
+    HIPCHK(lsg::launch_moments(sl.X, sl.N, ctx->dstate + p, (double *)ln.mom_part->p,
                                lsg::moments_blocks(sl.N), xmom, st));
   HIPCHK(lsg::launch_init_state(ctx->dstate + p, ymom, xmom, sl.M, sl.N, v_auto, s2_auto, st));
   return LSGCPD_OK;
@@ -284,22 +339,23 @@ lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, int p, co
 
 // Y (M points) in Hilbert order into ys4 + off (x, y, z, index within Y) and
 // yperm + off.
-lsgcpd_status sort_targets(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t off,
-                           hipStream_t st) {
+lsgcpd_status sort_targets(lsgcpd_ctx *ctx, const Lane &ln, const float *Y, int64_t M,
+                           int64_t off) {
+  const hipStream_t st = ln.st;
   const int nb = lsg::moments_blocks(M);
-  double *box = (double *)ctx->mom.p + 32;
-  HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ctx->mom_part.p, nb, box, st));
-  HIPCHK(lsg::launch_curve_order(Y, M, box, ctx->order.p, ctx->order.cap, nullptr,
+  double *box = (double *)ln.mom->p + 32;
+  HIPCHK(lsg::launch_moments(Y, M, nullptr, (double *)ln.mom_part->p, nb, box, st));
+  HIPCHK(lsg::launch_curve_order(Y, M, box, ln.order->p, ln.order->cap, nullptr,
                                  (float4 *)ctx->ys4.p + off, (uint32_t *)ctx->yperm.p + off, st));
   return LSGCPD_OK;
 }
 
-lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t off, int k,
-                             double alpha_max, double lambda, float *normals, float *kappa,
-                             float *alpha, hipStream_t st) {
+lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const Lane &ln, const float *Y, int64_t M,
+                             int64_t off, int k, double alpha_max, double lambda, float *normals,
+                             float *kappa, float *alpha) {
   HIPCHK(lsg::launch_normals(Y, M, (const float4 *)ctx->ys4.p + off,
                              (const uint32_t *)ctx->yperm.p + off, k, alpha_max, lambda, normals,
-                             kappa, alpha, ctx->knn.p, ctx->knn.cap, st));
+                             kappa, alpha, ln.knn->p, ln.knn->cap, ln.st));
   return LSGCPD_OK;
 }
 
@@ -308,9 +364,10 @@ lsgcpd_status normals_sorted(lsgcpd_ctx *ctx, const float *Y, int64_t M, int64_t
 // neighbours) over each target cloud, and the sorted copies of `mtot`
 // targets.  The sort and search workspaces are maxima over the clouds, not
 // the workspace of the largest cloud: the number of target splits of the
-// search falls as M grows, and so may the sort's scratch.
+// search falls as M grows, and so may the sort's scratch.  Each of the first
+// `lanes` set-up lanes gets its own scratch.
 lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int npairs, const int64_t *N, const int64_t *M,
-                              int64_t mtot, int k) {
+                              int64_t mtot, int k, int lanes) {
   size_t ob = 0, kb = 0;
   int64_t nmax = 1;
   for (int i = 0; i < npairs; ++i) {
@@ -324,14 +381,17 @@ lsgcpd_status ensure_geometry(lsgcpd_ctx *ctx, int npairs, const int64_t *N, con
     nmax = M[i] > nmax ? M[i] : nmax;
     nmax = n > nmax ? n : nmax;
   }
-  ENSURE(order, ob);
-  ENSURE(mom_part, (size_t)lsg::moments_blocks(nmax) * 10 * sizeof(double));
-  ENSURE(mom, 48 * sizeof(double));
   ENSURE(yperm, (size_t)mtot * sizeof(uint32_t));
   ENSURE(ys4, (size_t)mtot * sizeof(float4));
-  ENSURE(knn, kb);
-  ENSURE(prior, (size_t)2 * lsg::prior_blocks(nmax) * sizeof(double));
-  return LSGCPD_OK;
+  for (int q = 0; q < lanes; ++q) {
+    const Lane ln = lane_of(ctx, q, nullptr);
+    RETURN_IF(ensure(ctx, *ln.order, ob));
+    RETURN_IF(ensure(ctx, *ln.mom_part, (size_t)lsg::moments_blocks(nmax) * 10 * sizeof(double)));
+    RETURN_IF(ensure(ctx, *ln.mom, 48 * sizeof(double)));
+    RETURN_IF(ensure(ctx, *ln.knn, kb));
+    RETURN_IF(ensure(ctx, *ln.prior, (size_t)2 * lsg::prior_blocks(nmax) * sizeof(double)));
+  }
+  return ensure_lanes(ctx, lanes);
 }
 
 // Makes room for `steps` more timed E steps (no-op unless profiling).
@@ -497,6 +557,42 @@ lsgcpd_status upload_tables(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, hipStream
   return LSGCPD_OK;
 }
 
+// Target geometry of pair i (Hilbert order of Y, neighbours, normals) and,
+// with culling, its sources in Hilbert order (their confidences carried
+// along), on lane ln.  With culling the target records follow the Hilbert
+// order of Y and the sources are put in Hilbert order too, so that a source
+// group's and a target tile's points are neighbours.  Every statistic is a
+// sum over all sources and all targets, so the order changes only the
+// rounding of the sums.
+lsgcpd_status pair_geometry(lsgcpd_ctx *ctx, const Lane &ln, lsg::BatchPlan &pl, int i,
+                            const float *X, const float *Y, const float *phx,
+                            const lsgcpd_params *p, float *nrm, float *kap, float *alp) {
+  lsg::Slot &sl = pl.slots[i];
+  const int64_t yo = sl.y_off, M = sl.M, N = sl.N;
+  RETURN_IF(sort_targets(ctx, ln, Y, M, yo));
+  RETURN_IF(normals_sorted(ctx, ln, Y, M, yo, p->k, p->alpha_max, p->lambda, nrm + 3 * yo,
+                           kap + yo, alp + yo));
+  sl.X = X;
+  sl.w = nullptr;
+  sl.phi = phx;
+  if (pl.cull && N > 256) {
+    const hipStream_t st = ln.st;
+    float *xs = (float *)ctx->xperm.p + 3 * sl.x_off;
+    double *xbox = (double *)ln.mom->p + 32;
+    uint32_t *xi = phx ? (uint32_t *)ln.xidx->p : nullptr;
+    HIPCHK(lsg::launch_moments(X, N, nullptr, (double *)ln.mom_part->p, lsg::moments_blocks(N),
+                               xbox, st));
+    HIPCHK(lsg::launch_curve_order(X, N, xbox, ln.order->p, ln.order->cap, xs, nullptr, xi, st));
+    sl.X = xs;
+    if (phx) {  // confidences follow their points
+      float *ps = (float *)ctx->xphi.p + sl.x_off;
+      HIPCHK(lsg::launch_gather_f32(phx, xi, N, ps, st));
+      sl.phi = ps;
+    }
+  }
+  return LSGCPD_OK;
+}
+
 // Registration of npairs problems that share the parameters: the E steps and
 // M steps of all problems run in the same launches.
 // phi_x / phi_y: null, or per-pair source / target confidences (entries may
@@ -513,7 +609,8 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   lsg::BatchPlan pl =
       lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1,
                       items_for(ctx, npairs, N, M));
-  RETURN_IF(ensure_geometry(ctx, npairs, N, M, pl.targets, p->k));
+  const int lanes = npairs < kSetupLanes ? npairs : kSetupLanes;
+  RETURN_IF(ensure_geometry(ctx, npairs, N, M, pl.targets, p->k, lanes));
   ENSURE(nrm, (size_t)pl.targets * 3 * sizeof(float));
   ENSURE(kap, (size_t)pl.targets * sizeof(float));
   ENSURE(alp, (size_t)pl.targets * sizeof(float));
@@ -528,46 +625,25 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   }
   if (any_phi_x && pl.cull) {
     ENSURE(xphi, (size_t)pl.sources * sizeof(float));
-    ENSURE(xidx, (size_t)nmax * sizeof(uint32_t));
+    for (int q = 0; q < lanes; ++q)
+      RETURN_IF(ensure(ctx, *lane_of(ctx, q, st).xidx, (size_t)nmax * sizeof(uint32_t)));
   }
   RETURN_IF(ensure_states(ctx, npairs));
   lsg::BatchDev bd;
   RETURN_IF(ensure_estep(ctx, pl));
 
   float *nrm = (float *)ctx->nrm.p, *kap = (float *)ctx->kap.p, *alp = (float *)ctx->alp.p;
-  // target geometry: neighbours over each Y in Hilbert order
-  for (int i = 0; i < npairs; ++i) {
-    const int64_t yo = pl.slots[i].y_off;
-    RETURN_IF(sort_targets(ctx, Y[i], M[i], yo, st));
-    RETURN_IF(normals_sorted(ctx, Y[i], M[i], yo, p->k, p->alpha_max, p->lambda, nrm + 3 * yo,
-                             kap + yo, alp + yo, st));
+  // The set-up kernels of a cloud are small and those of different pairs are
+  // independent: pair i is set up on lane i % lanes, and the lanes overlap.
+  lsgcpd_status status = fork_lanes(ctx, lanes, st);
+  for (int i = 0; status == LSGCPD_OK && i < npairs; ++i)
+    status = pair_geometry(ctx, lane_of(ctx, i % lanes, st), pl, i, X[i], Y[i],
+                           phi_x ? phi_x[i] : nullptr, p, nrm, kap, alp);
+  {
+    const lsgcpd_status js = join_lanes(ctx, lanes, st);
+    if (status == LSGCPD_OK) status = js;
   }
-  // With culling the target records follow the Hilbert order of Y and the
-  // sources are put in Hilbert order too, so that a source group's and a target
-  // tile's points are neighbours.  Every statistic is a sum over all sources
-  // and all targets, so the order changes only the rounding of the sums.
-  for (int i = 0; i < npairs; ++i) {
-    lsg::Slot &sl = pl.slots[i];
-    const float *phx = phi_x ? phi_x[i] : nullptr;
-    sl.X = X[i];
-    sl.w = nullptr;
-    sl.phi = phx;
-    if (pl.cull && N[i] > 256) {
-      float *xs = (float *)ctx->xperm.p + 3 * sl.x_off;
-      double *xbox = (double *)ctx->mom.p + 32;
-      uint32_t *xi = phx ? (uint32_t *)ctx->xidx.p : nullptr;
-      HIPCHK(lsg::launch_moments(X[i], N[i], nullptr, (double *)ctx->mom_part.p,
-                                 lsg::moments_blocks(N[i]), xbox, st));
-      HIPCHK(lsg::launch_curve_order(X[i], N[i], xbox, ctx->order.p, ctx->order.cap, xs,
-                                     nullptr, xi, st));
-      sl.X = xs;
-      if (phx) {  // confidences follow their points
-        float *ps = (float *)ctx->xphi.p + sl.x_off;
-        HIPCHK(lsg::launch_gather_f32(phx, xi, N[i], ps, st));
-        sl.phi = ps;
-      }
-    }
-  }
+  RETURN_IF(status);
   RETURN_IF(upload_tables(ctx, pl, st, &bd));
   const int s2_auto = p->sigma2_init > 0.0 ? 0 : 1;
   for (int i = 0; i < npairs; ++i)
@@ -575,13 +651,19 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
                p->V > 0.0 ? p->V : 0.0, p->w0, p->eta, p->tol, p->newton_max, p->max_iter);
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, (size_t)npairs * sizeof(DevState),
                         hipMemcpyHostToDevice, st));
-  for (int i = 0; i < npairs; ++i) {
+  status = fork_lanes(ctx, lanes, st);
+  for (int i = 0; status == LSGCPD_OK && i < npairs; ++i) {
     const int64_t yo = pl.slots[i].y_off;
-    RETURN_IF(setup_problem(ctx, pl, i, Y[i], nrm + 3 * yo, alp + yo, nullptr,
-                            phi_y ? phi_y[i] : nullptr, p->eta,
-                            pl.cull ? (const uint32_t *)ctx->yperm.p + yo : nullptr, p->flags,
-                            p->V > 0.0 ? 0 : 1, s2_auto, st));
+    status = setup_problem(ctx, lane_of(ctx, i % lanes, st), pl, i, Y[i], nrm + 3 * yo, alp + yo,
+                           nullptr, phi_y ? phi_y[i] : nullptr, p->eta,
+                           pl.cull ? (const uint32_t *)ctx->yperm.p + yo : nullptr, p->flags,
+                           p->V > 0.0 ? 0 : 1, s2_auto);
   }
+  {
+    const lsgcpd_status js = join_lanes(ctx, lanes, st);
+    if (status == LSGCPD_OK) status = js;
+  }
+  RETURN_IF(status);
   RETURN_IF(prof_reserve(ctx, p->max_iter));
   RETURN_IF(run_em(ctx, pl, bd, p->max_iter, stride, (p->flags & LSGCPD_GRAPH) != 0, st));
   const size_t ntr = (size_t)npairs * stride;
@@ -610,7 +692,7 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
                                                 : M[i] * N[i] * (s.iter + s.converged);
   }
   RETURN_IF(prof_collect(ctx, evaluated));
-  lsgcpd_status status = LSGCPD_OK;
+  status = LSGCPD_OK;
   for (int i = 0; i < npairs; ++i) {
     const DevState &s = ctx->hstate[i];
     const int filled = s.iter + s.converged;
@@ -686,6 +768,14 @@ LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
                  &c->xidx,  &c->prior};
   for (Buf *b : bufs)
     if (b->p) (void)hipFree(b->p);
+  for (lsgcpd_ctx::LaneBufs &l : c->lane)
+    for (Buf *b : {&l.order, &l.knn, &l.mom_part, &l.mom, &l.prior, &l.xidx})
+      if (b->p) (void)hipFree(b->p);
+  for (hipStream_t s : c->lstream)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : c->ljoin)
+    if (e) (void)hipEventDestroy(e);
+  if (c->lfork) (void)hipEventDestroy(c->lfork);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->hstate) (void)hipHostFree(c->hstate);
   if (c->hcount) (void)hipHostFree(c->hcount);
@@ -729,9 +819,10 @@ LSG_API lsgcpd_status lsgcpd_normals(lsgcpd_ctx *ctx, const float *Y, int64_t M,
   if (!finite_pos(lambda)) return fail(ctx, LSGCPD_E_INVALID, "lambda must be finite and > 0");
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
-  RETURN_IF(ensure_geometry(ctx, 1, nullptr, &M, M, k));
-  RETURN_IF(sort_targets(ctx, Y, M, 0, st));
-  return normals_sorted(ctx, Y, M, 0, k, alpha_max, lambda, normals, kappa, alpha, st);
+  RETURN_IF(ensure_geometry(ctx, 1, nullptr, &M, M, k, 1));
+  const Lane ln = lane_of(ctx, 0, st);
+  RETURN_IF(sort_targets(ctx, ln, Y, M, 0));
+  return normals_sorted(ctx, ln, Y, M, 0, k, alpha_max, lambda, normals, kappa, alpha);
 }
 
 LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
@@ -767,8 +858,8 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   RETURN_IF(upload_tables(ctx, pl, st, &bd));
   fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 0.0, 20, 1);
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
-  RETURN_IF(setup_problem(ctx, pl, 0, Y, normals, alpha, pi, nullptr, 0.0, nullptr, flags,
-                          V > 0.0 ? 0 : 1, 0, st));
+  RETURN_IF(setup_problem(ctx, lane_of(ctx, 0, st), pl, 0, Y, normals, alpha, pi, nullptr, 0.0,
+                          nullptr, flags, V > 0.0 ? 0 : 1, 0));
   RETURN_IF(prof_reserve(ctx, 1));
   RETURN_IF(run_estep(ctx, pl, bd, (double *)ctx->colS.p, colstats, nullptr, 1, 0, st));
   if (P)
