@@ -370,8 +370,8 @@ def main():
         copy_kernel(a.copy_kernel)
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the "
-              "multi-GPU layout is a design note, not an implemented path", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {a.gpus}); "
+              "sharding across GPUs is a design note, not an implemented path", file=sys.stderr)
         sys.exit(2)
     if a.workload == "batch256":
         batch_main(a)

@@ -47,7 +47,7 @@ typedef enum {
   LSGCPD_E_HIP = 2,         /* a HIP runtime call failed (no device, launch) */
   LSGCPD_E_NOMEM = 3,       /* workspace allocation failed                   */
   LSGCPD_E_NUMERIC = 4,     /* non-finite variance or pose                   */
-  LSGCPD_E_UNSUPPORTED = 5  /* size or option this build does not handle     */
+  LSGCPD_E_UNSUPPORTED = 5  /* size or option the library does not handle    */
 } lsgcpd_status;
 
 /* Flags for lsgcpd_estep / lsgcpd_params.flags */
