@@ -21,9 +21,12 @@ at the function that takes it.
 Parity status: every function here is pinned by the CPU test-suite
 (tests/test_oracle_*.py) against closed forms, brute force, special cases that
 reduce to textbook routines (rigid CPD, weighted Procrustes), finite
-differences, or invariants -- except the surface normal at a repeated smallest
-eigenvalue, which is not unique ("parity unpinned": only n n^T at a clear
-eigengap is compared).
+differences, or invariants.  The 86 lifted statistics are pinned by the
+quadratic they encode: D(G) rebuilt from them equals the dense double sum of
+P_mn d_mn(G) at arbitrary 3 x 4 matrices G, and its derivatives along SE(3)
+are Eq. (11)-(12) as printed.  Not pinned: the surface normal at a repeated
+smallest eigenvalue, which is not unique ("parity unpinned": only n n^T at a
+clear eigengap is compared).
 """
 from __future__ import annotations
 
@@ -404,6 +407,18 @@ def pd_of(cols, X, R, t):
     Xg = _f64(X) @ _f64(R).T + _f64(t)
     return float(np.sum(np.einsum("ni,nij,nj->n", Xg, cols.A, Xg)
                         - 2.0 * np.einsum("ni,ni->n", Xg, cols.B) + cols.C))
+
+
+def nll_terms(es, w=None, w0=None):
+    """The three E-step by-products that complete the 86 statistics: the sum
+    over sources of log(sum_m K_mn + gamma), the outlier mass
+    sum_n gamma / (sum_m K_mn + gamma) (the outlier posterior of each source,
+    Eq. 5/9), and sum_n log w_n.  With them the negative log-likelihood of
+    Eq. (4) is  -(t[2] + t[0] - (3/2) N log(2 pi sigma^2))."""
+    w = np.full(es.Ksum.shape[0], float(w0)) if w is None else _f64(w)
+    den = es.Ksum + es.gamma
+    return [float(np.sum(np.log(den))), float(np.sum(es.gamma / den)),
+            float(np.sum(np.log(w)))]
 
 
 def lifted_stats(cols, X, nll_terms=None):

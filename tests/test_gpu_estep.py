@@ -78,10 +78,7 @@ def _check_estep(X32, Y32, n32, a32, R, t, s2, w0=0.1, V=None, pi=None, w=None, 
                  V=V, pi=None if pi is None else pi.astype(np.float64),
                  w=None if w is None else w.astype(np.float64), exact_normalizer=exact)
     cols = O.columns(es.P, X, Y, n32.astype(np.float64), a32.astype(np.float64), R, t)
-    ww = np.full(len(X), w0) if w is None else w.astype(np.float64)
-    nll_terms = [np.sum(np.log(es.Ksum + es.gamma)), np.sum(es.gamma / (es.Ksum + es.gamma)),
-                 np.sum(np.log(ww))]
-    ref_stats = O.lifted_stats(cols, X, nll_terms)
+    ref_stats = O.lifted_stats(cols, X, O.nll_terms(es, None if w is None else w, w0))
     g = L.estep(dev(X32), dev(Y32), dev(n32), dev(a32), R, t, s2, w0=w0,
                 V=0.0 if V is None else V, pi=None if pi is None else dev(pi),
                 w=None if w is None else dev(w), exact=exact, backend=backend, dump_P=check_P,
