@@ -27,7 +27,7 @@
 //  * estep_pairs_items (default): all lanes of a wave take the same target
 //    at the same time, so the target record is wave-uniform and is read
 //    through the scalar data cache straight into SGPR operands; each lane keeps
-//    4 sources in registers.  Target tiles that provably hold only exact-zero
+//    2 sources in registers (one of each half of a 128-source group).  Target tiles that provably hold only exact-zero
 //    exponentials for a source group are dropped, and the rest is cut into
 //    balanced work items.
 //  * estep_pairs_lds<S>: the block stages tiles of target records in LDS and
@@ -184,6 +184,9 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 // groups to balance, more waves per SIMD) and than 1 on both benchmark pairs
 constexpr int kSrcPerLane = 2;
 constexpr int kGroup = 64 * kSrcPerLane;
+// the per-half culling (two half boxes per group, slot s of a lane = half s)
+// is written for exactly two sources per lane
+static_assert(kSrcPerLane == 2, "per-half culling assumes two sources per lane");
 // Per source group: the boxes of its two halves of 64 sources (the sources
 // of slot 0 and slot 1 of the pair kernel's lanes), lo and hi each.
 constexpr int kGBox = 16;

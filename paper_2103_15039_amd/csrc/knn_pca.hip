@@ -3,16 +3,17 @@
 // kappa and the penalty alpha.
 //
 // The caller puts the cloud in Hilbert order (order.hip) and passes the sorted
-// copy Ys (x, y, z, original index).  Pass 1 (knn_tiles): S waves per tile of
-// 64 sorted queries keep the k best (distance, original index) keys of each
-// query in registers.  Each scans the own tile and the two next to it first;
-// then every other tile whose box lies farther from the box of the wave's
-// queries than their largest current k-th distance is skipped, which cannot
-// change any answer (with a relative margin of 1e-5 for the float32 rounding
-// of the distances), and the S waves share the remaining tiles; knn_merge
-// combines their lists.  Isolated queries, whose k-th distance would widen
-// the search of the whole wave, are instead answered by pass 2 (knn_hard),
-// one wave per query over all points.
+// copy Ys (x, y, z, original index).  Pass 1a (knn_seed): one wave per tile
+// of 64 sorted queries scans the own tile and the two next to it, which gives
+// every query a first list of its k best (distance, original index) keys and
+// a bound on its k-th distance.  Pass 1b (knn_tiles): S waves per query tile
+// skip every other tile whose box lies farther from the box of the wave's
+// queries than their largest bound, which cannot change any answer (with a
+// relative margin of 1e-5 for the float32 rounding of the distances), and
+// share the remaining tiles; knn_merge combines their lists.  Isolated
+// queries, whose k-th distance would widen the search of the whole wave, are
+// instead answered by pass 2 (knn_hard), one wave per query over the tiles
+// that their pass-1 list cannot rule out.
 // Distances are float32 ((dx*dx + dy*dy) + dz*dz), no contraction, so that
 // the neighbour set is decided exactly as the float32 definition says; keys
 // are ordered by (distance bits, original index), i.e. by distance with ties
