@@ -8,7 +8,8 @@
 // an exact quadratic in the 12 entries of G.  Newton steps are taken on the
 // group: G <- G exp(xi^), xi = -Hs^{-1} grad, where grad and the symmetrised
 // Hessian Hs are the right derivatives of Eq. 11-12 (divided, as printed, by
-// sigma^2).  If Hs is not positive definite the Gauss-Newton part is used;
+// sigma^2).  If Hs is not positive definite the Gauss-Newton part is used
+// through its minimum-norm least-squares solution;
 // steps are halved until D does not grow beyond a rounding allowance (the
 // change of D is evaluated as the exact difference of the quadratic).  After
 // the pose, sigma^2 = D(G_new) / (3 N_P) (Sec. 3.5, last paragraph).
@@ -104,6 +105,70 @@ __device__ bool chol_solve6(const double A[6][6], const double g[6], double x[6]
     double s = y[i];
     for (int k = i + 1; k < 6; ++k) s -= L[k][i] * x[k];
     x[i] = s * inv[i];
+  }
+  return true;
+}
+
+// Minimum-norm least-squares solution of A x = -g for the symmetric 6x6
+// Gauss-Newton matrix A (singular for degenerate inputs such as a single
+// source point, whose rotations about itself are free): eigen-decomposition by cyclic Jacobi rotations, then
+//   x = -sum_i (v_i . g / lambda_i) v_i  over |lambda_i| > 6 eps max|lambda|,
+// the pseudo-inverse a singular-value solve with that cutoff gives (for a
+// symmetric matrix the singular values are the |lambda_i|).  False if A is 0.
+__device__ bool pinv_solve6(const double Ain[6][6], const double g[6], double x[6]) {
+  double a[6][6], v[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) {
+      a[r][c] = Ain[r][c];
+      v[r][c] = r == c ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int r = 0; r < 6; ++r) {
+      dia += a[r][r] * a[r][r];
+      for (int c = r + 1; c < 6; ++c) off += a[r][c] * a[r][c];
+    }
+    if (off == 0.0 || off <= 1e-36 * dia) break;
+    for (int p = 0; p < 5; ++p)
+      for (int q = p + 1; q < 6; ++q) {
+        const double apq = a[p][q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+        const double t = fabs(theta) > 1e150
+                             ? 0.5 / theta
+                             : (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0);
+        const double sn = t * c;
+        for (int k = 0; k < 6; ++k) {  // columns p, q
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 6; ++k) {  // rows p, q
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+        a[p][q] = a[q][p] = 0.0;
+        for (int k = 0; k < 6; ++k) {
+          const double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = c * vkp - sn * vkq;
+          v[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  double mx = 0.0;
+  for (int i = 0; i < 6; ++i) mx = fmax(mx, fabs(a[i][i]));
+  if (!(mx > 0.0) || !isfinite(mx)) return false;
+  const double cut = 6.0 * 2.220446049250313e-16 * mx;
+  for (int i = 0; i < 6; ++i) x[i] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    const double lam = a[j][j];
+    if (!(fabs(lam) > cut)) continue;
+    double d = 0.0;
+    for (int k = 0; k < 6; ++k) d += v[k][j] * g[k];
+    const double f = -d / lam;
+    for (int k = 0; k < 6; ++k) x[k] += f * v[k][j];
   }
   return true;
 }
@@ -371,13 +436,9 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
       bool ok = chol_solve6(m.Hs, m.grad, xi);
       if (!ok) {
         ++gnf;
-        ok = chol_solve6(m.Hgn, m.grad, xi);
-        if (!ok) {
-          double mx = 0.0;
-          for (int i = 0; i < 6; ++i) mx = fmax(mx, m.Hgn[i][i]);
-          for (int i = 0; i < 6; ++i) m.Hgn[i][i] += 1e-10 * mx + 1e-300;
-          ok = chol_solve6(m.Hgn, m.grad, xi);
-        }
+        // least squares, as a singular Gauss-Newton matrix (degenerate
+        // inputs) can pass a Cholesky factorisation by rounding alone
+        ok = pinv_solve6(m.Hgn, m.grad, xi);
       }
       for (int i = 0; i < 6; ++i) m.xi[i] = ok ? xi[i] : 0.0;
       m.go = ok ? 1 : 0;

@@ -4,9 +4,13 @@
 * one E step: every statistic against the C form of the oracle over all
   M x N pairs; per-source sums of a random sample of sources against the
   dense NumPy oracle; the column identity for every source;
-* registration: the 20k pair for 25 EM iterations and the 100k x 50k pair for
-  3 iterations against the oracle driven by the C E step (rotation <= 1e-3
-  deg, translation <= 1e-5 * box diagonal, NLL per iteration 1e-6).
+* registration: the 20k pair for its whole 50 EM iterations, and the
+  100k x 50k pair for 3 iterations from the identity and 5 from its ground
+  truth at a small sigma^2, against the oracle driven by the C E step
+  (rotation <= 1e-3 deg, translation <= 1e-5 * box diagonal, NLL per
+  iteration 1e-6); after the runs that end in the converged regime, one E
+  step at the oracle's final pose and sigma^2 with all 86 statistics against
+  the C oracle.
 Normals for the E-step checks are seeded random unit vectors and penalties
 (an E step does not care where they come from); registrations compute their
 own normals on each side.
@@ -103,22 +107,107 @@ def _oracle_normals(Y, k):
     return n, O.penalty_alpha(kappa, 30.0, 0.2)
 
 
-@pytest.mark.parametrize("name,iters", [("rgbd", 25), ("lidar", 3)])
-def test_register_full_size(name, iters):
-    p = pair(name)
-    k = 20
-    g = L.register(dev(p.X), dev(p.Y), k=k, max_iter=iters)
-    n, a = _oracle_normals(p.Y, k)
+def _spatial_order(X, bits=10):
+    """A permutation that lists the points cell by cell along a Z-order curve
+    of a 2^bits grid over their box (numpy only): lsgcpd_estep takes the
+    sources in the caller's order, and spatially coherent groups of sources
+    let its exact culling work as it does inside a registration.  The
+    statistics are sums over all sources, so any order gives them."""
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    q = ((X - lo) / np.maximum(hi - lo, 1e-30) * ((1 << bits) - 1)).astype(np.uint64)
+    key = np.zeros(len(X), np.uint64)
+    for b in range(bits):
+        for a in range(3):
+            key |= ((q[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + a)
+    return np.argsort(key, kind="stable")
+
+
+def _stats_vs_c_oracle(p, n, a, R, t, s2, w0=0.1):
+    """One GPU E step against the C oracle over all M x N pairs: every one of
+    the 86 statistics within 2e-6 of the sum of the magnitudes of its terms
+    (the float32 exponential's relative error, argument rounding included, is
+    below 2e-6 wherever a term is not negligible), the NLL within 1e-6.
+    Returns the fraction of pairs the GPU evaluated."""
+    N, M = len(p.X), len(p.Y)
     V = O.working_volume(p.Y)
-    s20 = CO.sigma2_init(p.X, p.Y, np.eye(3), np.zeros(3))
-    o = O.register(p.X, p.Y, max_iter=iters, target_normals=n, target_alpha=a, V=V,
-                   sigma2_0=s20, estep_columns=CO.register_columns_fn(p.X, p.Y, n, a, 0.1, V))
+    p = datagen.Pair(X=np.ascontiguousarray(p.X[_spatial_order(p.X)]), Y=p.Y, R_gt=p.R_gt,
+                     t_gt=p.t_gt)
+    L.profile_enable(True)
+    L.profile_read(reset=True)
+    g = L.estep(dev(p.X), dev(p.Y), dev(n), dev(a), R, t, s2, w0=w0)
+    prof = L.profile_read(reset=True)
+    L.profile_enable(False)
+    cc, ks = CO.estep_columns(p.X, p.Y, n, a, R, t, s2, w0=w0, V=V)
+    gamma = (2 * np.pi * s2) ** 1.5 / V
+    ref = O.lifted_stats(cc, p.X, [np.sum(np.log(ks + gamma)), np.sum(gamma / (ks + gamma)),
+                                   N * np.log(w0)])
+    scale = _abs_scale(cc, p.X.astype(np.float64))
+    scale[83:] = np.abs(ref[83:]) + N
+    d = np.abs(g.stats - ref)
+    bad = np.nonzero(d > 2e-6 * scale + 1e-300)[0]
+    assert bad.size == 0, f"stats {bad[:8]}: gpu {g.stats[bad[:4]]} ref {ref[bad[:4]]}"
+    nll = -(ref[85] + ref[83] - 1.5 * N * np.log(2 * np.pi * s2))
+    assert g.nll == pytest.approx(nll, rel=1e-6)
+    return prof["evaluated_pairs"] / (M * N)
+
+
+def _c_register(p, n, a, iters, R0=None, t0=None, s20=None):
+    V = O.working_volume(p.Y)
+    if s20 is None:
+        s20 = CO.sigma2_init(p.X, p.Y, np.eye(3) if R0 is None else R0,
+                             np.zeros(3) if t0 is None else t0)
+    return O.register(p.X, p.Y, max_iter=iters, target_normals=n, target_alpha=a, V=V,
+                      R0=R0, t0=t0, sigma2_0=s20,
+                      estep_columns=CO.register_columns_fn(p.X, p.Y, n, a, 0.1, V))
+
+
+def _check_registration(g, o, p, iters):
     diag = O.bbox_diag(p.Y)
     assert g.iters == o.iters == iters
     assert O.rotation_error_deg(g.R, o.R) <= 1e-3
     assert O.translation_error(g.t, o.t) <= 1e-5 * diag
     np.testing.assert_allclose(g.nll, o.nll, rtol=1e-6)
     assert g.sigma2 == pytest.approx(o.sigma2, rel=1e-4)
+
+
+def test_register_rgbd_full_run_and_final_estep():
+    """The RGB-D pair's whole 50-iteration registration against the oracle
+    driven by the C E step; then one E step at the pose and sigma^2 the
+    oracle's registration ends on (the late regime, where the exact culling
+    drops most pairs), all 86 statistics against the C oracle."""
+    p = pair("rgbd")
+    k, iters = 20, 50
+    g = L.register(dev(p.X), dev(p.Y), k=k, max_iter=iters)
+    n, a = _oracle_normals(p.Y, k)
+    o = _c_register(p, n, a, iters)
+    _check_registration(g, o, p, iters)
+    frac = _stats_vs_c_oracle(p, n.astype(np.float32), a.astype(np.float32), o.R, o.t, o.sigma2)
+    assert frac < 0.5   # the check covered the culled regime
+
+
+def test_register_lidar_from_truth_and_final_estep():
+    """The LiDAR pair started at its ground-truth pose with sigma^2_0 = 0.05:
+    5 EM iterations against the oracle driven by the C E step reach the
+    converged regime; then one E step at the oracle's final pose and sigma^2,
+    all 86 statistics against the C oracle."""
+    p = pair("lidar")
+    k, iters = 20, 5
+    g = L.register(dev(p.X), dev(p.Y), k=k, max_iter=iters, R0=p.R_gt, t0=p.t_gt,
+                   sigma2_init=0.05)
+    n, a = _oracle_normals(p.Y, k)
+    o = _c_register(p, n, a, iters, R0=p.R_gt, t0=p.t_gt, s20=0.05)
+    _check_registration(g, o, p, iters)
+    frac = _stats_vs_c_oracle(p, n.astype(np.float32), a.astype(np.float32), o.R, o.t, o.sigma2)
+    assert frac < 0.5
+
+
+def test_register_lidar_first_iterations():
+    """The LiDAR pair from the identity, 3 EM iterations (the dense regime)."""
+    p = pair("lidar")
+    k, iters = 20, 3
+    g = L.register(dev(p.X), dev(p.Y), k=k, max_iter=iters)
+    n, a = _oracle_normals(p.Y, k)
+    _check_registration(g, _c_register(p, n, a, iters), p, iters)
 
 
 def test_register_cf_full_size():
