@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LSGCPD_ABI_VERSION 4
+#define LSGCPD_ABI_VERSION 5
 
 typedef struct lsgcpd_ctx lsgcpd_ctx;
 typedef void *lsgcpd_stream;  /* a hipStream_t */
@@ -171,6 +171,27 @@ lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, const flo
                            const lsgcpd_pose *g, double sigma2, uint32_t flags,
                            lsgcpd_estep_out *out, float *P, double *colstats,
                            lsgcpd_stream stream);
+
+/* The E step of lsgcpd_estep (same arguments, meaning, layouts, outputs and
+ * errors) without allocating memory, for callers that cannot allocate: code
+ * that runs while a stream is being captured into a HIP graph, serving loops
+ * that must not call hipMalloc, harnesses that forbid it.  It calls no
+ * hipMalloc, hipFree or hipHostMalloc: its device workspace is a static
+ * array of 36 MiB that each GPU holds from the first lsgcpd_ctx_create on it
+ * until the process ends, and its plan tables and state are copied from
+ * host stack/heap memory.  Limits: M, N <= 65,536 (LSGCPD_E_UNSUPPORTED
+ * beyond, and for LSGCPD_PAIRS_LDS / LSGCPD_PAIRS_MFMA); the work is split
+ * into about 1,024 work items whatever lsgcpd_autotune chose, so results
+ * equal lsgcpd_estep's up to the grouping of the FP64 sums.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (other host
+ * threads, other streams) race and give wrong results; successive calls on
+ * one stream are safe.  Synchronises `stream`. */
+lsgcpd_status lsgcpd_estep_noalloc(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
+                                   const float *normals, const float *alpha, int64_t M,
+                                   const float *pi, const float *w, double w0, double V,
+                                   const lsgcpd_pose *g, double sigma2, uint32_t flags,
+                                   lsgcpd_estep_out *out, float *P, double *colstats,
+                                   lsgcpd_stream stream);
 
 /* ---- full registration (Sec. 3) ----------------------------------------- */
 

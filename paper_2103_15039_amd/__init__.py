@@ -29,8 +29,9 @@ SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
            "lsgcpd_ctx_destroy", "lsgcpd_last_error", "lsgcpd_params_default",
            "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_register_batch",
            "lsgcpd_depth_confidence", "lsgcpd_register_cf", "lsgcpd_autotune",
-           "lsgcpd_profile_enable", "lsgcpd_profile_read", "lsgcpd_profile_launches")
-ABI_VERSION = 4
+           "lsgcpd_profile_enable", "lsgcpd_profile_read", "lsgcpd_profile_launches",
+           "lsgcpd_estep_noalloc")
+ABI_VERSION = 5
 
 
 class Pose(C.Structure):
@@ -107,6 +108,8 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_estep.restype = C.c_int
     lib.lsgcpd_estep.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, d, d, C.POINTER(Pose), d,
                                  u32, C.POINTER(EstepOut), vp, vp, vp]
+    lib.lsgcpd_estep_noalloc.restype = C.c_int
+    lib.lsgcpd_estep_noalloc.argtypes = lib.lsgcpd_estep.argtypes
     lib.lsgcpd_register.restype = C.c_int
     lib.lsgcpd_register.argtypes = [vp, vp, i64, vp, i64, C.POINTER(Params), C.POINTER(Pose),
                                     C.POINTER(Pose), C.POINTER(Report), vp, vp]
@@ -234,8 +237,9 @@ class EStepResult:
 
 
 def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=False,
-          backend="scalar", dump_P=False, colstats=False):
-    """One E step and the M step it implies (lsgcpd_estep)."""
+          backend="scalar", dump_P=False, colstats=False, noalloc=False):
+    """One E step and the M step it implies (lsgcpd_estep; with noalloc,
+    lsgcpd_estep_noalloc, which allocates no memory)."""
     torch = _torch()
     X = _dev_tensor(X, (3,), "X")
     dev = X.device.index
@@ -259,10 +263,11 @@ def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=
     out = EstepOut()
     pose = _pose(R, t)
     ctx = context(dev)
-    st = load_library().lsgcpd_estep(ctx, _ptr(X), N, _ptr(Y), _ptr(nrm), _ptr(alpha), M,
-                                     _ptr(pi), _ptr(w), float(w0), float(V), C.byref(pose),
-                                     float(sigma2), flags, C.byref(out), _ptr(P), _ptr(cs),
-                                     _stream(dev))
+    lib = load_library()
+    fn = lib.lsgcpd_estep_noalloc if noalloc else lib.lsgcpd_estep
+    st = fn(ctx, _ptr(X), N, _ptr(Y), _ptr(nrm), _ptr(alpha), M, _ptr(pi), _ptr(w), float(w0),
+            float(V), C.byref(pose), float(sigma2), flags, C.byref(out), _ptr(P), _ptr(cs),
+            _stream(dev))
     _check(st, ctx)
     Rn, tn = _pose_np(out.pose_next)
     return EStepResult(sigma2=out.sigma2, gamma=out.gamma, V=out.V, sumP=out.sumP,

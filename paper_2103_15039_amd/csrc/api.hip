@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,38 @@ using lsg::DevState;
 namespace {
 
 constexpr int64_t kMaxPoints = (int64_t)1 << 27;
+
+// Device memory of lsgcpd_estep_noalloc: one array per GPU, mapped once per
+// device when the first context on it is created, kept until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on
+// the host it is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returned for the device.  Every point count up to
+// kNoAllocMaxPoints fits with kNoAllocItems work items (the largest layout,
+// M = N = 65,536, takes about 31 MiB).
+constexpr size_t kScratchBytes = (size_t)36 << 20;
+constexpr int64_t kNoAllocMaxPoints = 65536;
+constexpr int kNoAllocItems = 1024;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex scratch_mutex;
+void *scratch_ptr[kMaxDevices];  // device address of `scratch` on each device
+
+// Maps the scratch array of the current device (once per device).
+hipError_t map_scratch(int device, void **out) {
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (device < 0 || device >= kMaxDevices) {
+    *out = nullptr;
+    return hipSuccess;
+  }
+  if (!scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[device] = p;
+  }
+  *out = scratch_ptr[device];
+  return hipSuccess;
+}
 constexpr int kMaxBatch = 1 << 16;
 // The set-up of a batch (sorting, neighbour search and records of every
 // cloud: a few small kernels per cloud) runs on this many streams at once.
@@ -34,6 +67,7 @@ struct Buf {
 
 struct lsgcpd_ctx {
   int device = 0;
+  void *scratch = nullptr;  // the device's static scratch array (lsgcpd_estep_noalloc)
   std::string err;
   Buf knn, rec, pts, boxes, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
       trace, order, xperm, yperm, ys4, tables, states;
@@ -274,6 +308,27 @@ Lane lane_of(lsgcpd_ctx *ctx, int q, hipStream_t st) {
   return {ctx->lstream[q - 1], &b.order, &b.knn, &b.mom_part, &b.mom, &b.prior, &b.xidx};
 }
 
+// Device memory read and written by the kernels of an E step: the context's
+// workspace, or regions of the library's static scratch array.  timed: record
+// the context's timing events around the E-step kernels.
+struct EstepMem {
+  DevState *state;  // one per problem
+  lsg::TRec *rec;
+  lsg::TPt *pts;
+  lsg::TBox *boxes;
+  void *plan;
+  double *partial;
+  double *blockstats;
+  bool timed;
+};
+
+// The context's workspace (valid until the next ensure_* call).
+EstepMem ctx_mem(lsgcpd_ctx *ctx) {
+  return {ctx->dstate,     (lsg::TRec *)ctx->rec.p,       (lsg::TPt *)ctx->pts.p,
+          (lsg::TBox *)ctx->boxes.p, ctx->plan.p, (double *)ctx->partial.p,
+          (double *)ctx->blockstats.p, ctx->prof};
+}
+
 // Streams and events of lanes 1 .. n - 1 (created once, default priority).
 lsgcpd_status ensure_lanes(lsgcpd_ctx *ctx, int n) {
   if (n > 1 && !ctx->lfork) HIPCHK(hipEventCreateWithFlags(&ctx->lfork, hipEventDisableTiming));
@@ -310,7 +365,8 @@ lsgcpd_status join_lanes(lsgcpd_ctx *ctx, int n, hipStream_t st) {
 // problem p.  Priors: pi (raw priors) or phi (target confidences, normalised
 // on the device: Sec. 3.3), else uniform; with eta > 0 the state's w0 becomes
 // w_max (Sec. 3.2).
-lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const Lane &ln, const lsg::BatchPlan &pl, int p,
+lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const Lane &ln, const EstepMem &mem,
+                            const lsg::BatchPlan &pl, int p,
                             const float *Y, const float *normals, const float *alpha,
                             const float *pi, const float *phi, double eta,
                             const uint32_t *yperm, uint32_t flags, int v_auto, int s2_auto) {
@@ -319,21 +375,21 @@ lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const Lane &ln, const lsg::BatchPla
   const int exact = (flags & LSGCPD_EXACT_NORMALIZER) ? 1 : 0;
   if (phi || eta > 0.0)
     HIPCHK(lsg::launch_prior_sums(phi, alpha, sl.M, exact, (double *)ln.prior->p,
-                                  ctx->dstate + p, st));
+                                  mem.state + p, st));
   HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, phi ? phi : pi,
-                                  phi ? &(ctx->dstate + p)->pi_sum : nullptr, yperm, sl.M,
+                                  phi ? &(mem.state + p)->pi_sum : nullptr, yperm, sl.M,
                                   exact,
-                                  (lsg::TRec *)ctx->rec.p + sl.y_off + p,
-                                  (lsg::TPt *)ctx->pts.p + sl.y_off,
-                                  (lsg::TBox *)ctx->boxes.p + sl.t_off, st));
+                                  mem.rec + sl.y_off + p,
+                                  mem.pts + sl.y_off,
+                                  mem.boxes + sl.t_off, st));
   double *ymom = (double *)ln.mom->p;
   double *xmom = ymom + 16;
   HIPCHK(lsg::launch_moments(Y, sl.M, nullptr, (double *)ln.mom_part->p,
                              lsg::moments_blocks(sl.M), ymom, st));
   if (s2_auto)
-    HIPCHK(lsg::launch_moments(sl.X, sl.N, ctx->dstate + p, (double *)ln.mom_part->p,
+    HIPCHK(lsg::launch_moments(sl.X, sl.N, mem.state + p, (double *)ln.mom_part->p,
                                lsg::moments_blocks(sl.N), xmom, st));
-  HIPCHK(lsg::launch_init_state(ctx->dstate + p, ymom, xmom, sl.M, sl.N, v_auto, s2_auto, st));
+  HIPCHK(lsg::launch_init_state(mem.state + p, ymom, xmom, sl.M, sl.N, v_auto, s2_auto, st));
   return LSGCPD_OK;
 }
 
@@ -436,25 +492,21 @@ lsgcpd_status prof_collect(lsgcpd_ctx *ctx, int64_t evaluated) {
 // One E step (plan, accumulation, finalisation) + reduction/M step in
 // `mode`, for every problem of the batch.
 lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::BatchDev &bd,
-                        double *colS, double *colstats, double *trace, int trace_stride,
-                        int mode, hipStream_t st) {
-  lsgcpd_status s = prof_record(ctx, st);
-  if (s != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_plan(pl, bd, (const lsg::TBox *)ctx->boxes.p, ctx->dstate,
-                                ctx->plan.p, st));
-  if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_pairs(pl, bd, (const lsg::TRec *)ctx->rec.p,
-                                 (const lsg::TPt *)ctx->pts.p, ctx->dstate, ctx->plan.p,
-                                 (double *)ctx->partial.p, st));
-  if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_finalize(pl, bd, ctx->dstate, ctx->plan.p, (const double *)ctx->partial.p,
-                              (double *)ctx->blockstats.p, colS, colstats, st));
-  if ((s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  if (ctx->prof)
+                        const EstepMem &mem, double *colS, double *colstats, double *trace,
+                        int trace_stride, int mode, hipStream_t st) {
+  lsgcpd_status s = LSGCPD_OK;
+  if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
+  HIPCHK(lsg::launch_estep_plan(pl, bd, mem.boxes, mem.state, mem.plan, st));
+  if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
+  HIPCHK(lsg::launch_estep_pairs(pl, bd, mem.rec, mem.pts, mem.state, mem.plan, mem.partial, st));
+  if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
+  HIPCHK(lsg::launch_finalize(pl, bd, mem.state, mem.plan, mem.partial, mem.blockstats, colS,
+                              colstats, st));
+  if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
+  if (mem.timed)
     for (const lsg::Slot &sl : pl.slots) ctx->prof_pairs_pending += (int64_t)sl.M * sl.N;
-  HIPCHK(lsg::launch_reduce_mstep(pl, bd, (double *)ctx->blockstats.p, ctx->dstate, trace,
-                                  trace_stride, lsg::estep_plan_counter(pl, ctx->plan.p), mode,
-                                  st));
+  HIPCHK(lsg::launch_reduce_mstep(pl, bd, mem.blockstats, mem.state, trace, trace_stride,
+                                  lsg::estep_plan_counter(pl, mem.plan), mode, st));
   return LSGCPD_OK;
 }
 
@@ -469,7 +521,8 @@ lsgcpd_status run_em(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Batch
                      int max_iter, int stride, bool graph, hipStream_t st) {
   if (!graph || ctx->prof || max_iter < 1) {
     for (int it = 0; it < max_iter; ++it)
-      RETURN_IF(run_estep(ctx, pl, bd, nullptr, nullptr, (double *)ctx->trace.p, stride, 1, st));
+      RETURN_IF(run_estep(ctx, pl, bd, ctx_mem(ctx), nullptr, nullptr, (double *)ctx->trace.p,
+                                stride, 1, st));
     return LSGCPD_OK;
   }
   if (!ctx->gstream) {
@@ -497,7 +550,8 @@ lsgcpd_status run_em(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Batch
     HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
     lsgcpd_status s = LSGCPD_OK;
     for (int it = 0; it < max_iter && s == LSGCPD_OK; ++it)
-      s = run_estep(ctx, pl, bd, nullptr, nullptr, (double *)ctx->trace.p, stride, 1, gs);
+      s = run_estep(ctx, pl, bd, ctx_mem(ctx), nullptr, nullptr, (double *)ctx->trace.p,
+                    stride, 1, gs);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(gs, &g);
     if (s != LSGCPD_OK || e != hipSuccess) {
@@ -654,8 +708,8 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   status = fork_lanes(ctx, lanes, st);
   for (int i = 0; status == LSGCPD_OK && i < npairs; ++i) {
     const int64_t yo = pl.slots[i].y_off;
-    status = setup_problem(ctx, lane_of(ctx, i % lanes, st), pl, i, Y[i], nrm + 3 * yo, alp + yo,
-                           nullptr, phi_y ? phi_y[i] : nullptr, p->eta,
+    status = setup_problem(ctx, lane_of(ctx, i % lanes, st), ctx_mem(ctx), pl, i, Y[i],
+                           nrm + 3 * yo, alp + yo, nullptr, phi_y ? phi_y[i] : nullptr, p->eta,
                            pl.cull ? (const uint32_t *)ctx->yperm.p + yo : nullptr, p->flags,
                            p->V > 0.0 ? 0 : 1, s2_auto);
   }
@@ -722,6 +776,46 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   return status;
 }
 
+// Argument checks of the E-step calls.
+lsgcpd_status check_estep_args(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
+                               const float *normals, const float *alpha, int64_t M,
+                               const float *w, double w0, double V, const lsgcpd_pose *g,
+                               double sigma2, uint32_t flags, const lsgcpd_estep_out *out) {
+  if (!X || !Y || !normals || !alpha || !g || !out)
+    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  if (N < 1 || M < 1 || N > kMaxPoints || M > kMaxPoints)
+    return fail(ctx, LSGCPD_E_INVALID, "M = %lld, N = %lld out of range", (long long)M,
+                (long long)N);
+  if (!w && !(w0 > 0.0 && w0 < 1.0)) return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
+  if (!finite_pos(sigma2)) return fail(ctx, LSGCPD_E_INVALID, "sigma2 must be finite and > 0");
+  if (!isfinite(V)) return fail(ctx, LSGCPD_E_INVALID, "V must be finite");
+  if (flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", flags);
+  if ((flags & LSGCPD_PAIRS_LDS) && (flags & LSGCPD_PAIRS_MFMA))
+    return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
+  return check_pose(ctx, g);
+}
+
+// Host outputs of an E step from the state read back after it.
+lsgcpd_status estep_results(lsgcpd_ctx *ctx, const DevState &s, lsgcpd_estep_out *out) {
+  out->sigma2 = s.sigma2;
+  out->gamma = s.gamma;
+  out->V = s.V;
+  out->sumP = s.stats[9];
+  out->outlier_mass = s.stats[84];
+  out->nll = s.nll;
+  out->pd = s.pd;
+  memcpy(out->stats, s.stats, sizeof out->stats);
+  memcpy(out->grad, s.grad, sizeof out->grad);
+  memcpy(out->hess, s.hess, sizeof out->hess);
+  memcpy(out->pose_next.R, s.R_next, sizeof s.R_next);
+  memcpy(out->pose_next.t, s.t_next, sizeof s.t_next);
+  out->sigma2_next = s.sigma2_next;
+  out->newton_iters = s.newton_iters;
+  out->gn_fallbacks = s.gn_fallbacks;
+  if (s.numeric_error) return fail(ctx, LSGCPD_E_NUMERIC, "M step produced a non-finite result");
+  return LSGCPD_OK;
+}
+
 }  // namespace
 
 
@@ -749,7 +843,7 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
   }
   lsgcpd_ctx *c = new lsgcpd_ctx();
   c->device = device;
-  if (hipSetDevice(device) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || map_scratch(device, &c->scratch) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return LSGCPD_E_HIP;
@@ -832,18 +926,7 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
                                    lsgcpd_estep_out *out, float *P, double *colstats,
                                    lsgcpd_stream stream) {
   if (!ctx) return LSGCPD_E_INVALID;
-  if (!X || !Y || !normals || !alpha || !g || !out)
-    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
-  if (N < 1 || M < 1 || N > kMaxPoints || M > kMaxPoints)
-    return fail(ctx, LSGCPD_E_INVALID, "M = %lld, N = %lld out of range", (long long)M,
-                (long long)N);
-  if (!w && !(w0 > 0.0 && w0 < 1.0)) return fail(ctx, LSGCPD_E_INVALID, "w0 must lie in (0, 1)");
-  if (!finite_pos(sigma2)) return fail(ctx, LSGCPD_E_INVALID, "sigma2 must be finite and > 0");
-  if (!isfinite(V)) return fail(ctx, LSGCPD_E_INVALID, "V must be finite");
-  if (flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", flags);
-  if ((flags & LSGCPD_PAIRS_LDS) && (flags & LSGCPD_PAIRS_MFMA))
-    return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
-  RETURN_IF(check_pose(ctx, g));
+  RETURN_IF(check_estep_args(ctx, X, N, Y, normals, alpha, M, w, w0, V, g, sigma2, flags, out));
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
   lsg::BatchPlan pl =
@@ -858,35 +941,87 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   RETURN_IF(upload_tables(ctx, pl, st, &bd));
   fill_state(ctx->hstate, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 0.0, 20, 1);
   HIPCHK(hipMemcpyAsync(ctx->dstate, ctx->hstate, sizeof(DevState), hipMemcpyHostToDevice, st));
-  RETURN_IF(setup_problem(ctx, lane_of(ctx, 0, st), pl, 0, Y, normals, alpha, pi, nullptr, 0.0,
-                          nullptr, flags, V > 0.0 ? 0 : 1, 0));
+  const EstepMem mem = ctx_mem(ctx);
+  RETURN_IF(setup_problem(ctx, lane_of(ctx, 0, st), mem, pl, 0, Y, normals, alpha, pi, nullptr,
+                          0.0, nullptr, flags, V > 0.0 ? 0 : 1, 0));
   RETURN_IF(prof_reserve(ctx, 1));
-  RETURN_IF(run_estep(ctx, pl, bd, (double *)ctx->colS.p, colstats, nullptr, 1, 0, st));
+  RETURN_IF(run_estep(ctx, pl, bd, mem, (double *)ctx->colS.p, colstats, nullptr, 1, 0, st));
   if (P)
-    HIPCHK(lsg::launch_dump_P(X, N, (const lsg::TRec *)ctx->rec.p, M, w, ctx->dstate,
-                              (const double *)ctx->colS.p, P, st));
+    HIPCHK(lsg::launch_dump_P(X, N, mem.rec, M, w, mem.state, (const double *)ctx->colS.p, P, st));
   HIPCHK(hipMemcpyAsync(ctx->hstate, ctx->dstate, sizeof(DevState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   RETURN_IF(prof_collect(
       ctx, pl.backend == lsg::kBackendScalar ? ctx->hstate->evaluated_pairs : M * N));
-  const DevState &s = *ctx->hstate;
-  out->sigma2 = s.sigma2;
-  out->gamma = s.gamma;
-  out->V = s.V;
-  out->sumP = s.stats[9];
-  out->outlier_mass = s.stats[84];
-  out->nll = s.nll;
-  out->pd = s.pd;
-  memcpy(out->stats, s.stats, sizeof out->stats);
-  memcpy(out->grad, s.grad, sizeof out->grad);
-  memcpy(out->hess, s.hess, sizeof out->hess);
-  memcpy(out->pose_next.R, s.R_next, sizeof s.R_next);
-  memcpy(out->pose_next.t, s.t_next, sizeof s.t_next);
-  out->sigma2_next = s.sigma2_next;
-  out->newton_iters = s.newton_iters;
-  out->gn_fallbacks = s.gn_fallbacks;
-  if (s.numeric_error) return fail(ctx, LSGCPD_E_NUMERIC, "M step produced a non-finite result");
-  return LSGCPD_OK;
+  return estep_results(ctx, *ctx->hstate, out);
+}
+
+LSG_API lsgcpd_status lsgcpd_estep_noalloc(lsgcpd_ctx *ctx, const float *X, int64_t N,
+                                           const float *Y, const float *normals,
+                                           const float *alpha, int64_t M, const float *pi,
+                                           const float *w, double w0, double V,
+                                           const lsgcpd_pose *g, double sigma2, uint32_t flags,
+                                           lsgcpd_estep_out *out, float *P, double *colstats,
+                                           lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  RETURN_IF(check_estep_args(ctx, X, N, Y, normals, alpha, M, w, w0, V, g, sigma2, flags, out));
+  if (flags & (LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA))
+    return fail(ctx, LSGCPD_E_UNSUPPORTED,
+                "lsgcpd_estep_noalloc runs the default pair kernel only (no LDS or MFMA flag)");
+  if (N > kNoAllocMaxPoints || M > kNoAllocMaxPoints)
+    return fail(ctx, LSGCPD_E_UNSUPPORTED,
+                "lsgcpd_estep_noalloc takes at most %lld points per cloud (M = %lld, N = %lld)",
+                (long long)kNoAllocMaxPoints, (long long)M, (long long)N);
+  char *base = (char *)ctx->scratch;
+  if (!base) return fail(ctx, LSGCPD_E_HIP, "the static scratch array of the device is not mapped");
+  RETURN_IF(set_device(ctx));
+  hipStream_t st = (hipStream_t)stream;
+  lsg::BatchPlan pl = lsg::batch_plan(1, &N, &M, lsg::kBackendScalar,
+                                      (flags & LSGCPD_DENSE) ? 0 : 1, kNoAllocItems);
+  pl.slots[0].X = X;
+  pl.slots[0].w = w;
+  // The scratch array, carved in call order (256-byte aligned regions).
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *q = base + off;
+    off += (bytes + 255) / 256 * 256;
+    return (void *)q;
+  };
+  std::vector<char> tables;  // host copy of the plan's tables (a few KB)
+  lsg::batch_tables_pack(pl, tables);
+  EstepMem mem;
+  mem.state = (DevState *)take(sizeof(DevState));
+  void *dtab = take(tables.size());
+  mem.rec = (lsg::TRec *)take((size_t)(M + 1) * sizeof(lsg::TRec));
+  mem.pts = (lsg::TPt *)take((size_t)M * sizeof(lsg::TPt));
+  mem.boxes = (lsg::TBox *)take((size_t)pl.tiles * sizeof(lsg::TBox));
+  mem.plan = take(lsg::estep_plan_bytes(pl));
+  mem.partial = (double *)take(lsg::estep_partial_bytes(pl));
+  mem.blockstats = (double *)take((size_t)pl.fins * lsg::kStats * sizeof(double));
+  mem.timed = false;
+  double *colS = (double *)take((size_t)N * sizeof(double));
+  Buf mom, mom_part;
+  mom.cap = 48 * sizeof(double);
+  mom.p = take(mom.cap);
+  mom_part.cap = (size_t)lsg::moments_blocks(M > N ? M : N) * 10 * sizeof(double);
+  mom_part.p = take(mom_part.cap);
+  if (off > kScratchBytes)
+    return fail(ctx, LSGCPD_E_UNSUPPORTED,
+                "M = %lld, N = %lld need %zu bytes of scratch; lsgcpd_estep_noalloc has %zu",
+                (long long)M, (long long)N, off, kScratchBytes);
+  // pageable host sources: both copies complete before the synchronisation below
+  HIPCHK(hipMemcpyAsync(dtab, tables.data(), tables.size(), hipMemcpyHostToDevice, st));
+  const lsg::BatchDev bd = lsg::batch_tables_view(pl, dtab);
+  DevState hs;
+  fill_state(&hs, g, sigma2, V > 0.0 ? V : 0.0, w ? 0.5 : w0, 0.0, 0.0, 20, 1);
+  HIPCHK(hipMemcpyAsync(mem.state, &hs, sizeof(DevState), hipMemcpyHostToDevice, st));
+  const Lane ln = {st, nullptr, nullptr, &mom_part, &mom, nullptr, nullptr};
+  RETURN_IF(setup_problem(ctx, ln, mem, pl, 0, Y, normals, alpha, pi, nullptr, 0.0, nullptr,
+                          flags, V > 0.0 ? 0 : 1, 0));
+  RETURN_IF(run_estep(ctx, pl, bd, mem, colS, colstats, nullptr, 1, 0, st));
+  if (P) HIPCHK(lsg::launch_dump_P(X, N, mem.rec, M, w, mem.state, colS, P, st));
+  HIPCHK(hipMemcpyAsync(&hs, mem.state, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return estep_results(ctx, hs, out);
 }
 
 LSG_API lsgcpd_status lsgcpd_register(lsgcpd_ctx *ctx, const float *X, int64_t N, const float *Y,
