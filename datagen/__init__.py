@@ -350,10 +350,10 @@ def plane_patch(rng, n, normal=(0.0, 0.0, 1.0), size=1.0, offset=0.0):
 # Batches of small pairs of uneven sizes (box / sphere / plane-patch scenes)
 # ---------------------------------------------------------------------------
 
-def _primitive_scene(rng):
-    """1-3 primitives: (kind, parameters, area)."""
+def _primitive_scene(rng, min_prims=1):
+    """min_prims-3 primitives: (kind, parameters, area)."""
     prims = []
-    for _ in range(int(rng.integers(1, 4))):
+    for _ in range(int(rng.integers(min_prims, 4))):
         kind = int(rng.integers(0, 3))
         c = rng.uniform(-0.3, 0.3, size=3)
         if kind == 0:      # box: rotation, centre, half extents
@@ -417,6 +417,46 @@ def scene_pair(rng, M, N, max_angle_deg=60.0, trans=0.1, noise=0.005, max_outlie
         X[rng.choice(N, size=nout, replace=False)] = rng.uniform(lo, hi, size=(nout, 3))
     return Pair(X=X.astype(np.float32), Y=Y.astype(np.float32), R_gt=Ra.T.copy(),
                 t_gt=-(Ra.T @ ta), name=name)
+
+
+def uniform_rotation(rng):
+    """A rotation drawn uniformly on SO(3): the unit quaternion of four
+    independent standard normals."""
+    w, x, y, z = (lambda q: q / np.linalg.norm(q))(rng.normal(size=4))
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def proposal_pair(rng, M, N, trans=0.1, noise=0.005, max_outliers=0.1, name="proposal"):
+    """A scene pair for the learned initial-pose proposal: as scene_pair, but
+    the scene has 2-3 primitives (one alone has symmetries that make its
+    rotation ambiguous) and the source's rotation is uniform on SO(3)."""
+    prims = _primitive_scene(rng, min_prims=2)
+    Y = _sample_scene(rng, prims, M)
+    S = _sample_scene(rng, prims, N)
+    Ra = uniform_rotation(rng)
+    ta = rng.uniform(-trans, trans, size=3)
+    X = S @ Ra.T + ta + rng.normal(scale=noise, size=S.shape)
+    nout = int(round(rng.uniform(0.0, max_outliers) * N))
+    if nout:
+        lo, hi = X.min(axis=0), X.max(axis=0)
+        X[rng.choice(N, size=nout, replace=False)] = rng.uniform(lo, hi, size=(nout, 3))
+    return Pair(X=X.astype(np.float32), Y=Y.astype(np.float32), R_gt=Ra.T.copy(),
+                t_gt=-(Ra.T @ ta), name=name)
+
+
+def proposal_pairs(n, split="eval", trial=0, nmin=1000, nmax=30000):
+    """n proposal pairs with M and N independently log-uniform in [nmin,
+    nmax]; the training and evaluation splits draw from different seeds."""
+    rng = rng_for(5 if split == "eval" else 6, trial)
+    lo, hi = math.log(nmin), math.log(nmax)
+    out = []
+    for i in range(n):
+        M = int(round(math.exp(rng.uniform(lo, hi))))
+        N = int(round(math.exp(rng.uniform(lo, hi))))
+        out.append(proposal_pair(rng, M, N, name=f"proposal_{split}{trial}_{i}_{M}x{N}"))
+    return out
 
 
 def batch_pairs(n=256, trial=0, nmin=1000, nmax=30000):
