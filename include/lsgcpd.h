@@ -74,6 +74,24 @@ typedef enum {
                                        context and replayed by later calls of
                                        the same sizes and parameters (ignored
                                        while kernel timing is on) */
+#define LSGCPD_BF16_CROSS 32u       /* E steps at large sigma^2 evaluate the
+                                       exponent on the matrix cores: c d_mn as
+                                       the product of lifted quadratic features
+                                       (Eq. 10's bilinear structure), each split
+                                       into BF16 high and low parts, FP32 sums,
+                                       and the accumulation as a second BF16
+                                       product.  An E step takes this path only
+                                       while its exponent error bound,
+                                       |dz| <= 4.96e-5 (1 + alpha_m)(|u| + |v|)^2
+                                       with u, v the source and target in units
+                                       of sqrt(2 sigma^2 / log2 e) about the box
+                                       centre of 64 neighbouring sources, stays
+                                       below 1/32 for every pair within distance
+                                       2 of the sources' box (the early, large-
+                                       sigma^2 iterations; typical errors are
+                                       1e-4); the others run the FP64 kernel.
+                                       Not with LSGCPD_DENSE, _PAIRS_LDS or
+                                       _PAIRS_MFMA (LSGCPD_E_INVALID) */
 
 typedef struct {
   double R[9]; /* row-major rotation */
@@ -148,6 +166,8 @@ typedef struct {
   double sigma2_next;        /* sigma^2 after that M step                      */
   int32_t newton_iters;
   int32_t gn_fallbacks;
+  int32_t bf16_cross;        /* 1 if the LSGCPD_BF16_CROSS path ran this E step */
+  int32_t pad;
 } lsgcpd_estep_out;
 
 /* One E step at pose g and variance sigma2, plus the M step it implies.
@@ -226,6 +246,8 @@ typedef struct {
   double w0;             /* uniform outlier weight used (w_max when eta > 0)  */
   int64_t n_used;        /* source / target points registered (after the     */
   int64_t m_used;        /* truncation of lsgcpd_register_cf)                */
+  int32_t bf16_steps;    /* E steps that took the LSGCPD_BF16_CROSS path      */
+  int32_t pad;
 } lsgcpd_report;
 
 /* Fills p with the defaults used by the examples: k=10, alpha_max=30,

@@ -22,6 +22,7 @@ PAIRS_LDS = 2
 PAIRS_MFMA = 4
 DENSE = 8
 GRAPH = 16
+BF16_CROSS = 32
 _BACKENDS = {"scalar": 0, "lds": PAIRS_LDS, "mfma": PAIRS_MFMA, "dense": DENSE}
 NSTATS = 86
 
@@ -43,7 +44,8 @@ class EstepOut(C.Structure):
                 ("sumP", C.c_double), ("outlier_mass", C.c_double), ("nll", C.c_double),
                 ("pd", C.c_double), ("stats", C.c_double * NSTATS), ("grad", C.c_double * 6),
                 ("hess", C.c_double * 36), ("pose_next", Pose), ("sigma2_next", C.c_double),
-                ("newton_iters", C.c_int32), ("gn_fallbacks", C.c_int32)]
+                ("newton_iters", C.c_int32), ("gn_fallbacks", C.c_int32),
+                ("bf16_cross", C.c_int32), ("pad", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -57,7 +59,7 @@ class Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("gn_fallbacks", C.c_int32),
                 ("sigma2", C.c_double), ("nll_first", C.c_double), ("nll_last", C.c_double),
                 ("V", C.c_double), ("w0", C.c_double), ("n_used", C.c_int64),
-                ("m_used", C.c_int64)]
+                ("m_used", C.c_int64), ("bf16_steps", C.c_int32), ("pad", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -234,12 +236,14 @@ class EStepResult:
     gn_fallbacks: int
     P: object = None          # torch (M, N) float32 if requested
     colstats: object = None   # torch (N, 16) float64 if requested
+    bf16_cross: bool = False  # the LSGCPD_BF16_CROSS path ran this E step
 
 
 def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=False,
-          backend="scalar", dump_P=False, colstats=False, noalloc=False):
+          backend="scalar", dump_P=False, colstats=False, noalloc=False, bf16=False):
     """One E step and the M step it implies (lsgcpd_estep; with noalloc,
-    lsgcpd_estep_noalloc, which allocates no memory)."""
+    lsgcpd_estep_noalloc, which allocates no memory).  bf16: LSGCPD_BF16_CROSS
+    (the matrix-core exponent where its error bound allows)."""
     torch = _torch()
     X = _dev_tensor(X, (3,), "X")
     dev = X.device.index
@@ -259,7 +263,7 @@ def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=
             raise ValueError("w must have N entries")
     P = torch.empty((M, N), dtype=torch.float32, device=X.device) if dump_P else None
     cs = torch.empty((N, 16), dtype=torch.float64, device=X.device) if colstats else None
-    flags = (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend]
+    flags = (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend] | (BF16_CROSS if bf16 else 0)
     out = EstepOut()
     pose = _pose(R, t)
     ctx = context(dev)
@@ -275,7 +279,8 @@ def estep(X, Y, nrm, alpha, R, t, sigma2, w0=0.1, V=0.0, pi=None, w=None, exact=
                        stats=np.array(out.stats[:]), grad=np.array(out.grad[:]),
                        hess=np.array(out.hess[:]).reshape(6, 6), R_next=Rn, t_next=tn,
                        sigma2_next=out.sigma2_next, newton_iters=out.newton_iters,
-                       gn_fallbacks=out.gn_fallbacks, P=P, colstats=cs)
+                       gn_fallbacks=out.gn_fallbacks, P=P, colstats=cs,
+                       bf16_cross=bool(out.bf16_cross))
 
 
 @dataclass
@@ -291,6 +296,7 @@ class RegistrationResult:
     w0: float = 0.0     # uniform outlier weight used
     n_used: int = 0     # points registered (after truncation)
     m_used: int = 0
+    bf16_steps: int = 0  # E steps on the LSGCPD_BF16_CROSS path
 
 
 def default_params():
@@ -311,7 +317,7 @@ def _result(out, rep, nll):
     return RegistrationResult(R=R, t=t, sigma2=rep.sigma2, iters=rep.iters,
                               converged=bool(rep.converged), gn_fallbacks=rep.gn_fallbacks,
                               nll=nll, V=rep.V, w0=rep.w0, n_used=rep.n_used,
-                              m_used=rep.m_used)
+                              m_used=rep.m_used, bf16_steps=rep.bf16_steps)
 
 
 def _init_pose(R0, t0):
@@ -322,16 +328,16 @@ def _init_pose(R0, t0):
 
 def register(X, Y, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
              sigma2_init=0.0, newton_max=20, exact=False, backend="scalar", R0=None, t0=None,
-             eta=None, graph=False):
+             eta=None, graph=False, bf16=False):
     """Full LSG-CPD registration of X onto Y (lsgcpd_register).  eta: outlier
     ratio; w0 is then w_max (Sec. 3.2).  graph: replay the EM loop from a HIP
-    graph recording (LSGCPD_GRAPH)."""
+    graph recording (LSGCPD_GRAPH).  bf16: LSGCPD_BF16_CROSS."""
     X = _dev_tensor(X, (3,), "X")
     dev = X.device.index
     Y = _dev_tensor(Y, (3,), "Y", dev)
     p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
-                (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend] | (GRAPH if graph else 0),
-                eta)
+                (EXACT_NORMALIZER if exact else 0) | _BACKENDS[backend] | (GRAPH if graph else 0)
+                | (BF16_CROSS if bf16 else 0), eta)
     init = _init_pose(R0, t0)
     out = Pose()
     rep = Report()
@@ -413,7 +419,7 @@ def register_cf(X, Y, phi_x=None, phi_y=None, threshold=0.0, k=10, alpha_max=30.
 
 def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter=50, tol=0.0,
                    sigma2_init=0.0, newton_max=20, exact=False, dense=False, init=None,
-                   eta=None, graph=False):
+                   eta=None, graph=False, bf16=False):
     """Registers every (X, Y) of `pairs` in one batched pipeline
     (lsgcpd_register_batch); returns one RegistrationResult per pair (its
     `nll` holds the first and the last value of Eq. 4 only)."""
@@ -429,7 +435,7 @@ def register_batch(pairs, k=10, alpha_max=30.0, lam=0.2, w0=0.1, V=0.0, max_iter
         Ys.append(_dev_tensor(Y, (3,), "Y", dev))
     p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
                 (EXACT_NORMALIZER if exact else 0) | (DENSE if dense else 0) |
-                (GRAPH if graph else 0), eta)
+                (GRAPH if graph else 0) | (BF16_CROSS if bf16 else 0), eta)
     xp = (C.c_void_p * n)(*[_ptr(X) for X in Xs])
     yp = (C.c_void_p * n)(*[_ptr(Y) for Y in Ys])
     nn = (C.c_int64 * n)(*[X.shape[0] for X in Xs])

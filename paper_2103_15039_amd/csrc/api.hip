@@ -69,7 +69,7 @@ struct lsgcpd_ctx {
   int device = 0;
   void *scratch = nullptr;  // the device's static scratch array (lsgcpd_estep_noalloc)
   std::string err;
-  Buf knn, rec, pts, boxes, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
+  Buf knn, rec, pts, boxes, ftab, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
       trace, order, xperm, yperm, ys4, tables, states;
   // confidence filtering: kept points and confidences of X and Y, selection
   // workspace, sorted source confidences, source permutation, prior sums
@@ -169,7 +169,7 @@ lsgcpd_status ensure(lsgcpd_ctx *ctx, Buf &b, size_t bytes) {
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 constexpr uint32_t kKnownFlags = LSGCPD_EXACT_NORMALIZER | LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA |
-                                 LSGCPD_DENSE | LSGCPD_GRAPH;
+                                 LSGCPD_DENSE | LSGCPD_GRAPH | LSGCPD_BF16_CROSS;
 
 // About this many work items per E step for the scalar back end, by the
 // number of pairs of the E step (whole registrations measured on MI355X: 1024
@@ -249,6 +249,10 @@ lsgcpd_status check_params(lsgcpd_ctx *ctx, const lsgcpd_params *p) {
   if (p->flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", p->flags);
   if ((p->flags & LSGCPD_PAIRS_LDS) && (p->flags & LSGCPD_PAIRS_MFMA))
     return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
+  if ((p->flags & LSGCPD_BF16_CROSS) &&
+      (p->flags & (LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA | LSGCPD_DENSE)))
+    return fail(ctx, LSGCPD_E_INVALID,
+                "LSGCPD_BF16_CROSS runs on the culled default plan (no LDS, MFMA or DENSE flag)");
   return LSGCPD_OK;
 }
 
@@ -316,6 +320,7 @@ struct EstepMem {
   lsg::TRec *rec;
   lsg::TPt *pts;
   lsg::TBox *boxes;
+  void *ftab;  // BF16 feature tables (null unless the plan may use them)
   void *plan;
   double *partial;
   double *blockstats;
@@ -324,9 +329,15 @@ struct EstepMem {
 
 // The context's workspace (valid until the next ensure_* call).
 EstepMem ctx_mem(lsgcpd_ctx *ctx) {
-  return {ctx->dstate,     (lsg::TRec *)ctx->rec.p,       (lsg::TPt *)ctx->pts.p,
-          (lsg::TBox *)ctx->boxes.p, ctx->plan.p, (double *)ctx->partial.p,
-          (double *)ctx->blockstats.p, ctx->prof};
+  return {ctx->dstate,
+          (lsg::TRec *)ctx->rec.p,
+          (lsg::TPt *)ctx->pts.p,
+          (lsg::TBox *)ctx->boxes.p,
+          ctx->ftab.p,
+          ctx->plan.p,
+          (double *)ctx->partial.p,
+          (double *)ctx->blockstats.p,
+          ctx->prof};
 }
 
 // Streams and events of lanes 1 .. n - 1 (created once, default priority).
@@ -379,9 +390,11 @@ lsgcpd_status setup_problem(lsgcpd_ctx *ctx, const Lane &ln, const EstepMem &mem
   HIPCHK(lsg::launch_prep_targets(Y, normals, alpha, phi ? phi : pi,
                                   phi ? &(mem.state + p)->pi_sum : nullptr, yperm, sl.M,
                                   exact,
-                                  mem.rec + sl.y_off + p,
-                                  mem.pts + sl.y_off,
-                                  mem.boxes + sl.t_off, st));
+                                  mem.rec + sl.y_off + p, mem.pts + sl.y_off,
+                                  mem.boxes + sl.t_off,
+                                  pl.f3 ? (char *)mem.ftab + lsg::f3_table_bytes(sl.t_off)
+                                        : nullptr,
+                                  st));
   double *ymom = (double *)ln.mom->p;
   double *xmom = ymom + 16;
   HIPCHK(lsg::launch_moments(Y, sl.M, nullptr, (double *)ln.mom_part->p,
@@ -498,7 +511,8 @@ lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Ba
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_estep_plan(pl, bd, mem.boxes, mem.state, mem.plan, st));
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_pairs(pl, bd, mem.rec, mem.pts, mem.state, mem.plan, mem.partial, st));
+  HIPCHK(lsg::launch_estep_pairs(pl, bd, mem.rec, mem.pts, mem.ftab, mem.state, mem.plan,
+                                 mem.partial, st));
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_finalize(pl, bd, mem.state, mem.plan, mem.partial, mem.blockstats, colS,
                               colstats, st));
@@ -578,6 +592,7 @@ lsgcpd_status ensure_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl) {
   ENSURE(rec, (size_t)(pl.targets + pl.npairs) * sizeof(lsg::TRec));  // + a sentinel each
   ENSURE(pts, (size_t)pl.targets * sizeof(lsg::TPt));
   ENSURE(boxes, (size_t)pl.tiles * sizeof(lsg::TBox));
+  if (pl.f3) ENSURE(ftab, lsg::f3_table_bytes(pl.tiles));
   ENSURE(mom, 48 * sizeof(double));
   int64_t nmax = 1;
   for (const lsg::Slot &sl : pl.slots) {
@@ -663,6 +678,7 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   lsg::BatchPlan pl =
       lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1,
                       items_for(ctx, npairs, N, M));
+  pl.f3 = (p->flags & LSGCPD_BF16_CROSS) && pl.cull ? 1 : 0;
   const int lanes = npairs < kSetupLanes ? npairs : kSetupLanes;
   RETURN_IF(ensure_geometry(ctx, npairs, N, M, pl.targets, p->k, lanes));
   ENSURE(nrm, (size_t)pl.targets * 3 * sizeof(float));
@@ -765,6 +781,8 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
       r.w0 = s.w0;
       r.n_used = N[i];
       r.m_used = M[i];
+      r.bf16_steps = s.f3_steps;
+      r.pad = 0;
     }
     if (i == 0 && nll_trace && p->max_iter > 0)
       memcpy(nll_trace, tr, (size_t)filled * sizeof(double));
@@ -792,6 +810,10 @@ lsgcpd_status check_estep_args(lsgcpd_ctx *ctx, const float *X, int64_t N, const
   if (flags & ~kKnownFlags) return fail(ctx, LSGCPD_E_INVALID, "unknown flags 0x%x", flags);
   if ((flags & LSGCPD_PAIRS_LDS) && (flags & LSGCPD_PAIRS_MFMA))
     return fail(ctx, LSGCPD_E_INVALID, "LSGCPD_PAIRS_LDS and LSGCPD_PAIRS_MFMA exclude each other");
+  if ((flags & LSGCPD_BF16_CROSS) &&
+      (flags & (LSGCPD_PAIRS_LDS | LSGCPD_PAIRS_MFMA | LSGCPD_DENSE)))
+    return fail(ctx, LSGCPD_E_INVALID,
+                "LSGCPD_BF16_CROSS runs on the culled default plan (no LDS, MFMA or DENSE flag)");
   return check_pose(ctx, g);
 }
 
@@ -812,6 +834,8 @@ lsgcpd_status estep_results(lsgcpd_ctx *ctx, const DevState &s, lsgcpd_estep_out
   out->sigma2_next = s.sigma2_next;
   out->newton_iters = s.newton_iters;
   out->gn_fallbacks = s.gn_fallbacks;
+  out->bf16_cross = s.f3_steps;
+  out->pad = 0;
   if (s.numeric_error) return fail(ctx, LSGCPD_E_NUMERIC, "M step produced a non-finite result");
   return LSGCPD_OK;
 }
@@ -855,7 +879,7 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
 LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  Buf *bufs[] = {&c->knn,   &c->rec,   &c->pts,        &c->boxes, &c->plan,  &c->partial,
+  Buf *bufs[] = {&c->knn,   &c->rec,   &c->pts,        &c->boxes, &c->ftab, &c->plan,  &c->partial,
                  &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm,  &c->kap,
                  &c->alp,   &c->trace, &c->order,      &c->xperm, &c->yperm, &c->ys4,
                  &c->tables, &c->states, &c->cfx, &c->cfy, &c->cfwork, &c->xphi,
@@ -932,6 +956,7 @@ LSG_API lsgcpd_status lsgcpd_estep(lsgcpd_ctx *ctx, const float *X, int64_t N, c
   lsg::BatchPlan pl =
       lsg::batch_plan(1, &N, &M, backend_of(flags), (flags & LSGCPD_DENSE) ? 0 : 1,
                       items_for(ctx, 1, &N, &M));
+  pl.f3 = (flags & LSGCPD_BF16_CROSS) && pl.cull ? 1 : 0;
   pl.slots[0].X = X;
   pl.slots[0].w = w;
   RETURN_IF(ensure_states(ctx, 1));
@@ -977,6 +1002,7 @@ LSG_API lsgcpd_status lsgcpd_estep_noalloc(lsgcpd_ctx *ctx, const float *X, int6
   hipStream_t st = (hipStream_t)stream;
   lsg::BatchPlan pl = lsg::batch_plan(1, &N, &M, lsg::kBackendScalar,
                                       (flags & LSGCPD_DENSE) ? 0 : 1, kNoAllocItems);
+  pl.f3 = (flags & LSGCPD_BF16_CROSS) && pl.cull ? 1 : 0;
   pl.slots[0].X = X;
   pl.slots[0].w = w;
   // The scratch array, carved in call order (256-byte aligned regions).
@@ -994,6 +1020,7 @@ LSG_API lsgcpd_status lsgcpd_estep_noalloc(lsgcpd_ctx *ctx, const float *X, int6
   mem.rec = (lsg::TRec *)take((size_t)(M + 1) * sizeof(lsg::TRec));
   mem.pts = (lsg::TPt *)take((size_t)M * sizeof(lsg::TPt));
   mem.boxes = (lsg::TBox *)take((size_t)pl.tiles * sizeof(lsg::TBox));
+  mem.ftab = pl.f3 ? take(lsg::f3_table_bytes(pl.tiles)) : nullptr;
   mem.plan = take(lsg::estep_plan_bytes(pl));
   mem.partial = (double *)take(lsg::estep_partial_bytes(pl));
   mem.blockstats = (double *)take((size_t)pl.fins * lsg::kStats * sizeof(double));

@@ -190,6 +190,16 @@ static_assert(kSrcPerLane == 2, "per-half culling assumes two sources per lane")
 // Per source group: the boxes of its two halves of 64 sources (the sources
 // of slot 0 and slot 1 of the pair kernel's lanes), lo and hi each.
 constexpr int kGBox = 16;
+// BF16 matrix-core pair kernel (estep_pairs_f3, below): operand types, the
+// feature count of its accumulation, and its exponent error bound: |dz| <=
+// kF3Kappa (1 + alpha_m) (|u| + |v|)^2 (3 products of BF16 halves, each off
+// by 2^-16 of its size, plus FP32 sums of 32 terms), admitted while it is at
+// most kF3MaxDz for pairs within scaled distance 2 of a source half
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kF3Feat = 16;  // features 0 (the constant 1), 1..10, 11..15 zero
+constexpr double kF3Kappa = 3.0 / 65536.0 + 64.0 / 16777216.0;
+constexpr double kF3MaxDz = 1.0 / 32.0;
 
 // Scaled-coordinate bounding box of each source group (kept for the pair
 // kernel), then the live tiles in increasing order.  One block per group of
@@ -276,8 +286,10 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
 // off[g_off + p + g + 1] - 1 (local to the problem's item range).
 template <bool CULL>
 __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ slots,
-                                                     const DevState *__restrict__ states,
+                                                     DevState *__restrict__ states,
                                                      const int *__restrict__ counts,
+                                                     const double *__restrict__ gboxes,
+                                                     const TBox *__restrict__ boxes, int f3,
                                                      CullHdr *__restrict__ hdrs,
                                                      int *__restrict__ offs,
                                                      int *__restrict__ maps,
@@ -326,11 +338,45 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
     run += scan[kBlock - 1];
     __syncthreads();
   }
+  // the BF16 matrix-core kernel runs this E step if its exponent error bound
+  // holds for every source half: largest scaled half-diagonal h of the
+  // halves' boxes, largest alpha of the targets
+  int use_f3 = 0;
+  if (CULL && f3) {
+    double hm = 0.0, am = 0.0;
+    const double *gb = gboxes + (int64_t)sl.g_off * kGBox;
+    for (int g = threadIdx.x; g < 2 * ngroups; g += kBlock) {
+      const double *hb = gb + (int64_t)(g >> 1) * kGBox + 6 * (g & 1);
+      if (hb[0] <= hb[3]) {  // a half without sources has an empty box
+        const double e0 = hb[3] - hb[0], e1 = hb[4] - hb[1], e2 = hb[5] - hb[2];
+        hm = fmax(hm, 0.5 * sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+      }
+    }
+    const TBox *tb = boxes + sl.t_off;
+    for (int t = threadIdx.x; t < ntiles; t += kBlock) am = fmax(am, tb[t].pad);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      hm = fmax(hm, __shfl_xor(hm, o, 64));
+      am = fmax(am, __shfl_xor(am, o, 64));
+    }
+    __shared__ double mx[2][4];
+    if (lane == 0) {
+      mx[0][wave] = hm;
+      mx[1][wave] = am;
+    }
+    __syncthreads();
+    hm = fmax(fmax(mx[0][0], mx[0][1]), fmax(mx[0][2], mx[0][3]));
+    am = fmax(fmax(mx[1][0], mx[1][1]), fmax(mx[1][2], mx[1][3]));
+    const double r = 2.0 * hm + 2.0;
+    use_f3 = kF3Kappa * (1.0 + am) * r * r <= kF3MaxDz ? 1 : 0;
+  }
   if (threadIdx.x == 0) {
     off[ngroups] = run;
     hdrs[p].items = run < cap ? run : cap;
     hdrs[p].tiles_per_item = (int)L;
+    hdrs[p].f3 = use_f3;
     evcounts[p] = 0ull;
+    if (use_f3) states[p].f3_steps += 1;
   }
 }
 
@@ -347,6 +393,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   const int p = item_slot[blockIdx.x];
   const DevState *st = states + p;
   if (st->done) return;
+  if (CULL && hdrs[p].f3) return;  // the BF16 matrix-core kernel runs this E step
   const Slot &sl = slots[p];
   const int nitems = hdrs[p].items;
   int item = blockIdx.x - sl.item_off;
@@ -481,6 +528,296 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
              : nv * (unsigned long long)(wdone[0][0] + wdone[0][1] + wdone[0][2] + wdone[0][3]);
     atomicAdd(evcounts + p, ev);
   }
+}
+
+// ------------------------------------------- pair kernel (BF16 matrix cores)
+// The exponent as a bilinear form of lifted features (Sec. 3.4, Eq. 10: the
+// paper's own recast of the Mahalanobis term is this product).  With every
+// coordinate scaled by sqrt(c) and taken relative to a centre o,
+// u = s_n - o, v = sqrt(c) y_m - o and M_m = I + a_m a_m^T,
+//   c d_mn = (u - v)^T M_m (u - v) = Phi_m . Psi_n,
+//   Psi_n = [u0^2, u1^2, u2^2, 2u0u1, 2u0u2, 2u1u2, u0, u1, u2, 1],
+//   Phi_m = [M00, M11, M22, M01, M02, M12, -2 M v, v^T M v],
+// a K = 10 contraction.  Each value is split into BF16 high and low parts
+// (v = hi + lo + O(2^-16 v)) and the K = 32 product
+//   [Phi_hi, Phi_hi, Phi_lo, 0, 0] . [Psi_hi, Psi_lo, Psi_hi, 0, 0]
+// runs as one V_MFMA_F32_16X16X32_BF16 per 16 targets x 16 sources, FP32
+// accumulation; the exponential is float32 on the vector unit; the
+// accumulation T_n += e_mn [1, f_m] is a second contraction over the targets,
+//   [e_hi, e_hi, e_lo] x [F_hi, F_lo, F_hi]  (3 MFMAs per 32 targets),
+// whose FP32 sums are moved into FP64 every second tile.
+// Error: each product carries about 3 * 2^-16 of its own size, and the
+// terms cancel for nearby pairs, so |dz| <= kF3Kappa (1 + alpha_m)
+// (|u| + |v|)^2 up to the FP32 sums; the centre is the box centre of the
+// wave's 64 sources (|u| <= h, its scaled half-diagonal).  cull_items runs
+// this kernel for an E step only if kF3Kappa (1 + alpha_max) (2 h + 2)^2 <=
+// kF3MaxDz for every source half, i.e. the bound holds for every pair within
+// scaled distance 2 (e at least 2^-4 of its largest possible value) -- the
+// early, large-sigma^2 iterations.  Same items, partial layout and
+// finalisation as the FP64 kernel; not a parity path (errors ~1e-4 in z).
+
+__device__ __forceinline__ void split_bf16(double v, __bf16 &hi, __bf16 &lo) {
+  const float f = (float)v;
+  hi = (__bf16)f;
+  lo = (__bf16)(f - (float)hi);
+}
+
+// Accumulation features of tile t (targets t*64 ..), BF16 high/low parts in
+// the order the MFMA B operand reads them: [t][hi, lo][feature][target];
+// and the tile's largest alpha (= |a_m|^2) in box[t].pad.  One wave per tile.
+__global__ void f3_tables(const TRec *__restrict__ rec, int64_t M, __bf16 *__restrict__ ftab,
+                          TBox *__restrict__ box) {
+  const int64_t t = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t ntiles = (M + kCullTile - 1) / kCullTile;
+  if (t >= ntiles) return;  // wave-uniform
+  const int64_t m = t * kCullTile + lane;
+  const bool valid = m < M;
+  double f[kF3Feat];
+  double a2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < kF3Feat; ++c) f[c] = 0.0;
+  if (valid) {
+    const TRec &r = rec[m];
+    f[0] = 1.0;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) f[1 + c] = r.f[c];
+    a2 = r.a[0] * r.a[0] + r.a[1] * r.a[1] + r.a[2] * r.a[2];
+  }
+  __bf16 *o = ftab + t * (2 * kF3Feat * kCullTile);
+#pragma unroll
+  for (int c = 0; c < kF3Feat; ++c) {
+    __bf16 hi, lo;
+    split_bf16(f[c], hi, lo);
+    o[c * kCullTile + lane] = hi;
+    o[(kF3Feat + c) * kCullTile + lane] = lo;
+  }
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) a2 = fmax(a2, __shfl_xor(a2, s, 64));
+  if (lane == 0) box[t].pad = a2;
+}
+
+// Picks entries 8 q .. 8 q + 7 of a 32-vector held in registers (q = lane / 16).
+__device__ __forceinline__ bf16x8 pick8(const __bf16 (&v)[32], int q) {
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    o[j] = q == 0 ? v[j] : q == 1 ? v[8 + j] : q == 2 ? v[16 + j] : v[24 + j];
+  return o;
+}
+
+// The K = 32 operand of a lifted 10-vector w: [hi, hi, lo] (targets, `first`)
+// or [hi, lo, hi] (sources), zero-padded.
+__device__ __forceinline__ void lifted32(const double (&w)[10], bool target, __bf16 (&v)[32]) {
+  __bf16 hi[10], lo[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) split_bf16(w[k], hi[k], lo[k]);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    v[k] = hi[k];
+    v[10 + k] = target ? hi[k] : lo[k];
+    v[20 + k] = target ? lo[k] : hi[k];
+  }
+  v[30] = v[31] = (__bf16)0.0f;
+}
+
+// One block of 4 waves per work item (the FP64 kernel's items).  Wave w takes
+// the 64 sources of half w & 1 of the group (4 blocks of 16, lanes l & 15) and
+// every second tile of the item (starting at w >> 1); the two waves of a half
+// add their sums through LDS in a fixed order.
+__global__ __launch_bounds__(kBlock, 2) void estep_pairs_f3(
+    const Slot *__restrict__ slots, const int *__restrict__ item_slot,
+    const DevState *__restrict__ states, const TRec *__restrict__ recs,
+    const __bf16 *__restrict__ ftabs, const CullHdr *__restrict__ hdrs,
+    const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
+    const int *__restrict__ list, const double *__restrict__ gboxes,
+    unsigned long long *__restrict__ evcounts, double *__restrict__ partial, int xcd_remap) {
+  const int p = item_slot[blockIdx.x];
+  const DevState *st = states + p;
+  if (st->done || !hdrs[p].f3) return;
+  const Slot &sl = slots[p];
+  const int nitems = hdrs[p].items;
+  int item = blockIdx.x - sl.item_off;
+  if (item >= nitems) return;
+  if (xcd_remap) {
+    const int x = item % 8, q = nitems / 8, r = nitems % 8;
+    item = x * q + (x < r ? x : r) + item / 8;
+  }
+  const int b = sl.item_off + item;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int half = wave & 1, par = wave >> 1;
+  const int lq = lane >> 4, lc = lane & 15;
+  const int N = sl.N, ntiles = sl.ntiles, Mi = sl.M;
+  const TRec *rec = recs + sl.y_off + p;
+  const __bf16 *ftab = ftabs + (int64_t)sl.t_off * (2 * kF3Feat * kCullTile);
+  const int g = maps[b];
+  const int L = hdrs[p].tiles_per_item;
+  const int k0 = (item - offs[sl.g_off + p + g]) * L;
+  const int cnt = counts[sl.g_off + g];
+  const int kn = cnt - k0 < L ? cnt - k0 : L;
+  const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
+  const double *hb = gboxes + (int64_t)(sl.g_off + g) * kGBox + 6 * half;
+  const int rest = N - g * kGroup - half * 64;
+  const int nv = rest < 0 ? 0 : rest < 64 ? rest : 64;  // sources of this half
+  double R[9], t[3];
+  for (int i = 0; i < 9; ++i) R[i] = st->R[i];
+  for (int i = 0; i < 3; ++i) t[i] = st->t[i];
+  const double sc = sqrt_c_of(st);
+  double o[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o[a] = nv > 0 ? 0.5 * (hb[a] + hb[3 + a]) : 0.0;
+  // B operands of the exponent: Psi of the lane's 4 sources
+  bf16x8 psi[4];
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb) {
+    const int j = 16 * sb + lc;
+    const int n = g * kGroup + half * 64 + j;
+    double w[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) w[k] = 0.0;
+    if (j < nv) {
+      const Src x = load_src(sl.X, n, N, R, t, sc);
+      const double u0 = x.x0 - o[0], u1 = x.x1 - o[1], u2 = x.x2 - o[2];
+      w[0] = u0 * u0;
+      w[1] = u1 * u1;
+      w[2] = u2 * u2;
+      w[3] = 2.0 * u0 * u1;
+      w[4] = 2.0 * u0 * u2;
+      w[5] = 2.0 * u1 * u2;
+      w[6] = u0;
+      w[7] = u1;
+      w[8] = u2;
+      w[9] = 1.0;
+    }
+    __bf16 v[32];
+    lifted32(w, false, v);
+    psi[sb] = pick8(v, lq);
+  }
+  __shared__ bf16x8 phis[4][kCullTile][4];  // per wave: each target's 32-vector
+  __shared__ float ls[4][kCullTile];
+  f32x4 acc[4];
+  double tot[4][4];
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[sb][i] = 0.0f;
+      tot[sb][i] = 0.0;
+    }
+  int done = 0;  // targets evaluated (against each of the nv sources)
+  int since = 0;
+  for (int q = par; nv > 0 && q < kn; q += 2) {
+    const int ti = tl[q];
+    const int base = ti * kCullTile;
+    const int n1 = Mi - base < kCullTile ? Mi - base : kCullTile;
+    done += n1;
+    {  // A operands of the exponent: Phi of the tile's targets (lane = target)
+      double w[10];
+      float l = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) w[k] = 0.0;
+      if (lane < n1) {
+        const TRec &r = rec[base + lane];
+        const double v0 = fma(sc, r.y[0], -o[0]), v1 = fma(sc, r.y[1], -o[1]),
+                     v2 = fma(sc, r.y[2], -o[2]);
+        const double av = r.a[0] * v0 + r.a[1] * v1 + r.a[2] * v2;
+        const double m0 = fma(r.a[0], av, v0), m1 = fma(r.a[1], av, v1), m2 = fma(r.a[2], av, v2);
+        w[0] = fma(r.a[0], r.a[0], 1.0);
+        w[1] = fma(r.a[1], r.a[1], 1.0);
+        w[2] = fma(r.a[2], r.a[2], 1.0);
+        w[3] = r.a[0] * r.a[1];
+        w[4] = r.a[0] * r.a[2];
+        w[5] = r.a[1] * r.a[2];
+        w[6] = -2.0 * m0;
+        w[7] = -2.0 * m1;
+        w[8] = -2.0 * m2;
+        w[9] = v0 * m0 + v1 * m1 + v2 * m2;
+        l = (float)r.l;
+      }
+      __bf16 v[32];
+      lifted32(w, true, v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) phis[wave][lane][k] = pick8(v, k);
+      ls[wave][lane] = l;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const __bf16 *ft = ftab + (int64_t)ti * (2 * kF3Feat * kCullTile);
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      // B operands of the accumulation: features lc of targets
+      // 32 kc + 4 lq + (0..3) and 32 kc + 16 + 4 lq + (0..3), high and low
+      bf16x8 fh, fl;
+      {
+        const __bf16 *ph = ft + lc * kCullTile + 32 * kc + 4 * lq;
+        const __bf16 *pl = ph + kF3Feat * kCullTile;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          fh[j] = ph[j];
+          fh[4 + j] = ph[16 + j];
+          fl[j] = pl[j];
+          fl[4 + j] = pl[16 + j];
+        }
+      }
+      const bf16x8 a0 = phis[wave][32 * kc + lc][lq];
+      const bf16x8 a1 = phis[wave][32 * kc + 16 + lc][lq];
+      float lr[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        lr[i] = ls[wave][32 * kc + 4 * lq + i];
+        lr[4 + i] = ls[wave][32 * kc + 16 + 4 * lq + i];
+      }
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+        const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, psi[sb], zero, 0, 0, 0);
+        const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, psi[sb], zero, 0, 0, 0);
+        bf16x8 eh, el;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float e = __builtin_amdgcn_exp2f(lr[i] - (i < 4 ? d0[i] : d1[i - 4]));
+          const __bf16 h = (__bf16)e;
+          eh[i] = h;
+          el[i] = (__bf16)(e - (float)h);
+        }
+        acc[sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(eh, fh, acc[sb], 0, 0, 0);
+        acc[sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(eh, fl, acc[sb], 0, 0, 0);
+        acc[sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(el, fh, acc[sb], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (++since == 2) {  // FP32 sums of at most 128 targets, then FP64
+      since = 0;
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          tot[sb][i] += (double)acc[sb][i];
+          acc[sb][i] = 0.0f;
+        }
+    }
+  }
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[sb][i] += (double)acc[sb][i];
+  // lane (lq, lc) holds T[source 16 sb + 4 lq + i of the half][feature lc]
+  __shared__ double red[2][4][4][64];
+  if (par == 1)
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[half][sb][i][lane] = tot[sb][i];
+  __syncthreads();
+  if (par == 0 && lc < kFeatUsed) {
+    double *dst = partial + (size_t)b * kFeatUsed * kGroup + (size_t)lc * kGroup + half * 64;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[16 * sb + 4 * lq + i] = tot[sb][i] + red[half][sb][i][lane];
+  }
+  if (lane == 0 && nv > 0 && done > 0)
+    atomicAdd(evcounts + p, (unsigned long long)nv * (unsigned long long)done);
 }
 
 // LDS back end: the block stages tiles of target records in LDS and every
@@ -1090,24 +1427,29 @@ hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox
     hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.groups), dim3(kBlock), 0, st, bd.slots,
                        bd.grp_slot, s, boxes, q.counts, q.gbox, q.list);
     hipLaunchKernelGGL(cull_items<true>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st, bd.slots,
-                       s, q.counts, q.hdr, q.off, q.map, q.evcount);
+                       s, q.counts, q.gbox, boxes, pl.f3, q.hdr, q.off, q.map, q.evcount);
   } else {
     hipLaunchKernelGGL(cull_items<false>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st,
-                       bd.slots, s, q.counts, q.hdr, q.off, q.map, q.evcount);
+                       bd.slots, s, q.counts, q.gbox, boxes, 0, q.hdr, q.off, q.map, q.evcount);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRec *rec,
-                              const TPt *pts, DevState *s, void *plan_ws, double *partial,
-                              hipStream_t st) {
+                              const TPt *pts, const void *ftab, DevState *s, void *plan_ws,
+                              double *partial, hipStream_t st) {
   if (pl.backend == kBackendScalar) {
     const PlanPtrs q = plan_ptrs(pl, plan_ws);
-    if (pl.cull)
+    if (pl.cull) {
       hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                          bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
                          q.list, q.gbox, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
-    else
+      if (pl.f3)
+        hipLaunchKernelGGL(estep_pairs_f3, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
+                           bd.slots, bd.item_slot, s, rec, (const __bf16 *)ftab, q.hdr, q.counts,
+                           q.off, q.map, q.list, q.gbox, q.evcount, partial,
+                           pl.npairs == 1 ? 1 : 0);
+    } else
       hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                          bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
                          q.list, q.gbox, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
@@ -1153,13 +1495,20 @@ hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, 
 hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
                                const float *pi, const double *pi_sum, const uint32_t *perm,
                                int64_t M, int exact, TRec *rec, TPt *pts, TBox *boxes,
-                               hipStream_t st) {
+                               void *ftab, hipStream_t st) {
   hipLaunchKernelGGL(prep_targets, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, Y,
                      normals, alpha, pi, pi_sum, perm, M, exact, rec, pts);
   const int64_t ntiles = (M + kCullTile - 1) / kCullTile;
   hipLaunchKernelGGL(tile_boxes, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, pts, M,
                      boxes);
+  if (ftab)
+    hipLaunchKernelGGL(f3_tables, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, rec, M,
+                       (__bf16 *)ftab, boxes);
   return hipGetLastError();
+}
+
+size_t f3_table_bytes(int64_t tiles) {
+  return (size_t)tiles * 2 * kF3Feat * kCullTile * sizeof(__bf16);
 }
 
 int moments_blocks(int64_t n) {

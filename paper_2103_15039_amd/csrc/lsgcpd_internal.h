@@ -79,6 +79,8 @@ struct DevState {
   int32_t numeric_error;
   int32_t newton_max;
   int32_t max_iter;
+  int32_t f3_steps;   // E steps that ran the BF16 matrix-core pair kernel
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -117,10 +119,14 @@ hipError_t launch_curve_order(const float *P, int64_t n, const double *box, void
 // whose exponent is -inf (rec holds M + 1 records); boxes gets one TBox per
 // tile of kCullTile records.  Priors: pi null => 1/M; else pi[m], divided by
 // *pi_sum when pi_sum (device) is not null.
+// ftab (may be null): the accumulation features of every tile split into
+// BF16 high and low parts for the matrix-core pair kernel (f3_table_bytes),
+// and the largest alpha of each tile in its box's `pad`.
 hipError_t launch_prep_targets(const float *Y, const float *normals, const float *alpha,
                                const float *pi, const double *pi_sum, const uint32_t *perm,
                                int64_t M, int exact, TRec *rec, TPt *pts, TBox *boxes,
-                               hipStream_t st);
+                               void *ftab, hipStream_t st);
+size_t f3_table_bytes(int64_t tiles);
 
 // Confidence filtering (confidence.hip).  phi of depth-sensor points from the
 // error model coef[0] + coef[1] z + coef[2] z^2; truncation to phi >= threshold
@@ -168,6 +174,7 @@ struct Slot {
 struct BatchPlan {
   int backend = 0;
   int cull = 0;        // drop target tiles whose exponentials are all exact zeros
+  int f3 = 0;          // E steps may run the BF16 matrix-core pair kernel (needs cull)
   int npairs = 0;
   int64_t groups = 0, tiles = 0, items = 0, fins = 0, list_ints = 0;
   int64_t sources = 0, targets = 0;
@@ -189,6 +196,8 @@ struct BatchDev {
 struct CullHdr {
   int items;           // work items of the problem
   int tiles_per_item;
+  int f3;              // 1: this E step runs the BF16 matrix-core pair kernel
+  int pad;
 };
 
 // Plans a batch of sizes N[p], M[p]: work items about target_items in all,
@@ -210,11 +219,15 @@ unsigned long long *estep_plan_counter(const BatchPlan &pl, void *plan_ws);
 // The work-item plan of the scalar back end (no-op for the others), then the
 // pair kernel, then the per-source finalisation into stat-major block rows
 // (problem p: rows at kStats * fin_off, nfin per row).
+// With pl.f3 the plan decides per E step and problem whether the BF16
+// matrix-core pair kernel runs (its exponent error bound holds at the
+// current sigma^2 and source groups) or the FP64 one; both are launched and
+// the one not chosen returns at once.  ftab: the tables of launch_prep_targets.
 hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox *boxes,
                              DevState *s, void *plan_ws, hipStream_t st);
 hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRec *rec,
-                              const TPt *pts, DevState *s, void *plan_ws, double *partial,
-                              hipStream_t st);
+                              const TPt *pts, const void *ftab, DevState *s, void *plan_ws,
+                              double *partial, hipStream_t st);
 hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
                            const void *plan_ws, const double *partial, double *blockstats,
                            double *colS, double *colstats, hipStream_t st);
