@@ -26,7 +26,8 @@ Input normalisation (one cloud pair, optional rotation Q of the source):
     k = 0 .. P-1 (evenly spaced in the cloud's order; repeats when N < P);
   * x' = Q x; mu_X = mean of the sampled x', mu_Y = mean of the sampled y;
     s = root-mean-square distance of the sampled y from mu_Y;
-  * inputs (x' - mu_X) / s and (y - mu_Y) / s.
+  * inputs (x' - mu_X) / s and (y - mu_Y) / s (s = 1 when the target's
+    samples are all one point, e.g. P = 1).
 A pose (R, t) mapping x' onto y reads, in normalised units, R and
 t^ = (R mu_X + t - mu_Y) / s; a prediction (R^, t^) maps back to
 t = mu_Y + s t^ - R^ mu_X.
@@ -84,6 +85,8 @@ def normalise(X, Y, P, Q=None):
         xs = xs @ np.asarray(Q, np.float64).T
     mx, my = xs.mean(axis=0), ys.mean(axis=0)
     s = np.sqrt(np.mean(np.sum((ys - my) ** 2, axis=1)))
+    if not s > 0.0:
+        s = 1.0  # the target's samples are one point: no scale to take
     return (xs - mx) / s, (ys - my) / s, (mx, my, s)
 
 

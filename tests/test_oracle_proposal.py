@@ -164,6 +164,9 @@ def test_sampling_and_normalisation_round_trip():
     assert list(PR.sample_indices(10, 5)) == [1, 3, 5, 7, 9]
     assert list(PR.sample_indices(3, 6)) == [0, 0, 1, 1, 2, 2]
     assert list(PR.sample_indices(7, 7)) == list(range(7))
+    # one sample: no spread, unit scale, both inputs at the origin
+    xs1, ys1, (_, _, s1) = PR.normalise(np.ones((5, 3)), np.arange(12.0).reshape(4, 3), 1)
+    assert s1 == 1.0 and not xs1.any() and not ys1.any()
     rng = np.random.default_rng(8)
     p = datagen.range_scanner_pair(trial=2, M=900, N=700)
     Q = datagen.random_rotation(rng, 2.0)
