@@ -31,8 +31,9 @@ SYMBOLS = ("lsgcpd_abi_version", "lsgcpd_status_string", "lsgcpd_ctx_create",
            "lsgcpd_normals", "lsgcpd_estep", "lsgcpd_register", "lsgcpd_register_batch",
            "lsgcpd_depth_confidence", "lsgcpd_register_cf", "lsgcpd_autotune",
            "lsgcpd_profile_enable", "lsgcpd_profile_read", "lsgcpd_profile_launches",
-           "lsgcpd_estep_noalloc")
-ABI_VERSION = 5
+           "lsgcpd_estep_noalloc", "lsgcpd_proposal_inputs", "lsgcpd_proposal_forward",
+           "lsgcpd_proposal_train_step", "lsgcpd_register_proposed")
+ABI_VERSION = 6
 
 
 class Pose(C.Structure):
@@ -133,6 +134,16 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_profile_launches.restype = C.c_int
     lib.lsgcpd_profile_launches.argtypes = [vp, C.POINTER(d), C.POINTER(d), i64,
                                             C.POINTER(i64)]
+    lib.lsgcpd_proposal_inputs.restype = C.c_int
+    lib.lsgcpd_proposal_inputs.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.lsgcpd_proposal_forward.restype = C.c_int
+    lib.lsgcpd_proposal_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.lsgcpd_proposal_train_step.restype = C.c_int
+    lib.lsgcpd_proposal_train_step.argtypes = [vp, vp, vp, vp, i32, d, i32, i32, vp, vp, vp, i32,
+                                               vp, vp, vp, vp, vp, vp, vp]
+    lib.lsgcpd_register_proposed.restype = C.c_int
+    lib.lsgcpd_register_proposed.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Params), vp, i32,
+                                             d, C.POINTER(Pose), C.POINTER(Report), vp, vp]
     _lib = lib
     return lib
 
@@ -485,3 +496,136 @@ def profile_launches(device=0):
     b = (C.c_double * max(n.value, 1))()
     _check(lib.lsgcpd_profile_launches(ctx, a, b, n.value, C.byref(n)), ctx)
     return np.array(a[:n.value]), np.array(b[:n.value])
+
+
+PROPOSAL_PARAMS = 108425
+
+
+def proposal_inputs(pairs, P, Q=None):
+    """Encoder inputs of the (X, Y) pairs (lsgcpd_proposal_inputs): Xn, Yn
+    (npairs, P, 3) float32 and norm (npairs, 7) float64 device tensors.  Q:
+    optional (npairs, 3, 3) rotations of the sources."""
+    torch = _torch()
+    n = len(pairs)
+    if n < 1:
+        raise ValueError("no pairs")
+    Xs, Ys, dev = [], [], None
+    for X, Y in pairs:
+        X = _dev_tensor(X, (3,), "X", dev)
+        dev = X.device.index
+        Xs.append(X)
+        Ys.append(_dev_tensor(Y, (3,), "Y", dev))
+    device = Xs[0].device
+    Xn = torch.empty((n, P, 3), dtype=torch.float32, device=device)
+    Yn = torch.empty((n, P, 3), dtype=torch.float32, device=device)
+    norm = torch.empty((n, 7), dtype=torch.float64, device=device)
+    Qh = None
+    if Q is not None:
+        Qh = np.ascontiguousarray(Q, dtype=np.float64).reshape(n, 9)
+    xp = (C.c_void_p * n)(*[_ptr(X) for X in Xs])
+    yp = (C.c_void_p * n)(*[_ptr(Y) for Y in Ys])
+    nn = (C.c_int64 * n)(*[X.shape[0] for X in Xs])
+    mm = (C.c_int64 * n)(*[Y.shape[0] for Y in Ys])
+    ctx = context(dev)
+    st = load_library().lsgcpd_proposal_inputs(ctx, n, C.cast(xp, C.c_void_p), C.cast(nn, C.c_void_p),
+                                               C.cast(yp, C.c_void_p), C.cast(mm, C.c_void_p),
+                                               _host(Qh), int(P), _ptr(Xn), _ptr(Yn), _ptr(norm),
+                                               _stream(dev))
+    _check(st, ctx)
+    return Xn, Yn, norm
+
+
+def _f32(a, n, name, dev):
+    a = _dev_tensor(a, None, name, dev)
+    if a.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return a
+
+
+def proposal_forward(theta, Xn, Yn, norm):
+    """Predicted poses (lsgcpd_proposal_forward): a (npairs, 12) float64
+    device tensor, R row-major then t, world units."""
+    torch = _torch()
+    if Xn.dim() != 3 or Xn.shape[2] != 3 or Yn.shape != Xn.shape:
+        raise ValueError("Xn and Yn must have shape (npairs, P, 3)")
+    n, P = Xn.shape[0], Xn.shape[1]
+    dev = Xn.device.index
+    theta = _f32(theta, PROPOSAL_PARAMS, "theta", dev)
+    pose = torch.empty((n, 12), dtype=torch.float64, device=Xn.device)
+    ctx = context(dev)
+    st = load_library().lsgcpd_proposal_forward(ctx, _ptr(theta), n, P, _ptr(Xn), _ptr(Yn),
+                                                _ptr(norm), _ptr(pose), _stream(dev))
+    _check(st, ctx)
+    return pose
+
+
+def _host(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else C.c_void_p(0)
+
+
+def proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, label, index=None, Q=None,
+                        want_argmax=False, want_grad=False):
+    """One Adam step of the proposal on a batch (lsgcpd_proposal_train_step);
+    theta, m, v (float32 device tensors of PROPOSAL_PARAMS) are updated in
+    place.  Xn, Yn, norm: stored inputs (proposal_inputs); label (B, 12),
+    index (B,) and Q (B, 3, 3): host arrays.  Returns the device tensors
+    (loss per pair, argmax or None, gradient or None)."""
+    torch = _torch()
+    dev = Xn.device.index
+    label = np.ascontiguousarray(label, np.float64).reshape(-1, 12)
+    B = label.shape[0]
+    P = Xn.shape[1]
+    for name, a in (("theta", theta), ("m", m), ("v", v)):
+        if a.dtype != torch.float32 or a.numel() != PROPOSAL_PARAMS or not a.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {PROPOSAL_PARAMS}")
+    idx = None if index is None else np.ascontiguousarray(index, np.int32).reshape(B)
+    Qh = None if Q is None else np.ascontiguousarray(Q, np.float64).reshape(B, 9)
+    loss = torch.empty(B, dtype=torch.float64, device=Xn.device)
+    am = torch.empty((B, 2, 256), dtype=torch.int32, device=Xn.device) if want_argmax else None
+    g = torch.empty(PROPOSAL_PARAMS, dtype=torch.float32, device=Xn.device) if want_grad else None
+    ctx = context(dev)
+    st = load_library().lsgcpd_proposal_train_step(
+        ctx, _ptr(theta), _ptr(m), _ptr(v), int(step), float(lr), B, P, _ptr(Xn), _ptr(Yn),
+        _ptr(norm), int(Xn.shape[0]), _host(idx), _host(Qh), _host(label), _ptr(loss), _ptr(am),
+        _ptr(g), _stream(dev))
+    _check(st, ctx)
+    return loss, am, g
+
+
+def register_proposed(pairs, theta, P=512, accept=0.05, k=10, alpha_max=30.0, lam=0.2, w0=0.1,
+                      V=0.0, max_iter=50, tol=0.0, sigma2_init=0.0, newton_max=20, exact=False,
+                      eta=None):
+    """Registers every (X, Y) of `pairs` from the learned proposal's pose,
+    with 24-start EM for the pairs it does not accept
+    (lsgcpd_register_proposed).  Returns (results, fallback flags)."""
+    n = len(pairs)
+    if n < 1:
+        raise ValueError("no pairs")
+    Xs, Ys, dev = [], [], None
+    for X, Y in pairs:
+        X = _dev_tensor(X, (3,), "X", dev)
+        dev = X.device.index
+        Xs.append(X)
+        Ys.append(_dev_tensor(Y, (3,), "Y", dev))
+    theta = _dev_tensor(theta, None, "theta", dev)
+    if theta.numel() != PROPOSAL_PARAMS:
+        raise ValueError(f"theta must have {PROPOSAL_PARAMS} entries")
+    p = _params(k, alpha_max, lam, w0, V, max_iter, tol, sigma2_init, newton_max,
+                EXACT_NORMALIZER if exact else 0, eta)
+    xp = (C.c_void_p * n)(*[_ptr(X) for X in Xs])
+    yp = (C.c_void_p * n)(*[_ptr(Y) for Y in Ys])
+    nn = (C.c_int64 * n)(*[X.shape[0] for X in Xs])
+    mm = (C.c_int64 * n)(*[Y.shape[0] for Y in Ys])
+    out = (Pose * n)()
+    rep = (Report * n)()
+    fb = (C.c_int32 * n)()
+    ctx = context(dev)
+    st = load_library().lsgcpd_register_proposed(ctx, n, C.cast(xp, C.c_void_p),
+                                                 C.cast(nn, C.c_void_p), C.cast(yp, C.c_void_p),
+                                                 C.cast(mm, C.c_void_p), C.byref(p), _ptr(theta),
+                                                 int(P), float(accept), out, rep,
+                                                 C.cast(fb, C.c_void_p), _stream(dev))
+    _check(st, ctx)
+    res = [_result(out[i], rep[i], np.array([rep[i].nll_first, rep[i].nll_last]))
+           for i in range(n)]
+    return res, np.array(fb[:], dtype=np.int32)

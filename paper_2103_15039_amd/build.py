@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblsgcpd.so")
-SOURCES = ["api.hip", "estep.hip", "mstep.hip", "knn_pca.hip", "order.hip", "confidence.hip"]
+SOURCES = ["api.hip", "estep.hip", "mstep.hip", "knn_pca.hip", "order.hip", "confidence.hip",
+           "proposal.hip"]
 ARCH = os.environ.get("LSGCPD_ARCH", "gfx950")
 
 

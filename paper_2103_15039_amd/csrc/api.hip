@@ -69,7 +69,7 @@ struct lsgcpd_ctx {
   int device = 0;
   void *scratch = nullptr;  // the device's static scratch array (lsgcpd_estep_noalloc)
   std::string err;
-  Buf knn, rec, pts, boxes, ftab, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
+  Buf knn, rec, pts, boxes, ftab, ptab, pws, pbatch, pin, plan, partial, blockstats, colS, mom_part, mom, nrm, kap, alp,
       trace, order, xperm, yperm, ys4, tables, states;
   // confidence filtering: kept points and confidences of X and Y, selection
   // workspace, sorted source confidences, source permutation, prior sums
@@ -879,7 +879,8 @@ LSG_API lsgcpd_status lsgcpd_ctx_create(int device, lsgcpd_ctx **out) {
 LSG_API void lsgcpd_ctx_destroy(lsgcpd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  Buf *bufs[] = {&c->knn,   &c->rec,   &c->pts,        &c->boxes, &c->ftab, &c->plan,  &c->partial,
+  Buf *bufs[] = {&c->knn,   &c->rec,   &c->pts,        &c->boxes, &c->ftab, &c->ptab, &c->pws,
+                 &c->pbatch, &c->pin, &c->plan,  &c->partial,
                  &c->blockstats, &c->colS, &c->mom_part, &c->mom, &c->nrm,  &c->kap,
                  &c->alp,   &c->trace, &c->order,      &c->xperm, &c->yperm, &c->ys4,
                  &c->tables, &c->states, &c->cfx, &c->cfy, &c->cfwork, &c->xphi,
@@ -1268,5 +1269,231 @@ LSG_API lsgcpd_status lsgcpd_profile_launches(lsgcpd_ctx *ctx, double *pair_us, 
     estep_us[i] = ctx->launch_estep_us[i];
   }
   if (count) *count = n;
+  return LSGCPD_OK;
+}
+
+// ---------------------------------------------------- pose proposal (f2)
+
+namespace {
+
+lsgcpd_status check_prop(lsgcpd_ctx *ctx, int npairs, int P) {
+  if (npairs < 1 || npairs > kMaxBatch)
+    return fail(ctx, LSGCPD_E_INVALID, "npairs = %d out of range", npairs);
+  if (P < 1 || P > lsg::kPropMaxPoints)
+    return fail(ctx, LSGCPD_E_INVALID, "P = %d must lie in [1, %d]", P, lsg::kPropMaxPoints);
+  return LSGCPD_OK;
+}
+
+}  // namespace
+
+LSG_API lsgcpd_status lsgcpd_proposal_inputs(lsgcpd_ctx *ctx, int32_t npairs,
+                                             const float *const *X, const int64_t *N,
+                                             const float *const *Y, const int64_t *M,
+                                             const double *Q, int32_t P, float *Xn, float *Yn,
+                                             double *norm, lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!X || !N || !Y || !M || !Xn || !Yn || !norm)
+    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  RETURN_IF(check_prop(ctx, npairs, P));
+  std::vector<lsg::PropPair> pairs((size_t)npairs);
+  for (int i = 0; i < npairs; ++i) {
+    if (!X[i] || !Y[i]) return fail(ctx, LSGCPD_E_INVALID, "pair %d: NULL cloud", i);
+    if (N[i] < 1 || M[i] < 1 || N[i] > kMaxPoints || M[i] > kMaxPoints)
+      return fail(ctx, LSGCPD_E_INVALID, "pair %d: M = %lld, N = %lld out of range", i,
+                  (long long)M[i], (long long)N[i]);
+    pairs[i] = {X[i], Y[i], N[i], M[i]};
+  }
+  RETURN_IF(set_device(ctx));
+  hipStream_t st = (hipStream_t)stream;
+  const size_t pb = pairs.size() * sizeof(lsg::PropPair), qb = Q ? (size_t)npairs * 9 * 8 : 0;
+  ENSURE(ptab, pb + qb);
+  // pageable sources: the call synchronises the stream before returning
+  HIPCHK(hipMemcpyAsync(ctx->ptab.p, pairs.data(), pb, hipMemcpyHostToDevice, st));
+  double *dq = nullptr;
+  if (Q) {
+    dq = (double *)((char *)ctx->ptab.p + pb);
+    HIPCHK(hipMemcpyAsync(dq, Q, qb, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(lsg::launch_prop_inputs((const lsg::PropPair *)ctx->ptab.p, npairs, dq, P, Xn, Yn, norm,
+                                 st));
+  HIPCHK(hipStreamSynchronize(st));
+  return LSGCPD_OK;
+}
+
+LSG_API lsgcpd_status lsgcpd_proposal_forward(lsgcpd_ctx *ctx, const float *theta, int32_t npairs,
+                                              int32_t P, const float *Xn, const float *Yn,
+                                              const double *norm, double *pose,
+                                              lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!theta || !Xn || !Yn || !norm || !pose)
+    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  RETURN_IF(check_prop(ctx, npairs, P));
+  RETURN_IF(set_device(ctx));
+  ENSURE(pws, lsg::prop_workspace_bytes(npairs, 0));
+  HIPCHK(lsg::launch_prop_forward(theta, npairs, P, Xn, Yn, norm, pose, ctx->pws.p,
+                                  (hipStream_t)stream));
+  return LSGCPD_OK;
+}
+
+LSG_API lsgcpd_status lsgcpd_proposal_train_step(lsgcpd_ctx *ctx, float *theta, float *m, float *v,
+                                                 int32_t step, double lr, int32_t npairs,
+                                                 int32_t P, const float *Xn, const float *Yn,
+                                                 const double *norm, int32_t nstored,
+                                                 const int32_t *index, const double *Q,
+                                                 const double *label, double *loss,
+                                                 int32_t *argmax, float *grad,
+                                                 lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!theta || !m || !v || !Xn || !Yn || !norm || !label || !loss)
+    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  RETURN_IF(check_prop(ctx, npairs, P));
+  if (step < 1) return fail(ctx, LSGCPD_E_INVALID, "step = %d must be >= 1", step);
+  if (!finite_pos(lr)) return fail(ctx, LSGCPD_E_INVALID, "lr must be finite and > 0");
+  if (index) {
+    for (int b = 0; b < npairs; ++b)
+      if (index[b] < 0 || index[b] >= nstored)
+        return fail(ctx, LSGCPD_E_INVALID, "index[%d] = %d not in [0, %d)", b, index[b], nstored);
+  } else if (nstored < npairs) {
+    return fail(ctx, LSGCPD_E_INVALID, "nstored = %d < npairs = %d", nstored, npairs);
+  }
+  RETURN_IF(set_device(ctx));
+  hipStream_t st = (hipStream_t)stream;
+  ENSURE(pws, lsg::prop_workspace_bytes(npairs, 1));
+  // the batch description (host) in one device buffer: labels, rotations, indices
+  const size_t lb = (size_t)npairs * 12 * 8, qb = Q ? (size_t)npairs * 9 * 8 : 0,
+               ib = index ? (size_t)npairs * 4 : 0;
+  ENSURE(pbatch, lb + qb + ib);
+  char *base = (char *)ctx->pbatch.p;
+  HIPCHK(hipMemcpyAsync(base, label, lb, hipMemcpyHostToDevice, st));
+  if (Q) HIPCHK(hipMemcpyAsync(base + lb, Q, qb, hipMemcpyHostToDevice, st));
+  if (index) HIPCHK(hipMemcpyAsync(base + lb + qb, index, ib, hipMemcpyHostToDevice, st));
+  HIPCHK(lsg::launch_prop_train(theta, m, v, step, lr, npairs, P, Xn, Yn, norm,
+                                index ? (const int *)(base + lb + qb) : nullptr,
+                                Q ? (const double *)(base + lb) : nullptr, (const double *)base,
+                                loss, argmax, grad, ctx->pws.p, st));
+  // pageable sources: the call synchronises the stream before returning
+  HIPCHK(hipStreamSynchronize(st));
+  return LSGCPD_OK;
+}
+
+namespace {
+
+// The 24 rotations of the cube (signed permutation matrices of determinant
+// +1), row-major: the multi-start set of lsgcpd_register_proposed.
+void cube_rotations(double (*G)[9]) {
+  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  int n = 0;
+  for (const auto &pm : perm)
+    for (int s = 0; s < 8; ++s) {
+      double R[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int r = 0; r < 3; ++r) R[3 * r + pm[r]] = (s >> r) & 1 ? -1.0 : 1.0;
+      const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                         R[2] * (R[3] * R[7] - R[4] * R[6]);
+      if (det > 0.0) memcpy(G[n++], R, sizeof R);
+    }
+}
+
+}  // namespace
+
+LSG_API lsgcpd_status lsgcpd_register_proposed(lsgcpd_ctx *ctx, int32_t npairs,
+                                               const float *const *X, const int64_t *N,
+                                               const float *const *Y, const int64_t *M,
+                                               const lsgcpd_params *p, const float *theta,
+                                               int32_t P, double accept, lsgcpd_pose *out,
+                                               lsgcpd_report *reports, int32_t *fallback,
+                                               lsgcpd_stream stream) {
+  if (!ctx) return LSGCPD_E_INVALID;
+  if (!X || !N || !Y || !M || !p || !theta || !out)
+    return fail(ctx, LSGCPD_E_INVALID, "NULL required argument");
+  RETURN_IF(check_prop(ctx, npairs, P));
+  if (!(accept > 0.0) || !isfinite(accept))
+    return fail(ctx, LSGCPD_E_INVALID, "accept must be finite and > 0");
+  RETURN_IF(check_params(ctx, p));
+  for (int i = 0; i < npairs; ++i) {
+    if (!X[i] || !Y[i]) return fail(ctx, LSGCPD_E_INVALID, "pair %d: NULL cloud", i);
+    if (N[i] < 1 || M[i] < 1 || N[i] > kMaxPoints || M[i] > kMaxPoints || p->k > M[i])
+      return fail(ctx, LSGCPD_E_INVALID, "pair %d: M = %lld, N = %lld out of range", i,
+                  (long long)M[i], (long long)N[i]);
+  }
+  RETURN_IF(set_device(ctx));
+  hipStream_t st = (hipStream_t)stream;
+  // 1. proposals
+  const size_t ni = (size_t)npairs * P * 3;
+  ENSURE(pin, ni * 2 * sizeof(float) + (size_t)npairs * (7 + 12) * sizeof(double));
+  float *Xn = (float *)ctx->pin.p, *Yn = Xn + ni;
+  double *norm = (double *)(Yn + ni), *pose = norm + (size_t)npairs * 7;
+  RETURN_IF(lsgcpd_proposal_inputs(ctx, npairs, X, N, Y, M, nullptr, P, Xn, Yn, norm, stream));
+  RETURN_IF(lsgcpd_proposal_forward(ctx, theta, npairs, P, Xn, Yn, norm, pose, stream));
+  std::vector<double> hp((size_t)npairs * 19);
+  HIPCHK(hipMemcpyAsync(hp.data(), norm, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<lsgcpd_pose> init((size_t)npairs);
+  for (int i = 0; i < npairs; ++i) {
+    const double *q = hp.data() + (size_t)npairs * 7 + 12 * (size_t)i;
+    memcpy(init[i].R, q, sizeof init[i].R);
+    memcpy(init[i].t, q + 9, sizeof init[i].t);
+  }
+  // 2. EM from the proposals, all pairs in one batch
+  std::vector<lsgcpd_report> rep((size_t)npairs);
+  {
+    // a pair whose EM ends on a non-finite state is simply not accepted
+    const lsgcpd_status s = register_problems(ctx, npairs, X, N, Y, M, nullptr, nullptr, p,
+                                              init.data(), out, rep.data(), nullptr, st);
+    if (s != LSGCPD_OK && s != LSGCPD_E_NUMERIC) return s;
+  }
+  // 3. acceptance: final sigma against the RMS radius of the target's samples
+  std::vector<int> rej;
+  for (int i = 0; i < npairs; ++i) {
+    const double s = hp[(size_t)7 * i + 6];
+    const bool ok = isfinite(rep[i].sigma2) && sqrt(rep[i].sigma2) <= accept * s;
+    if (fallback) fallback[i] = ok ? 0 : 1;
+    if (!ok) rej.push_back(i);
+  }
+  // 4. 24 starts for every rejected pair (rotation group of the cube, each
+  // with the translation that aligns the sampled centroids), batches of
+  // kFallbackPairs pairs (their live-tile lists stay within the culled
+  // plan's limit); the lowest final NLL of Eq. 4 wins, the proposal's own run
+  // included
+  constexpr size_t kFallbackPairs = 32;
+  double G[24][9];
+  cube_rotations(G);
+  for (size_t r0 = 0; r0 < rej.size(); r0 += kFallbackPairs) {
+    const size_t nr = rej.size() - r0 < kFallbackPairs ? rej.size() - r0 : kFallbackPairs;
+    const size_t nb = nr * 24;
+    std::vector<const float *> xs(nb), ys(nb);
+    std::vector<int64_t> ns(nb), ms(nb);
+    std::vector<lsgcpd_pose> st0(nb), so(nb);
+    std::vector<lsgcpd_report> sr(nb);
+    for (size_t r = 0; r < nr; ++r) {
+      const int i = rej[r0 + r];
+      const double *nm = hp.data() + (size_t)7 * i;
+      for (int k = 0; k < 24; ++k) {
+        const size_t j = r * 24 + k;
+        xs[j] = X[i];
+        ys[j] = Y[i];
+        ns[j] = N[i];
+        ms[j] = M[i];
+        memcpy(st0[j].R, G[k], sizeof G[k]);
+        for (int a = 0; a < 3; ++a)
+          st0[j].t[a] = nm[3 + a] - (G[k][3 * a] * nm[0] + G[k][3 * a + 1] * nm[1] +
+                                     G[k][3 * a + 2] * nm[2]);
+      }
+    }
+    const lsgcpd_status s = register_problems(ctx, (int)nb, xs.data(), ns.data(), ys.data(),
+                                              ms.data(), nullptr, nullptr, p, st0.data(),
+                                              so.data(), sr.data(), nullptr, st);
+    if (s != LSGCPD_OK && s != LSGCPD_E_NUMERIC) return s;
+    for (size_t r = 0; r < nr; ++r) {
+      const int i = rej[r0 + r];
+      for (int k = 0; k < 24; ++k) {
+        const size_t j = r * 24 + k;
+        if (isfinite(sr[j].nll_last) && !(sr[j].nll_last >= rep[i].nll_last)) {
+          out[i] = so[j];
+          rep[i] = sr[j];
+        }
+      }
+    }
+  }
+  if (reports) memcpy(reports, rep.data(), rep.size() * sizeof(lsgcpd_report));
   return LSGCPD_OK;
 }

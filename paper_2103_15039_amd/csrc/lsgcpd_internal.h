@@ -243,4 +243,35 @@ hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *
                                DevState *s, double *nll_trace, int trace_stride,
                                const unsigned long long *evcounts, int mode, hipStream_t st);
 
+// ---------------------------------------------------- pose proposal (f2)
+// Encoder parameters (flat float32, see proposal.hip) and the most points
+// per cloud the encoder takes.
+constexpr int kPropParams = 108425;
+constexpr int kPropMaxPoints = 4096;
+struct PropPair {
+  const float *X, *Y;
+  int64_t N, M;
+};
+// Workspace of a forward (train = 0) or training step (train = 1).
+size_t prop_workspace_bytes(int npairs, int train);
+// Encoder inputs: P sampled points of each cloud, the source rotated by
+// Q[9 b ..] (Q may be null), centred, divided by the target's RMS radius;
+// norm[7 b ..] = (mu_X, mu_Y, s).
+hipError_t launch_prop_inputs(const PropPair *pairs, int npairs, const double *Q, int P, float *Xn,
+                              float *Yn, double *norm, hipStream_t st);
+// Predicted poses (R row-major, t; world units), pose[12 b ..].
+hipError_t launch_prop_forward(const float *theta, int npairs, int P, const float *Xn,
+                               const float *Yn, const double *norm, double *pose, void *ws,
+                               hipStream_t st);
+// One Adam step on the mean loss of the batch: pair b of the batch is the
+// inputs of pair idx[b] (idx null: b) with the source rotated by Q[9 b ..]
+// (Q null: none); label[12 b ..] its pose (R row-major, t; world units, from
+// the rotated source to the target); loss[b] per pair; argmax (2 npairs x
+// 256, may be null) the pooled points; grad_out (may be null) the gradient
+// that was applied.
+hipError_t launch_prop_train(float *theta, float *m, float *v, int step, double lr, int npairs,
+                             int P, const float *Xn, const float *Yn, const double *norm,
+                             const int *idx, const double *Q, const double *label, double *loss,
+                             int *argmax, float *grad_out, void *ws, hipStream_t st);
+
 }  // namespace lsg

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
                          text=True).stdout
     exported = set(re.findall(r" T (lsgcpd_\w+)", out))
     assert exported == set(names)
-    assert lib.lsgcpd_abi_version() == L.ABI_VERSION == 5
+    assert lib.lsgcpd_abi_version() == L.ABI_VERSION == 6
     assert lib.lsgcpd_status_string(3) == b"LSGCPD_E_NOMEM"
 
 
