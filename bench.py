@@ -49,11 +49,18 @@ def parse():
                     help="pair-kernel back end (dense: scalar, every pair evaluated)")
     ap.add_argument("--workload", default="lidar_100000x50000",
                     choices=["rgbd_20000x20000", "lidar_100000x50000", "range_scanner_2000x2000",
-                             "batch256", "batch256_small", "depth_cf_20000x20000"],
+                             "batch256", "batch256_small", "depth_cf_20000x20000",
+                             "proposal1024"],
                     help="synthetic pair (the default is the benchmark's workload); batch256: "
                          "256 scene pairs of 1,000-30,000 points registered as one batch; "
                          "batch256_small: 256 pairs of 500-3,000 points; depth_cf: a depth-camera "
-                         "pair registered with confidence filtering and truncation")
+                         "pair registered with confidence filtering and truncation; "
+                         "proposal1024: 1,024 scene pairs at rotations uniform on SO(3), "
+                         "registered from the learned proposal (24-start fallback) against "
+                         "plain single-pair registrations")
+    ap.add_argument("--bf16", action="store_true",
+                    help="single-pair workloads: LSGCPD_BF16_CROSS (matrix-core exponent in "
+                         "the E steps whose error bound allows it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch workloads: skip the one-by-one registrations")
@@ -69,6 +76,11 @@ def parse():
                          "second interpreter through its launcher)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
+                                                          "COPY_WRITE"),
+                    help="only write profiles/estep_pairs_<workload>_traffic.json from four "
+                         "rocprofv3 --pmc output folders: FETCH_SIZE and WRITE_SIZE of a bench "
+                         "run of the workload, then of --copy-kernel 256")
     return ap.parse_args()
 
 
@@ -90,6 +102,59 @@ def measured_traffic(path):
         if hashlib.sha256(open(f, "rb").read()).hexdigest() != s.get("sha256"):
             return None
     return rec.get("bytes_per_launch")
+
+
+TRAFFIC_SOURCES = ["paper_2103_15039_amd/csrc/estep.hip", "paper_2103_15039_amd/csrc/api.hip",
+                   "paper_2103_15039_amd/csrc/order.hip"]
+PAIR_KERNEL = "estep_pairs_items"
+
+
+def pmc_per_dispatch(folder, kernel_substring=None, largest=False):
+    """Mean counter value per dispatch (KiB) from a rocprofv3 --pmc CSV
+    folder: over the dispatches of kernels whose name contains
+    kernel_substring, or of the kernel with the largest value (largest)."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection*.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    if not rows:
+        raise SystemExit(f"no counter_collection CSV under {folder}")
+    per = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        if kernel_substring and kernel_substring not in name:
+            continue
+        key = (name, r.get("Dispatch_Id"))
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    if largest:
+        top = max(per.items(), key=lambda kv: kv[1])[0][0]
+        per = {k: v for k, v in per.items() if k[0] == top}
+    vals = list(per.values())
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic_record(a):
+    """HBM bytes per pair-kernel launch: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) of the pair kernel, each scaled by bytes / counter of a plain
+    copy of 256 MiB; keyed on the SHA-256 of the kernel's and the plan's
+    sources."""
+    import hashlib
+    fetch, nf = pmc_per_dispatch(a.traffic_record[0], PAIR_KERNEL)
+    write, nw = pmc_per_dispatch(a.traffic_record[1], PAIR_KERNEL)
+    cf, _ = pmc_per_dispatch(a.traffic_record[2], largest=True)
+    cw, _ = pmc_per_dispatch(a.traffic_record[3], largest=True)
+    copy_bytes = 256 * (1 << 20)
+    fs, ws = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    rec = {"kernel": PAIR_KERNEL, "workload": a.workload,
+           "bytes_per_launch": fetch * 1024.0 * fs + write * 1024.0 * ws,
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+           "dispatches": [nf, nw], "fetch_scale": fs, "write_scale": ws,
+           "sources": [{"path": f, "sha256": hashlib.sha256(
+               open(os.path.join(ROOT, f), "rb").read()).hexdigest()} for f in TRAFFIC_SOURCES]}
+    out = os.path.join(ROOT, "profiles", f"estep_pairs_{a.workload}_traffic.json")
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec), flush=True)
 
 
 def rot_err_deg(R, R_gt):
@@ -410,6 +475,119 @@ def cpu_report():
     print(json.dumps(out), flush=True)
 
 
+PROPOSAL_THETA = os.path.join(ROOT, "paper_2103_15039_amd", "proposal_theta.npy")
+
+
+def proposal_main(a, npairs=1024, nsub=64, P=512, accept=0.05):
+    """The learned initial pose (the benchmark spec's M2): 1,024 held-out scene pairs
+    (2-3 primitives, M and N log-uniform in [1,000, 30,000], source rotation
+    uniform on SO(3)).  Timed, in registrations per second and with the
+    success rate (rotation error < 1 deg against the truth):
+      * proposed: lsgcpd_register_proposed -- the encoder's poses for all
+        pairs, EM from each in one batch, and for the pairs whose final sigma
+        exceeds `accept` times the target's RMS radius, EM from the 24
+        rotations of the cube in one batch (lowest NLL wins);
+      * plain: lsgcpd_register one pair at a time from the identity (all
+        pairs);
+      * plain, 24 starts: lsgcpd_register one pair at a time from each of the
+        24 cube rotations (centroids aligned), lowest NLL kept -- the plain
+        single-pair path at the proposal's success rate; timed on the first
+        `nsub` pairs (its rate per pair is what is reported).
+    EM: k = 10, 50 iterations at most, stopping when the relative NLL change
+    falls below 1e-6, for every path."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2103_15039_amd as L
+
+    theta = torch.from_numpy(np.load(PROPOSAL_THETA).astype(np.float32)).cuda()
+    pairs = datagen.proposal_pairs(npairs, split="eval", trial=0)
+    dev = [(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.Y).cuda()) for p in pairs]
+    kw = dict(k=10, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, tol=1e-6)
+    torch.cuda.synchronize()
+    L.register_proposed(dev[:8], theta, P=P, accept=accept, **kw)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, fb = L.register_proposed(dev, theta, P=P, accept=accept, **kw)
+    torch.cuda.synchronize()
+    dt_prop = time.perf_counter() - t0
+    # the encoder alone: its poses and their error
+    Xn, Yn, nm = L.proposal_inputs(dev, P)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pose = L.proposal_forward(theta, Xn, Yn, nm)
+    torch.cuda.synchronize()
+    dt_fwd = time.perf_counter() - t1
+    pose = pose.cpu().numpy()
+    prop_err = np.array([rot_err_deg(pose[i, :9].reshape(3, 3), p.R_gt)
+                         for i, p in enumerate(pairs)])
+
+    def ok(rs, ps):
+        return np.array([rot_err_deg(r.R, p.R_gt) < 1.0 for r, p in zip(rs, ps)])
+    succ_prop = ok(res, pairs)
+    t2 = time.perf_counter()
+    plain = [L.register(X, Y, **kw) for X, Y in dev]
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t2
+    succ_plain = ok(plain, pairs)
+    G = cube_rotations()
+    t3 = time.perf_counter()
+    best = []
+    for X, Y in dev[:nsub]:
+        mx = X.double().mean(0).cpu().numpy()
+        my = Y.double().mean(0).cpu().numpy()
+        rs = [L.register(X, Y, R0=g, t0=my - g @ mx, **kw) for g in G]
+        best.append(min(rs, key=lambda r: r.nll[-1]))
+    torch.cuda.synchronize()
+    dt_multi = time.perf_counter() - t3
+    succ_multi = ok(best, pairs[:nsub])
+    rate_prop = npairs / dt_prop
+    rate_multi = nsub / dt_multi
+    out = {
+        "metric": "pairs registered/s at rotation error < 1 deg",
+        "value": float(succ_prop.mean()) * rate_prop,
+        "unit": "successful pairs/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": dt_prop * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "proposal1024", "pairs": npairs,
+                   "points": "1000-30000 log-uniform", "rotation": "uniform on SO(3)",
+                   "encoder_points": P, "accept_sigma_over_radius": accept,
+                   "em_max_iters": EM_ITERS, "em_tol": 1e-6, "knn": 10},
+        "proposed": {"pairs_per_s": rate_prop, "success_rate": float(succ_prop.mean()),
+                     "fallback_rate": float(np.mean(fb)),
+                     "encoder_ms_all_pairs": dt_fwd * 1e3,
+                     "proposal_rot_err_deg_median": float(np.median(prop_err)),
+                     "proposal_within_30deg": float(np.mean(prop_err < 30)),
+                     "proposal_within_60deg": float(np.mean(prop_err < 60))},
+        "plain_identity": {"pairs_per_s": npairs / dt_plain,
+                           "success_rate": float(succ_plain.mean()),
+                           "successful_pairs_per_s": float(succ_plain.mean()) * npairs / dt_plain},
+        "plain_24_starts": {"pairs_per_s": rate_multi, "success_rate": float(succ_multi.mean()),
+                            "pairs_timed": nsub,
+                            "successful_pairs_per_s": float(succ_multi.mean()) * rate_multi},
+        "proposed_over_plain_24_starts": rate_prop / rate_multi,
+        "proposed_success_on_the_24_start_subset": float(succ_prop[:nsub].mean()),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cube_rotations():
+    """The 24 rotations of the cube (signed permutation matrices, det +1)."""
+    import itertools
+    import numpy as np
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1.0, -1.0), repeat=3):
+            R = np.zeros((3, 3))
+            for r in range(3):
+                R[r, perm[r]] = signs[r]
+            if np.linalg.det(R) > 0:
+                out.append(R)
+    return out
+
+
 def main():
     a = parse()
     if a.cpu_report:
@@ -417,6 +595,9 @@ def main():
         return
     if a.copy_kernel:
         copy_kernel(a.copy_kernel)
+        return
+    if a.traffic_record:
+        traffic_record(a)
         return
     if a.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -431,6 +612,9 @@ def main():
     if a.workload.startswith("depth_cf"):
         cf_main(a)
         return
+    if a.workload == "proposal1024":
+        proposal_main(a)
+        return
     import numpy as np
     import torch
     import datagen
@@ -441,7 +625,8 @@ def main():
     knn = 10 if a.workload.startswith("range") else 20
     X = torch.from_numpy(p.X).cuda()
     Y = torch.from_numpy(p.Y).cuda()
-    kw = dict(k=knn, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, backend=a.backend)
+    kw = dict(k=knn, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, backend=a.backend,
+              bf16=a.bf16)
     torch.cuda.synchronize()
     for _ in range(a.warmup):
         L.register(X, Y, **kw)
@@ -491,7 +676,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "M": M, "N": N, "em_iters": EM_ITERS,
                    "knn": knn, "alpha_max": 30.0, "lambda": 0.2, "w0": 0.1,
-                   "pair_kernel": a.backend},
+                   "pair_kernel": a.backend, "bf16_cross": a.bf16},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic},
         "estep": {"pair_kernel_ms": k_ms, "estep_ms": e_ms,
@@ -506,7 +691,8 @@ def main():
                   "dense_equiv_pair_evals_per_s_pair_kernel": M * N / (k_ms * 1e-3),
                   "dense_equiv_pair_evals_per_s_estep": M * N / (e_ms * 1e-3),
                   "launches_timed": prof["launches"]},
-        "result": {"rot_err_deg_vs_truth": rot_err, "iters": r.iters, "sigma2": r.sigma2},
+        "result": {"rot_err_deg_vs_truth": rot_err, "iters": r.iters, "sigma2": r.sigma2,
+                   "bf16_estep_count": r.bf16_steps},
     }
     if not a.no_cpu_baseline:
         nrm, al, Rp, tp, s2p = parity_inputs(p, a.workload)

@@ -365,57 +365,65 @@ lsgcpd_status lsgcpd_profile_launches(lsgcpd_ctx *ctx, double *pair_us, double *
 /* LSG-CPD converges from starts inside its basin (Sec. 1 and 5 of the paper
  * on initialisation); these calls run a small point-set encoder that
  * predicts the rigid motion of a cloud pair, to start registrations from.
- * Model: each cloud's P sampled points (normalised as below) pass a shared
- * per-point MLP 3 -> 64 -> 128 -> 256 (ReLU after each layer) and a max-pool
- * (ties to the lower point); the source's and the target's 256-vectors side
- * by side pass 512 -> 128 (ReLU) -> 9; outputs 0..5 are two 3-vectors made a
- * rotation by Gram-Schmidt (columns: the first normalised, the second's part
- * orthogonal to it normalised, their cross product), outputs 6..8 the
- * translation in normalised units.  theta: LSGCPD_PROPOSAL_PARAMS float32 in
- * device memory, layer by layer, each W row-major [out][in] then its b:
+ * Inputs: P points of each cloud (indices floor((2k + 1) N / (2P)), k =
+ * 0..P-1), each cloud centred on the mean of its samples and expressed in
+ * its principal-axis frame F = [e0 e1 e2] (eigenvectors of the samples'
+ * covariance, decreasing eigenvalues; e0, e1 signed so that the samples'
+ * third moment along them is >= 0, or their largest component positive if
+ * it is 0; e2 = e0 x e1; F = I for a zero covariance), both divided by the
+ * RMS radius s of the target's samples (1 if that is 0).  The inputs do not
+ * change when a cloud is rotated; the encoder predicts the rotation R_c and
+ * translation t^ between the two frames.
+ * Model: each cloud's inputs pass a shared per-point MLP 3 -> 64 -> 128 ->
+ * 256 (ReLU after each layer) and a max-pool (ties to the lower point); the
+ * source's and the target's 256-vectors side by side pass 512 -> 128 (ReLU)
+ * -> 9; outputs 0..5 are two 3-vectors made a rotation by Gram-Schmidt
+ * (columns: the first normalised, the second's part orthogonal to it
+ * normalised, their cross product), outputs 6..8 the translation t^.  The
+ * pose is R = F_Y R_c F_X^T, t = mu_Y + s F_Y t^ - R mu_X.  theta:
+ * LSGCPD_PROPOSAL_PARAMS float32 in device memory, layer by layer, each W
+ * row-major [out][in] then its b:
  *   W1 64x3, b1 64, W2 128x64, b2 128, W3 256x128, b3 256,
  *   W4 128x512, b4 128, W5 9x128, b5 9.
- * All arrays are caller-owned device memory; P <= 4096 points per cloud. */
+ * P <= 4096 points per cloud. */
 #define LSGCPD_PROPOSAL_PARAMS 108425
+#define LSGCPD_PROPOSAL_NORM 25  /* doubles of normalisation per pair */
 
 /* Encoder inputs of npairs pairs.  X[i] (N[i] x 3) and Y[i] (M[i] x 3):
- * float32 device clouds (the arrays of pointers and sizes are host memory).
- * P points of each cloud are taken at indices floor((2k + 1) N / (2P)),
- * k = 0..P-1; the source's are rotated by Q[9i..] (host, row-major; Q may
- * be NULL); each cloud is centred on the mean of its samples and both are
- * divided by the RMS distance s of the target's samples from their mean.
- * Outputs (device): Xn, Yn (npairs x P x 3 float32), norm[7i..] = (mu_X,
- * mu_Y, s) FP64.  Synchronises `stream`. */
+ * float32 device clouds (the arrays of pointers and sizes are host memory);
+ * the sources are first rotated by Q[9i..] (host, row-major; may be NULL).
+ * Outputs (device): Xn, Yn (npairs x P x 3 float32) and norm[25i..] =
+ * (mu_X, mu_Y, s, F_X, F_Y) FP64, frames row-major.  Synchronises `stream`. */
 lsgcpd_status lsgcpd_proposal_inputs(lsgcpd_ctx *ctx, int32_t npairs, const float *const *X,
                                      const int64_t *N, const float *const *Y, const int64_t *M,
                                      const double *Q, int32_t P, float *Xn, float *Yn,
                                      double *norm, lsgcpd_stream stream);
 
 /* Predicted poses of npairs pairs of inputs (device): pose[12i..] = (R
- * row-major, t) in world units, g(x) = R x + t mapping the (rotated) source
- * onto the target: t = mu_Y + s t^ - R mu_X.  Asynchronous on `stream`. */
+ * row-major, t) in world units, g(x) = R x + t mapping the source onto the
+ * target.  Asynchronous on `stream`. */
 lsgcpd_status lsgcpd_proposal_forward(lsgcpd_ctx *ctx, const float *theta, int32_t npairs,
                                       int32_t P, const float *Xn, const float *Yn,
                                       const double *norm, double *pose, lsgcpd_stream stream);
 
-/* One training step: the mean over the batch of |R^ - R_l|_F^2 +
- * |t^ - t^_l|^2 (t^_l = (R_l mu_X + t_l - mu_Y) / s, mu_X of the rotated
- * source), its gradient and one Adam update (beta1 0.9, beta2 0.999, eps
- * 1e-8, bias correction at step `step` >= 1, learning rate lr) of theta
- * with moments m and v (device float32, LSGCPD_PROPOSAL_PARAMS each, zero at
- * step 1).  Xn, Yn, norm (device) hold nstored pairs of inputs; pair b of the
- * batch is stored pair index[b] (host int32, each in [0, nstored), else
- * LSGCPD_E_INVALID; NULL: b), its source rotated by Q[9b..] (host, NULL:
- * none; a rotation of the normalised source is the same rotation of the raw
- * one); label[12b..] (host) its pose (R row-major, t; world units, rotated
- * source onto target).  Outputs (device): loss[b] per pair (FP64); argmax
- * (NULL or npairs x 2 x 256 int32: the pooled point of each channel, source
- * first) and grad (NULL or LSGCPD_PROPOSAL_PARAMS float32: the gradient
- * applied) are test aids.  Synchronises `stream`. */
+/* One training step: the mean over the batch of |a1 - R_l e_x|^2 +
+ * |a2 - R_l e_y|^2 + |t^ - t_l|^2 (a1, a2: the two output 3-vectors), with
+ * the label in the pair's frames (R_l = F_Y^T R F_X, t_l = F_Y^T (R mu_X +
+ * t - mu_Y) / s), its gradient and one Adam update
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias correction at step `step` >= 1,
+ * learning rate lr) of theta with moments m and v (device float32,
+ * LSGCPD_PROPOSAL_PARAMS each, zero at step 1).  Xn, Yn, norm (device) hold
+ * nstored pairs of inputs; pair b of the batch is stored pair index[b] (host
+ * int32, each in [0, nstored), else LSGCPD_E_INVALID; NULL: b);
+ * label[12b..] (host) its pose (R row-major, t; world units, source onto
+ * target).  Outputs (device): loss[b] per pair (FP64); argmax (NULL or
+ * npairs x 2 x 256 int32: the pooled point of each channel, source first)
+ * and grad (NULL or LSGCPD_PROPOSAL_PARAMS float32: the gradient applied)
+ * are test aids.  Synchronises `stream`. */
 lsgcpd_status lsgcpd_proposal_train_step(lsgcpd_ctx *ctx, float *theta, float *m, float *v,
                                          int32_t step, double lr, int32_t npairs, int32_t P,
                                          const float *Xn, const float *Yn, const double *norm,
-                                         int32_t nstored, const int32_t *index, const double *Q,
+                                         int32_t nstored, const int32_t *index,
                                          const double *label, double *loss, int32_t *argmax,
                                          float *grad, lsgcpd_stream stream);
 
@@ -424,11 +432,12 @@ lsgcpd_status lsgcpd_proposal_train_step(lsgcpd_ctx *ctx, float *theta, float *m
  *   1. the encoder's pose of every pair (theta, P points per cloud);
  *   2. LSG-CPD (params) from each, all pairs in one batch;
  *   3. a pair is accepted if its final sigma (sqrt of sigma2) is at most
- *      accept times the RMS radius of its target's samples;
- *   4. every other pair is registered again from 24 starts -- the rotations
- *      of the cube, each with the translation that aligns the sampled
- *      centroids -- in one batch, and the run with the lowest final NLL
- *      (Eq. 4), the proposal's included, is kept.
+ *      accept times the RMS radius s of its target's samples;
+ *   4. every other pair is registered again from R = F_Y G F_X^T (the
+ *      pair's principal-axis frames) with t aligning the sampled centroids,
+ *      G first the 4 sign changes of the axes, then, for pairs still not
+ *      accepted, the other 20 rotations of the cube; the run with the
+ *      lowest final NLL (Eq. 4), the proposal's included, is kept.
  * Clouds as for lsgcpd_register_batch (host arrays of device pointers and
  * sizes).  Outputs (host): out[i], reports[i] (NULL ok) of the run kept,
  * fallback[i] (NULL ok): 1 if step 4 ran for pair i.  Synchronises

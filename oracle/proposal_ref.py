@@ -25,13 +25,25 @@ Input normalisation (one cloud pair, optional rotation Q of the source):
   * P points of a cloud of N are taken at indices floor((2k + 1) N / (2P)),
     k = 0 .. P-1 (evenly spaced in the cloud's order; repeats when N < P);
   * x' = Q x; mu_X = mean of the sampled x', mu_Y = mean of the sampled y;
-    s = root-mean-square distance of the sampled y from mu_Y;
-  * inputs (x' - mu_X) / s and (y - mu_Y) / s (s = 1 when the target's
-    samples are all one point, e.g. P = 1).
-A pose (R, t) mapping x' onto y reads, in normalised units, R and
-t^ = (R mu_X + t - mu_Y) / s; a prediction (R^, t^) maps back to
-t = mu_Y + s t^ - R^ mu_X.
-Loss of a pair: |R^ - R_label|_F^2 + |t^ - t^_label|^2; of a batch: the mean.
+    s = root-mean-square distance of the sampled y from mu_Y (s = 1 when the
+    target's samples are all one point, e.g. P = 1);
+  * each cloud's principal-axis frame F = [e0 e1 e2]: the eigenvectors of
+    the covariance of its centred samples (1/P), eigenvalues in decreasing
+    order; e0 and e1 signed so that the third moment of the samples along
+    them is >= 0 (if it is exactly 0, so that their largest component is
+    positive), e2 = e0 x e1; F = I if the covariance is zero;
+  * inputs F_X^T (x' - mu_X) / s and F_Y^T (y - mu_Y) / s: both clouds in
+    their own frames, so the inputs do not change when either cloud is
+    rotated, and what is left to predict is the rotation between the frames.
+A pose (R, t) mapping x' onto y reads, in these units, R_c = F_Y^T R F_X and
+t^ = F_Y^T (R mu_X + t - mu_Y) / s; a prediction (R_c, t^) maps back to
+R = F_Y R_c F_X^T, t = mu_Y + s F_Y t^ - R mu_X.
+Loss of a pair: |a1 - R_c e_x|^2 + |a2 - R_c e_y|^2 + |t^ - t^_label|^2, with
+a1, a2 the two 3-vectors of the output and R_c the label's rotation in the
+frames -- least squares on the 6-D representation itself (the rotation it
+gives by Gram-Schmidt is the prediction).  A loss on the rotation would have
+no gradient where the prediction is a half turn from the label, which is
+where the frames' sign choices leave many labels; of a batch: the mean.
 Optimiser: Adam (Kingma and Ba, ICLR 2015) with bias correction,
 beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
 
@@ -40,7 +52,8 @@ activation is 0 (every point inactive), its gradient is 0.
 
 Parity status: pinned by tests/test_oracle_proposal.py -- Gram-Schmidt against
 its closed-form properties, the forward pass against an independent float64
-implementation in torch, every gradient against central finite differences,
+implementation in torch, every gradient against central finite differences
+(the loss is also pinned at the label, 0, and its minimiser),
 Adam against its published update in closed form, and the normalisation and
 pose mapping by round trips.
 """
@@ -77,8 +90,25 @@ def sample_indices(N, P):
     return ((2 * k + 1) * int(N)) // (2 * int(P))
 
 
+def principal_frame(c):
+    """Principal-axis frame of centred points c (P x 3), signs as stated in
+    the module docstring."""
+    C = c.T @ c / len(c)
+    if not np.any(C):
+        return np.eye(3)
+    w, V = np.linalg.eigh(C)
+    V = V[:, ::-1].copy()
+    for a in range(2):
+        m3 = np.sum((c @ V[:, a]) ** 3)
+        if m3 < 0.0 or (m3 == 0.0 and V[np.argmax(np.abs(V[:, a])), a] < 0.0):
+            V[:, a] = -V[:, a]
+    V[:, 2] = np.cross(V[:, 0], V[:, 1])
+    return V
+
+
 def normalise(X, Y, P, Q=None):
-    """Encoder inputs of one pair and the normalisation (mu_X, mu_Y, s)."""
+    """Encoder inputs of one pair and the normalisation (mu_X, mu_Y, s, F_X,
+    F_Y)."""
     xs = np.asarray(X, np.float64)[sample_indices(len(X), P)]
     ys = np.asarray(Y, np.float64)[sample_indices(len(Y), P)]
     if Q is not None:
@@ -87,19 +117,22 @@ def normalise(X, Y, P, Q=None):
     s = np.sqrt(np.mean(np.sum((ys - my) ** 2, axis=1)))
     if not s > 0.0:
         s = 1.0  # the target's samples are one point: no scale to take
-    return (xs - mx) / s, (ys - my) / s, (mx, my, s)
+    FX, FY = principal_frame(xs - mx), principal_frame(ys - my)
+    return (xs - mx) @ FX / s, (ys - my) @ FY / s, (mx, my, s, FX, FY)
 
 
 def label_normalised(R, t, norm):
-    """(R, t^) of a pose mapping x' onto y, in the normalised units of norm."""
-    mx, my, s = norm
-    return np.asarray(R, np.float64), (np.asarray(R) @ mx + np.asarray(t) - my) / s
+    """(R_c, t^) of a pose mapping x' onto y, in the units of norm."""
+    mx, my, s, FX, FY = norm
+    R = np.asarray(R, np.float64)
+    return FY.T @ R @ FX, FY.T @ (R @ mx + np.asarray(t) - my) / s
 
 
-def pose_from_prediction(R_hat, t_hat, norm):
-    """World pose of a normalised prediction."""
-    mx, my, s = norm
-    return np.asarray(R_hat, np.float64), my + s * np.asarray(t_hat) - R_hat @ mx
+def pose_from_prediction(R_c, t_hat, norm):
+    """World pose of a prediction in the units of norm."""
+    mx, my, s, FX, FY = norm
+    R = FY @ np.asarray(R_c, np.float64) @ FX.T
+    return R, my + s * (FY @ np.asarray(t_hat)) - R @ mx
 
 
 def gram_schmidt(a1, a2):
@@ -110,28 +143,6 @@ def gram_schmidt(a1, a2):
     b2 = u2 / np.linalg.norm(u2)
     b3 = np.cross(b1, b2)
     return np.stack([b1, b2, b3], axis=1)
-
-
-def gram_schmidt_backward(a1, a2, dR):
-    """Gradients of sum(dR * R) with respect to a1 and a2."""
-    n1 = np.linalg.norm(a1)
-    b1 = a1 / n1
-    c = b1 @ a2
-    u2 = a2 - c * b1
-    n2 = np.linalg.norm(u2)
-    b2 = u2 / n2
-    g1, g2, g3 = dR[:, 0], dR[:, 1], dR[:, 2]
-    # b3 = b1 x b2: d<g3, b1 x b2> = <b2 x g3, db1> + <g3 x b1, db2>
-    gb1 = g1 + np.cross(b2, g3)
-    gb2 = g2 + np.cross(g3, b1)
-    # b2 = u2 / |u2|
-    gu2 = (gb2 - (gb2 @ b2) * b2) / n2
-    # u2 = a2 - (b1 . a2) b1
-    ga2 = gu2 - (gu2 @ b1) * b1
-    gb1 = gb1 - (gu2 @ b1) * a2 - c * gu2
-    # b1 = a1 / |a1|
-    ga1 = (gb1 - (gb1 @ b1) * b1) / n1
-    return ga1, ga2
 
 
 @dataclass
@@ -177,8 +188,14 @@ def forward_pair(prm, xs, ys, argmax_src=None, argmax_tgt=None):
     return PairPass(src=a, tgt=b, z=z, h4=h4, o=o, R=R, t=o[6:9].copy())
 
 
+def pair_target(R_l, t_l):
+    """The 9 outputs a pair's label asks for: R_l's first two columns, t_l."""
+    R_l = np.asarray(R_l, np.float64)
+    return np.concatenate([R_l[:, 0], R_l[:, 1], np.asarray(t_l, np.float64)])
+
+
 def pair_loss(pp, R_l, t_l):
-    return float(np.sum((pp.R - R_l) ** 2) + np.sum((pp.t - t_l) ** 2))
+    return float(np.sum((pp.o - pair_target(R_l, t_l)) ** 2))
 
 
 def _encode_backward(prm, cp, gf, grads):
@@ -214,10 +231,7 @@ def batch_loss_and_grad(theta, X_in, Y_in, R_l, t_l, argmax=None):
                           am[0], am[1])
         passes.append(pp)
         total += pair_loss(pp, R_l[i], t_l[i])
-        dR = 2.0 * (pp.R - R_l[i]) / B
-        dt = 2.0 * (pp.t - t_l[i]) / B
-        ga1, ga2 = gram_schmidt_backward(pp.o[0:3], pp.o[3:6], dR)
-        go = np.concatenate([ga1, ga2, dt])
+        go = 2.0 * (pp.o - pair_target(R_l[i], t_l[i])) / B
         grads["W5"] += np.outer(go, pp.h4)
         grads["b5"] += go
         gh4 = prm["W5"].T @ go

@@ -140,7 +140,7 @@ def load_library(path=LIB_PATH):
     lib.lsgcpd_proposal_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
     lib.lsgcpd_proposal_train_step.restype = C.c_int
     lib.lsgcpd_proposal_train_step.argtypes = [vp, vp, vp, vp, i32, d, i32, i32, vp, vp, vp, i32,
-                                               vp, vp, vp, vp, vp, vp, vp]
+                                               vp, vp, vp, vp, vp, vp]
     lib.lsgcpd_register_proposed.restype = C.c_int
     lib.lsgcpd_register_proposed.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Params), vp, i32,
                                              d, C.POINTER(Pose), C.POINTER(Report), vp, vp]
@@ -499,12 +499,14 @@ def profile_launches(device=0):
 
 
 PROPOSAL_PARAMS = 108425
+PROPOSAL_NORM = 25
 
 
 def proposal_inputs(pairs, P, Q=None):
     """Encoder inputs of the (X, Y) pairs (lsgcpd_proposal_inputs): Xn, Yn
-    (npairs, P, 3) float32 and norm (npairs, 7) float64 device tensors.  Q:
-    optional (npairs, 3, 3) rotations of the sources."""
+    (npairs, P, 3) float32 and norm (npairs, 25: mu_X, mu_Y, s, F_X, F_Y)
+    float64 device tensors.  Q: optional (npairs, 3, 3) rotations of the
+    sources."""
     torch = _torch()
     n = len(pairs)
     if n < 1:
@@ -518,7 +520,7 @@ def proposal_inputs(pairs, P, Q=None):
     device = Xs[0].device
     Xn = torch.empty((n, P, 3), dtype=torch.float32, device=device)
     Yn = torch.empty((n, P, 3), dtype=torch.float32, device=device)
-    norm = torch.empty((n, 7), dtype=torch.float64, device=device)
+    norm = torch.empty((n, PROPOSAL_NORM), dtype=torch.float64, device=device)
     Qh = None
     if Q is not None:
         Qh = np.ascontiguousarray(Q, dtype=np.float64).reshape(n, 9)
@@ -563,13 +565,13 @@ def _host(a):
     return C.c_void_p(a.ctypes.data) if a is not None else C.c_void_p(0)
 
 
-def proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, label, index=None, Q=None,
+def proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, label, index=None,
                         want_argmax=False, want_grad=False):
     """One Adam step of the proposal on a batch (lsgcpd_proposal_train_step);
     theta, m, v (float32 device tensors of PROPOSAL_PARAMS) are updated in
-    place.  Xn, Yn, norm: stored inputs (proposal_inputs); label (B, 12),
-    index (B,) and Q (B, 3, 3): host arrays.  Returns the device tensors
-    (loss per pair, argmax or None, gradient or None)."""
+    place.  Xn, Yn, norm: stored inputs (proposal_inputs); label (B, 12) and
+    index (B,): host arrays.  Returns the device tensors (loss per pair,
+    argmax or None, gradient or None)."""
     torch = _torch()
     dev = Xn.device.index
     label = np.ascontiguousarray(label, np.float64).reshape(-1, 12)
@@ -579,15 +581,14 @@ def proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, label, index=None, 
         if a.dtype != torch.float32 or a.numel() != PROPOSAL_PARAMS or not a.is_contiguous():
             raise ValueError(f"{name} must be a contiguous float32 tensor of {PROPOSAL_PARAMS}")
     idx = None if index is None else np.ascontiguousarray(index, np.int32).reshape(B)
-    Qh = None if Q is None else np.ascontiguousarray(Q, np.float64).reshape(B, 9)
     loss = torch.empty(B, dtype=torch.float64, device=Xn.device)
     am = torch.empty((B, 2, 256), dtype=torch.int32, device=Xn.device) if want_argmax else None
     g = torch.empty(PROPOSAL_PARAMS, dtype=torch.float32, device=Xn.device) if want_grad else None
     ctx = context(dev)
     st = load_library().lsgcpd_proposal_train_step(
         ctx, _ptr(theta), _ptr(m), _ptr(v), int(step), float(lr), B, P, _ptr(Xn), _ptr(Yn),
-        _ptr(norm), int(Xn.shape[0]), _host(idx), _host(Qh), _host(label), _ptr(loss), _ptr(am),
-        _ptr(g), _stream(dev))
+        _ptr(norm), int(Xn.shape[0]), _host(idx), _host(label), _ptr(loss), _ptr(am), _ptr(g),
+        _stream(dev))
     _check(st, ctx)
     return loss, am, g
 

@@ -1339,9 +1339,8 @@ LSG_API lsgcpd_status lsgcpd_proposal_train_step(lsgcpd_ctx *ctx, float *theta, 
                                                  int32_t step, double lr, int32_t npairs,
                                                  int32_t P, const float *Xn, const float *Yn,
                                                  const double *norm, int32_t nstored,
-                                                 const int32_t *index, const double *Q,
-                                                 const double *label, double *loss,
-                                                 int32_t *argmax, float *grad,
+                                                 const int32_t *index, const double *label,
+                                                 double *loss, int32_t *argmax, float *grad,
                                                  lsgcpd_stream stream) {
   if (!ctx) return LSGCPD_E_INVALID;
   if (!theta || !m || !v || !Xn || !Yn || !norm || !label || !loss)
@@ -1359,17 +1358,14 @@ LSG_API lsgcpd_status lsgcpd_proposal_train_step(lsgcpd_ctx *ctx, float *theta, 
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
   ENSURE(pws, lsg::prop_workspace_bytes(npairs, 1));
-  // the batch description (host) in one device buffer: labels, rotations, indices
-  const size_t lb = (size_t)npairs * 12 * 8, qb = Q ? (size_t)npairs * 9 * 8 : 0,
-               ib = index ? (size_t)npairs * 4 : 0;
-  ENSURE(pbatch, lb + qb + ib);
+  // the batch description (host) in one device buffer: labels, indices
+  const size_t lb = (size_t)npairs * 12 * 8, ib = index ? (size_t)npairs * 4 : 0;
+  ENSURE(pbatch, lb + ib);
   char *base = (char *)ctx->pbatch.p;
   HIPCHK(hipMemcpyAsync(base, label, lb, hipMemcpyHostToDevice, st));
-  if (Q) HIPCHK(hipMemcpyAsync(base + lb, Q, qb, hipMemcpyHostToDevice, st));
-  if (index) HIPCHK(hipMemcpyAsync(base + lb + qb, index, ib, hipMemcpyHostToDevice, st));
+  if (index) HIPCHK(hipMemcpyAsync(base + lb, index, ib, hipMemcpyHostToDevice, st));
   HIPCHK(lsg::launch_prop_train(theta, m, v, step, lr, npairs, P, Xn, Yn, norm,
-                                index ? (const int *)(base + lb + qb) : nullptr,
-                                Q ? (const double *)(base + lb) : nullptr, (const double *)base,
+                                index ? (const int *)(base + lb) : nullptr, (const double *)base,
                                 loss, argmax, grad, ctx->pws.p, st));
   // pageable sources: the call synchronises the stream before returning
   HIPCHK(hipStreamSynchronize(st));
@@ -1418,18 +1414,19 @@ LSG_API lsgcpd_status lsgcpd_register_proposed(lsgcpd_ctx *ctx, int32_t npairs,
   RETURN_IF(set_device(ctx));
   hipStream_t st = (hipStream_t)stream;
   // 1. proposals
+  constexpr int NS = lsg::kPropNorm;
   const size_t ni = (size_t)npairs * P * 3;
-  ENSURE(pin, ni * 2 * sizeof(float) + (size_t)npairs * (7 + 12) * sizeof(double));
+  ENSURE(pin, ni * 2 * sizeof(float) + (size_t)npairs * (NS + 12) * sizeof(double));
   float *Xn = (float *)ctx->pin.p, *Yn = Xn + ni;
-  double *norm = (double *)(Yn + ni), *pose = norm + (size_t)npairs * 7;
+  double *norm = (double *)(Yn + ni), *pose = norm + (size_t)npairs * NS;
   RETURN_IF(lsgcpd_proposal_inputs(ctx, npairs, X, N, Y, M, nullptr, P, Xn, Yn, norm, stream));
   RETURN_IF(lsgcpd_proposal_forward(ctx, theta, npairs, P, Xn, Yn, norm, pose, stream));
-  std::vector<double> hp((size_t)npairs * 19);
+  std::vector<double> hp((size_t)npairs * (NS + 12));
   HIPCHK(hipMemcpyAsync(hp.data(), norm, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<lsgcpd_pose> init((size_t)npairs);
   for (int i = 0; i < npairs; ++i) {
-    const double *q = hp.data() + (size_t)npairs * 7 + 12 * (size_t)i;
+    const double *q = hp.data() + (size_t)npairs * NS + 12 * (size_t)i;
     memcpy(init[i].R, q, sizeof init[i].R);
     memcpy(init[i].t, q + 9, sizeof init[i].t);
   }
@@ -1442,57 +1439,80 @@ LSG_API lsgcpd_status lsgcpd_register_proposed(lsgcpd_ctx *ctx, int32_t npairs,
     if (s != LSGCPD_OK && s != LSGCPD_E_NUMERIC) return s;
   }
   // 3. acceptance: final sigma against the RMS radius of the target's samples
+  auto accepted = [&](int i) {
+    return isfinite(rep[i].sigma2) && sqrt(rep[i].sigma2) <= accept * hp[(size_t)NS * i + 6];
+  };
   std::vector<int> rej;
   for (int i = 0; i < npairs; ++i) {
-    const double s = hp[(size_t)7 * i + 6];
-    const bool ok = isfinite(rep[i].sigma2) && sqrt(rep[i].sigma2) <= accept * s;
-    if (fallback) fallback[i] = ok ? 0 : 1;
-    if (!ok) rej.push_back(i);
+    if (fallback) fallback[i] = accepted(i) ? 0 : 1;
+    if (!accepted(i)) rej.push_back(i);
   }
-  // 4. 24 starts for every rejected pair (rotation group of the cube, each
-  // with the translation that aligns the sampled centroids), batches of
+  // 4. starts in the pair's principal-axis frames, R = F_Y G F_X^T with G
+  // first the 4 sign changes of the axes, then the other 20 rotations of the
+  // cube (axis permutations), t aligning the sampled centroids; batches of
   // kFallbackPairs pairs (their live-tile lists stay within the culled
-  // plan's limit); the lowest final NLL of Eq. 4 wins, the proposal's own run
-  // included
+  // plan's limit).  The run with the lowest final NLL of Eq. 4 is kept, the
+  // proposal's own run included; a pair accepted after the sign changes
+  // does not take the other 20.
   constexpr size_t kFallbackPairs = 32;
   double G[24][9];
   cube_rotations(G);
-  for (size_t r0 = 0; r0 < rej.size(); r0 += kFallbackPairs) {
-    const size_t nr = rej.size() - r0 < kFallbackPairs ? rej.size() - r0 : kFallbackPairs;
-    const size_t nb = nr * 24;
-    std::vector<const float *> xs(nb), ys(nb);
-    std::vector<int64_t> ns(nb), ms(nb);
-    std::vector<lsgcpd_pose> st0(nb), so(nb);
-    std::vector<lsgcpd_report> sr(nb);
-    for (size_t r = 0; r < nr; ++r) {
-      const int i = rej[r0 + r];
-      const double *nm = hp.data() + (size_t)7 * i;
-      for (int k = 0; k < 24; ++k) {
-        const size_t j = r * 24 + k;
-        xs[j] = X[i];
-        ys[j] = Y[i];
-        ns[j] = N[i];
-        ms[j] = M[i];
-        memcpy(st0[j].R, G[k], sizeof G[k]);
-        for (int a = 0; a < 3; ++a)
-          st0[j].t[a] = nm[3 + a] - (G[k][3 * a] * nm[0] + G[k][3 * a + 1] * nm[1] +
-                                     G[k][3 * a + 2] * nm[2]);
-      }
+  for (int stage = 0; stage < 2 && !rej.empty(); ++stage) {
+    std::vector<int> ks;
+    for (int k = 0; k < 24; ++k) {
+      const bool diag = G[k][1] == 0.0 && G[k][2] == 0.0 && G[k][5] == 0.0;
+      if (diag == (stage == 0)) ks.push_back(k);
     }
-    const lsgcpd_status s = register_problems(ctx, (int)nb, xs.data(), ns.data(), ys.data(),
-                                              ms.data(), nullptr, nullptr, p, st0.data(),
-                                              so.data(), sr.data(), nullptr, st);
-    if (s != LSGCPD_OK && s != LSGCPD_E_NUMERIC) return s;
-    for (size_t r = 0; r < nr; ++r) {
-      const int i = rej[r0 + r];
-      for (int k = 0; k < 24; ++k) {
-        const size_t j = r * 24 + k;
-        if (isfinite(sr[j].nll_last) && !(sr[j].nll_last >= rep[i].nll_last)) {
-          out[i] = so[j];
-          rep[i] = sr[j];
+    const size_t nk = ks.size();
+    for (size_t r0 = 0; r0 < rej.size(); r0 += kFallbackPairs) {
+      const size_t nr = rej.size() - r0 < kFallbackPairs ? rej.size() - r0 : kFallbackPairs;
+      const size_t nb = nr * nk;
+      std::vector<const float *> xs(nb), ys(nb);
+      std::vector<int64_t> ns(nb), ms(nb);
+      std::vector<lsgcpd_pose> st0(nb), so(nb);
+      std::vector<lsgcpd_report> sr(nb);
+      for (size_t r = 0; r < nr; ++r) {
+        const int i = rej[r0 + r];
+        const double *nm = hp.data() + (size_t)NS * i, *FX = nm + 7, *FY = nm + 16;
+        for (size_t kk = 0; kk < nk; ++kk) {
+          const double *g = G[ks[kk]];
+          const size_t j = r * nk + kk;
+          xs[j] = X[i];
+          ys[j] = Y[i];
+          ns[j] = N[i];
+          ms[j] = M[i];
+          double T[9];
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              T[3 * a + b] = FY[3 * a] * g[b] + FY[3 * a + 1] * g[3 + b] + FY[3 * a + 2] * g[6 + b];
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+              st0[j].R[3 * a + b] =
+                  T[3 * a] * FX[3 * b] + T[3 * a + 1] * FX[3 * b + 1] + T[3 * a + 2] * FX[3 * b + 2];
+          for (int a = 0; a < 3; ++a)
+            st0[j].t[a] = nm[3 + a] - (st0[j].R[3 * a] * nm[0] + st0[j].R[3 * a + 1] * nm[1] +
+                                       st0[j].R[3 * a + 2] * nm[2]);
+        }
+      }
+      const lsgcpd_status s = register_problems(ctx, (int)nb, xs.data(), ns.data(), ys.data(),
+                                                ms.data(), nullptr, nullptr, p, st0.data(),
+                                                so.data(), sr.data(), nullptr, st);
+      if (s != LSGCPD_OK && s != LSGCPD_E_NUMERIC) return s;
+      for (size_t r = 0; r < nr; ++r) {
+        const int i = rej[r0 + r];
+        for (size_t kk = 0; kk < nk; ++kk) {
+          const size_t j = r * nk + kk;
+          if (isfinite(sr[j].nll_last) && !(sr[j].nll_last >= rep[i].nll_last)) {
+            out[i] = so[j];
+            rep[i] = sr[j];
+          }
         }
       }
     }
+    std::vector<int> still;
+    for (int i : rej)
+      if (!accepted(i)) still.push_back(i);
+    rej.swap(still);
   }
   if (reports) memcpy(reports, rep.data(), rep.size() * sizeof(lsgcpd_report));
   return LSGCPD_OK;

@@ -494,46 +494,6 @@ __global__ void knn_boxes(const float4 *__restrict__ Ys, int M, int ntiles,
   }
 }
 
-// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (FP64).
-// On return a holds the eigenvalues on its diagonal and v the eigenvectors as
-// columns.
-__device__ void jacobi3(double a[3][3], double v[3][3]) {
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) v[r][c] = r == c ? 1.0 : 0.0;
-  const int P[3] = {0, 0, 1};
-  const int Q[3] = {1, 2, 2};
-  for (int sweep = 0; sweep < 32; ++sweep) {
-    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
-    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-    if (off == 0.0 || off <= 1e-36 * dia) break;
-    for (int e = 0; e < 3; ++e) {
-      const int p = P[e], q = Q[e];
-      const double apq = a[p][q];
-      if (apq == 0.0) continue;
-      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
-      double t;
-      if (fabs(theta) > 1e150)
-        t = 0.5 / theta;
-      else
-        t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-      const double c = 1.0 / sqrt(t * t + 1.0);
-      const double s = t * c;
-      a[p][p] -= t * apq;
-      a[q][q] += t * apq;
-      a[p][q] = a[q][p] = 0.0;
-      const int r = 3 - p - q;
-      const double arp = a[r][p], arq = a[r][q];
-      a[r][p] = a[p][r] = c * arp - s * arq;
-      a[r][q] = a[q][r] = s * arp + c * arq;
-      for (int k = 0; k < 3; ++k) {
-        const double vkp = v[k][p], vkq = v[k][q];
-        v[k][p] = c * vkp - s * vkq;
-        v[k][q] = s * vkp + c * vkq;
-      }
-    }
-  }
-}
-
 // Query q (sorted position) is target qorig[q] of the caller's order; keys
 // hold original indices into Y.
 template <int KM>

@@ -83,6 +83,46 @@ struct DevState {
   int32_t pad;
 };
 
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (FP64).
+// On return a holds the eigenvalues on its diagonal and v the eigenvectors as
+// columns.
+__device__ inline void jacobi3(double a[3][3], double v[3][3]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) v[r][c] = r == c ? 1.0 : 0.0;
+  const int P[3] = {0, 0, 1};
+  const int Q[3] = {1, 2, 2};
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off == 0.0 || off <= 1e-36 * dia) break;
+    for (int e = 0; e < 3; ++e) {
+      const int p = P[e], q = Q[e];
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      double t;
+      if (fabs(theta) > 1e150)
+        t = 0.5 / theta;
+      else
+        t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0);
+      const double s = t * c;
+      a[p][p] -= t * apq;
+      a[q][q] += t * apq;
+      a[p][q] = a[q][p] = 0.0;
+      const int r = 3 - p - q;
+      const double arp = a[r][p], arq = a[r][q];
+      a[r][p] = a[p][r] = c * arp - s * arq;
+      a[r][q] = a[q][r] = s * arp + c * arq;
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = v[k][p], vkq = v[k][q];
+        v[k][p] = c * vkp - s * vkq;
+        v[k][q] = s * vkp + c * vkq;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the hipError_t of the launch.
 
@@ -255,8 +295,10 @@ struct PropPair {
 // Workspace of a forward (train = 0) or training step (train = 1).
 size_t prop_workspace_bytes(int npairs, int train);
 // Encoder inputs: P sampled points of each cloud, the source rotated by
-// Q[9 b ..] (Q may be null), centred, divided by the target's RMS radius;
-// norm[7 b ..] = (mu_X, mu_Y, s).
+// Q[9 b ..] (Q may be null), each centred and expressed in its principal-axis
+// frame, divided by the target's RMS radius; norm[kPropNorm b ..] =
+// (mu_X, mu_Y, s, F_X, F_Y) with the frames row-major (columns = axes).
+constexpr int kPropNorm = 25;
 hipError_t launch_prop_inputs(const PropPair *pairs, int npairs, const double *Q, int P, float *Xn,
                               float *Yn, double *norm, hipStream_t st);
 // Predicted poses (R row-major, t; world units), pose[12 b ..].
@@ -264,14 +306,13 @@ hipError_t launch_prop_forward(const float *theta, int npairs, int P, const floa
                                const float *Yn, const double *norm, double *pose, void *ws,
                                hipStream_t st);
 // One Adam step on the mean loss of the batch: pair b of the batch is the
-// inputs of pair idx[b] (idx null: b) with the source rotated by Q[9 b ..]
-// (Q null: none); label[12 b ..] its pose (R row-major, t; world units, from
-// the rotated source to the target); loss[b] per pair; argmax (2 npairs x
+// inputs of pair idx[b] (idx null: b); label[12 b ..] its pose (R row-major,
+// t; world units, source onto target); loss[b] per pair; argmax (2 npairs x
 // 256, may be null) the pooled points; grad_out (may be null) the gradient
 // that was applied.
 hipError_t launch_prop_train(float *theta, float *m, float *v, int step, double lr, int npairs,
                              int P, const float *Xn, const float *Yn, const double *norm,
-                             const int *idx, const double *Q, const double *label, double *loss,
-                             int *argmax, float *grad_out, void *ws, hipStream_t st);
+                             const int *idx, const double *label, double *loss, int *argmax,
+                             float *grad_out, void *ws, hipStream_t st);
 
 }  // namespace lsg

@@ -26,8 +26,10 @@
 //                     largest value and, on ties, the lowest point -- no
 //                     P x 256 activation ever reaches memory;
 //  * prop_head        one block per pair: 512 -> 128 -> 9, Gram-Schmidt, pose;
-//  * prop_head_train  the same, the loss |R - R_l|_F^2 + |t - t_l|^2 and its
-//                     gradient back to the pooled features;
+//  * prop_head_train  the same, the loss (least squares of the 9 outputs
+//                     against the label's first two rotation columns and its
+//                     translation, in the frames) and its gradient back to
+//                     the pooled features;
 //  * prop_encode_back one block per cloud: the gradient reaches only the
 //                     argmax point of each live channel, so the per-point
 //                     layers are recomputed and differentiated at those
@@ -70,11 +72,10 @@ __device__ __forceinline__ int64_t sample_index(int k, int64_t n, int P) {
 }
 
 // Point p of cloud c (pair c >> 1; source if c is even): the inputs of pair
-// idx[b] (idx null: pair b), the source rotated by Q[9 b ..] (Q null: none).
+// idx[b] (idx null: pair b).
 __device__ __forceinline__ void load_point(const float *__restrict__ Xn,
                                            const float *__restrict__ Yn, int P,
-                                           const int *__restrict__ idx,
-                                           const double *__restrict__ Q, int cloud, int p,
+                                           const int *__restrict__ idx, int cloud, int p,
                                            float &x0, float &x1, float &x2) {
   const int b = cloud >> 1;
   const int base = idx ? idx[b] : b;
@@ -82,15 +83,49 @@ __device__ __forceinline__ void load_point(const float *__restrict__ Xn,
   x0 = q[0];
   x1 = q[1];
   x2 = q[2];
-  if (Q && !(cloud & 1)) {
-    const double *r = Q + 9 * b;
-    const double a0 = x0, a1 = x1, a2 = x2;
-    x0 = (float)(r[0] * a0 + r[1] * a1 + r[2] * a2);
-    x1 = (float)(r[3] * a0 + r[4] * a1 + r[5] * a2);
-    x2 = (float)(r[6] * a0 + r[7] * a1 + r[8] * a2);
-  }
 }
 
+// Principal-axis frame of a cloud from its covariance (00 01 02 11 12 22,
+// about the mean): eigenvectors in decreasing order of eigenvalue, as the
+// columns of F (row-major 3x3); the identity for a zero covariance.  Signs
+// are set afterwards from the third moments (sign_frame).
+__device__ void eigen_frame(const double (&cv)[6], double (&F)[9]) {
+  if (cv[0] == 0.0 && cv[1] == 0.0 && cv[2] == 0.0 && cv[3] == 0.0 && cv[4] == 0.0 &&
+      cv[5] == 0.0) {
+    for (int i = 0; i < 9; ++i) F[i] = i % 4 == 0 ? 1.0 : 0.0;
+    return;
+  }
+  double a[3][3] = {{cv[0], cv[1], cv[2]}, {cv[1], cv[3], cv[4]}, {cv[2], cv[4], cv[5]}};
+  double v[3][3];
+  jacobi3(a, v);
+  int o[3] = {0, 1, 2};  // decreasing eigenvalues
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2 - i; ++j)
+      if (a[o[j]][o[j]] < a[o[j + 1]][o[j + 1]]) {
+        const int t = o[j];
+        o[j] = o[j + 1];
+        o[j + 1] = t;
+      }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) F[3 * r + c] = v[r][o[c]];
+}
+
+// Signs of e0 and e1 from their third moments m3 (if one is exactly 0: the
+// largest component positive), then e2 = e0 x e1.
+__device__ void sign_frame(double (&F)[9], const double *m3) {
+  for (int c = 0; c < 2; ++c) {
+    int big = 0;
+    for (int r = 1; r < 3; ++r)
+      if (fabs(F[3 * r + c]) > fabs(F[3 * big + c])) big = r;
+    if (m3[c] < 0.0 || (m3[c] == 0.0 && F[3 * big + c] < 0.0))
+      for (int r = 0; r < 3; ++r) F[3 * r + c] = -F[3 * r + c];
+  }
+  F[2] = F[3] * F[7] - F[6] * F[4];
+  F[5] = F[6] * F[1] - F[0] * F[7];
+  F[8] = F[0] * F[4] - F[3] * F[1];
+}
+
+// One block per pair: samples, means, target scale, the two frames, inputs.
 __global__ __launch_bounds__(256) void prop_inputs(const PropPair *__restrict__ pairs,
                                                    const double *__restrict__ Q, int P,
                                                    float *__restrict__ Xn, float *__restrict__ Yn,
@@ -101,47 +136,101 @@ __global__ __launch_bounds__(256) void prop_inputs(const PropPair *__restrict__ 
   if (Q)
     for (int i = 0; i < 9; ++i) q[i] = Q[9 * b + i];
   __shared__ double red[4];
+  auto xpt = [&](int k, double (&x)[3]) {
+    const int64_t ix = sample_index(k, pr.N, P);
+    const double x0 = pr.X[3 * ix], x1 = pr.X[3 * ix + 1], x2 = pr.X[3 * ix + 2];
+    for (int a = 0; a < 3; ++a) x[a] = q[3 * a] * x0 + q[3 * a + 1] * x1 + q[3 * a + 2] * x2;
+  };
+  auto ypt = [&](int k, double (&y)[3]) {
+    const int64_t iy = sample_index(k, pr.M, P);
+    for (int a = 0; a < 3; ++a) y[a] = (double)pr.Y[3 * iy + a];
+  };
   double sx[3] = {0, 0, 0}, sy[3] = {0, 0, 0};
   for (int k = threadIdx.x; k < P; k += 256) {
-    const int64_t ix = sample_index(k, pr.N, P), iy = sample_index(k, pr.M, P);
-    const double x0 = pr.X[3 * ix], x1 = pr.X[3 * ix + 1], x2 = pr.X[3 * ix + 2];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) sx[a] += q[3 * a] * x0 + q[3 * a + 1] * x1 + q[3 * a + 2] * x2;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) sy[a] += (double)pr.Y[3 * iy + a];
+    double x[3], y[3];
+    xpt(k, x);
+    ypt(k, y);
+    for (int a = 0; a < 3; ++a) {
+      sx[a] += x[a];
+      sy[a] += y[a];
+    }
   }
   double mx[3], my[3];
   for (int a = 0; a < 3; ++a) {
     mx[a] = block_sum(sx[a], red) / P;
     my[a] = block_sum(sy[a], red) / P;
   }
-  double ss = 0.0;
+  // covariances about the means
+  double cx[6] = {0, 0, 0, 0, 0, 0}, cy[6] = {0, 0, 0, 0, 0, 0};
   for (int k = threadIdx.x; k < P; k += 256) {
-    const int64_t iy = sample_index(k, pr.M, P);
-#pragma unroll
+    double x[3], y[3];
+    xpt(k, x);
+    ypt(k, y);
     for (int a = 0; a < 3; ++a) {
-      const double d = (double)pr.Y[3 * iy + a] - my[a];
-      ss += d * d;
+      x[a] -= mx[a];
+      y[a] -= my[a];
+    }
+    int o = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j, ++o) {
+        cx[o] += x[i] * x[j];
+        cy[o] += y[i] * y[j];
+      }
+  }
+  for (int o = 0; o < 6; ++o) {
+    cx[o] = block_sum(cx[o], red) / P;
+    cy[o] = block_sum(cy[o], red) / P;
+  }
+  double s = sqrt(cy[0] + cy[3] + cy[5]);
+  if (!(s > 0.0)) s = 1.0;  // the target's samples are one point
+  double FX[9], FY[9];
+  eigen_frame(cx, FX);
+  eigen_frame(cy, FY);
+  // third moments along e0 and e1 of each cloud
+  double m3[4] = {0, 0, 0, 0};
+  for (int k = threadIdx.x; k < P; k += 256) {
+    double x[3], y[3];
+    xpt(k, x);
+    ypt(k, y);
+    for (int c = 0; c < 2; ++c) {
+      double u = 0.0, w = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        u += (x[a] - mx[a]) * FX[3 * a + c];
+        w += (y[a] - my[a]) * FY[3 * a + c];
+      }
+      m3[c] += u * u * u;
+      m3[2 + c] += w * w * w;
     }
   }
-  double s = sqrt(block_sum(ss, red) / P);
-  if (!(s > 0.0)) s = 1.0;  // a cloud of one repeated point
+  for (int c = 0; c < 4; ++c) m3[c] = block_sum(m3[c], red);
+  sign_frame(FX, m3);
+  sign_frame(FY, m3 + 2);
   float *xo = Xn + (size_t)b * P * 3, *yo = Yn + (size_t)b * P * 3;
   for (int k = threadIdx.x; k < P; k += 256) {
-    const int64_t ix = sample_index(k, pr.N, P), iy = sample_index(k, pr.M, P);
-    const double x0 = pr.X[3 * ix], x1 = pr.X[3 * ix + 1], x2 = pr.X[3 * ix + 2];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      xo[3 * k + a] = (float)((q[3 * a] * x0 + q[3 * a + 1] * x1 + q[3 * a + 2] * x2 - mx[a]) / s);
-      yo[3 * k + a] = (float)(((double)pr.Y[3 * iy + a] - my[a]) / s);
+    double x[3], y[3];
+    xpt(k, x);
+    ypt(k, y);
+    for (int c = 0; c < 3; ++c) {
+      double u = 0.0, w = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        u += (x[a] - mx[a]) * FX[3 * a + c];
+        w += (y[a] - my[a]) * FY[3 * a + c];
+      }
+      xo[3 * k + c] = (float)(u / s);
+      yo[3 * k + c] = (float)(w / s);
     }
   }
   if (threadIdx.x == 0) {
+    double *nm = norm + kPropNorm * b;
     for (int a = 0; a < 3; ++a) {
-      norm[7 * b + a] = mx[a];
-      norm[7 * b + 3 + a] = my[a];
+      nm[a] = mx[a];
+      nm[3 + a] = my[a];
     }
-    norm[7 * b + 6] = s;
+    nm[6] = s;
+    for (int i = 0; i < 9; ++i) {
+      nm[7 + i] = FX[i];
+      nm[16 + i] = FY[i];
+    }
   }
 }
 
@@ -168,7 +257,6 @@ __global__ __launch_bounds__(256) void prop_encode(const float *__restrict__ th,
                                                    const float *__restrict__ Xn,
                                                    const float *__restrict__ Yn, int P,
                                                    const int *__restrict__ idx,
-                                                   const double *__restrict__ Q,
                                                    unsigned long long *__restrict__ pool) {
   const int cloud = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -176,7 +264,7 @@ __global__ __launch_bounds__(256) void prop_encode(const float *__restrict__ th,
   const int p0 = blockIdx.x * kChunk + wave * 16;
   const int pa = p0 + lr;
   float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-  if (pa < P) load_point(Xn, Yn, P, idx, Q, cloud, pa, x0, x1, x2);
+  if (pa < P) load_point(Xn, Yn, P, idx, cloud, pa, x0, x1, x2);
   const float *W2T = wt, *W3T = wt + 64 * 128;
   __shared__ float h2s[4][16][129];
   __shared__ unsigned long long best[4][256];
@@ -279,12 +367,6 @@ __device__ void gram_schmidt(const double *a1, const double *a2, double *b1, dou
   b3[2] = b1[0] * b2[1] - b1[1] * b2[0];
 }
 
-__device__ __forceinline__ void cross3(const double *a, const double *b, double *o) {
-  o[0] = a[1] * b[2] - a[2] * b[1];
-  o[1] = a[2] * b[0] - a[0] * b[2];
-  o[2] = a[0] * b[1] - a[1] * b[0];
-}
-
 // Inference: pose[b] = (R row-major, t) in world units.
 __global__ __launch_bounds__(128) void prop_head(const float *__restrict__ th,
                                                  const unsigned long long *__restrict__ pool,
@@ -297,16 +379,22 @@ __global__ __launch_bounds__(128) void prop_head(const float *__restrict__ th,
     double a1[3] = {os[0], os[1], os[2]}, a2[3] = {os[3], os[4], os[5]};
     double b1[3], b2[3], b3[3], n1, n2, c;
     gram_schmidt(a1, a2, b1, b2, b3, n1, n2, c);
-    const double *nm = norm + 7 * b;
+    const double *nm = norm + kPropNorm * b, *FX = nm + 7, *FY = nm + 16;
+    const double Rc[9] = {b1[0], b2[0], b3[0], b1[1], b2[1], b3[1], b1[2], b2[2], b3[2]};
+    // R = F_Y R_c F_X^T, t = mu_Y + s F_Y t^ - R mu_X
+    double T[9], R[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        T[3 * i + j] = FY[3 * i] * Rc[j] + FY[3 * i + 1] * Rc[3 + j] + FY[3 * i + 2] * Rc[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        R[3 * i + j] = T[3 * i] * FX[3 * j] + T[3 * i + 1] * FX[3 * j + 1] + T[3 * i + 2] * FX[3 * j + 2];
     double *out = pose + 12 * b;
-    for (int r = 0; r < 3; ++r) {  // R = [b1 b2 b3] (columns)
-      out[3 * r] = b1[r];
-      out[3 * r + 1] = b2[r];
-      out[3 * r + 2] = b3[r];
-    }
+    for (int i = 0; i < 9; ++i) out[i] = R[i];
     for (int r = 0; r < 3; ++r)
-      out[9 + r] = nm[3 + r] + nm[6] * (double)os[6 + r] -
-                   (out[3 * r] * nm[0] + out[3 * r + 1] * nm[1] + out[3 * r + 2] * nm[2]);
+      out[9 + r] = nm[3 + r] +
+                   nm[6] * (FY[3 * r] * os[6] + FY[3 * r + 1] * os[7] + FY[3 * r + 2] * os[8]) -
+                   (R[3 * r] * nm[0] + R[3 * r + 1] * nm[1] + R[3 * r + 2] * nm[2]);
   }
 }
 
@@ -316,64 +404,35 @@ __global__ __launch_bounds__(128) void prop_head(const float *__restrict__ th,
 // (rotated) source onto the target, in world units.
 __global__ __launch_bounds__(128) void prop_head_train(
     const float *__restrict__ th, const unsigned long long *__restrict__ pool,
-    const double *__restrict__ norm, const int *__restrict__ idx, const double *__restrict__ Q,
+    const double *__restrict__ norm, const int *__restrict__ idx,
     const double *__restrict__ label, int B, double *__restrict__ loss, float *__restrict__ zo, float *__restrict__ h4o,
     float *__restrict__ goo, float *__restrict__ ga4o, float *__restrict__ gzo) {
   const int b = blockIdx.x, t = threadIdx.x;
   __shared__ float zs[512], h4s[128], os[9], gos[9], ga4s[128];
   head_forward(th, pool, b, zs, h4s, os);
   if (t == 0) {
-    double a1[3] = {os[0], os[1], os[2]}, a2[3] = {os[3], os[4], os[5]};
-    double b1[3], b2[3], b3[3], n1, n2, c;
-    gram_schmidt(a1, a2, b1, b2, b3, n1, n2, c);
-    const double *nm = norm + 7 * (idx ? idx[b] : b), *lb = label + 12 * b;
-    // the rotated source's mean
-    double mx[3] = {nm[0], nm[1], nm[2]};
-    if (Q)
-      for (int r = 0; r < 3; ++r)
-        mx[r] = Q[9 * b + 3 * r] * nm[0] + Q[9 * b + 3 * r + 1] * nm[1] + Q[9 * b + 3 * r + 2] * nm[2];
-    // normalised label: R_l, t_l = (R_l mu_X + t - mu_Y) / s
-    double tl[3];
+    const double *nm = norm + kPropNorm * (idx ? idx[b] : b), *lb = label + 12 * b;
+    const double *FX = nm + 7, *FY = nm + 16;
+    // label in the frames: R_l = F_Y^T R F_X, t_l = F_Y^T (R mu_X + t - mu_Y) / s
+    double T[9], Rl[9], tl[3], d[3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        T[3 * i + j] = FY[i] * lb[j] + FY[3 + i] * lb[3 + j] + FY[6 + i] * lb[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        Rl[3 * i + j] = T[3 * i] * FX[j] + T[3 * i + 1] * FX[3 + j] + T[3 * i + 2] * FX[6 + j];
     for (int r = 0; r < 3; ++r)
-      tl[r] = (lb[3 * r] * mx[0] + lb[3 * r + 1] * mx[1] + lb[3 * r + 2] * mx[2] + lb[9 + r] - nm[3 + r]) /
-              nm[6];
-    const double *cols[3] = {b1, b2, b3};
-    double L = 0.0, g[3][3];  // g[col][row] = dL/dR[row][col]
-    for (int col = 0; col < 3; ++col)
-      for (int r = 0; r < 3; ++r) {
-        const double d = cols[col][r] - lb[3 * r + col];
-        L += d * d;
-        g[col][r] = 2.0 * d / B;
-      }
-    double gt[3];
-    for (int r = 0; r < 3; ++r) {
-      const double d = (double)os[6 + r] - tl[r];
-      L += d * d;
-      gt[r] = 2.0 * d / B;
+      d[r] = lb[3 * r] * nm[0] + lb[3 * r + 1] * nm[1] + lb[3 * r + 2] * nm[2] + lb[9 + r] - nm[3 + r];
+    for (int i = 0; i < 3; ++i) tl[i] = (FY[i] * d[0] + FY[3 + i] * d[1] + FY[6 + i] * d[2]) / nm[6];
+    // least squares on the outputs: R_l's first two columns, then t_l
+    const double tgt[9] = {Rl[0], Rl[3], Rl[6], Rl[1], Rl[4], Rl[7], tl[0], tl[1], tl[2]};
+    double L = 0.0;
+    for (int q = 0; q < 9; ++q) {
+      const double e = (double)os[q] - tgt[q];
+      L += e * e;
+      gos[q] = (float)(2.0 * e / B);
     }
     loss[b] = L;
-    // Gram-Schmidt backward
-    double gb1[3], gb2[3], x[3];
-    cross3(b2, g[2], x);
-    for (int i = 0; i < 3; ++i) gb1[i] = g[0][i] + x[i];
-    cross3(g[2], b1, x);
-    for (int i = 0; i < 3; ++i) gb2[i] = g[1][i] + x[i];
-    const double gb2b2 = gb2[0] * b2[0] + gb2[1] * b2[1] + gb2[2] * b2[2];
-    double gu[3];
-    for (int i = 0; i < 3; ++i) gu[i] = (gb2[i] - gb2b2 * b2[i]) / n2;
-    const double gub1 = gu[0] * b1[0] + gu[1] * b1[1] + gu[2] * b1[2];
-    double ga2[3], ga1[3];
-    for (int i = 0; i < 3; ++i) {
-      ga2[i] = gu[i] - gub1 * b1[i];
-      gb1[i] = gb1[i] - gub1 * a2[i] - c * gu[i];
-    }
-    const double gb1b1 = gb1[0] * b1[0] + gb1[1] * b1[1] + gb1[2] * b1[2];
-    for (int i = 0; i < 3; ++i) ga1[i] = (gb1[i] - gb1b1 * b1[i]) / n1;
-    for (int i = 0; i < 3; ++i) {
-      gos[i] = (float)ga1[i];
-      gos[3 + i] = (float)ga2[i];
-      gos[6 + i] = (float)gt[i];
-    }
   }
   __syncthreads();
   {
@@ -403,8 +462,8 @@ __global__ __launch_bounds__(128) void prop_head_train(
 // points (in point order), so the result is deterministic.
 __global__ __launch_bounds__(256) void prop_encode_back(
     const float *__restrict__ th, const float *__restrict__ Xn, const float *__restrict__ Yn, int P,
-    const int *__restrict__ idx, const double *__restrict__ Q,
-    const unsigned long long *__restrict__ pool, const float *__restrict__ gz,
+    const int *__restrict__ idx, const unsigned long long *__restrict__ pool,
+    const float *__restrict__ gz,
     float *__restrict__ part) {
   const int cloud = blockIdx.x, k = threadIdx.x;
   float *gp = part + (size_t)cloud * kEncParams;
@@ -468,7 +527,7 @@ __global__ __launch_bounds__(256) void prop_encode_back(
     __syncthreads();
     if (k < kBackPts) {
       float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-      if (k < nd) load_point(Xn, Yn, P, idx, Q, cloud, dpt[k], x0, x1, x2);
+      if (k < nd) load_point(Xn, Yn, P, idx, cloud, dpt[k], x0, x1, x2);
       XP[k][0] = x0;
       XP[k][1] = x1;
       XP[k][2] = x2;
@@ -626,14 +685,14 @@ PropWs prop_ws(void *ws, int npairs, int train) {
 }
 
 void encode_launch(const float *theta, const PropWs &w, int npairs, int P, const float *Xn,
-                   const float *Yn, const int *idx, const double *Q, hipStream_t st) {
+                   const float *Yn, const int *idx, hipStream_t st) {
   const int n = 256 * 128;
   const int npool = 2 * npairs * 256;
   const int m = n > npool ? n : npool;
   hipLaunchKernelGGL(prop_prepare, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, theta, w.wt,
                      w.pool, npool);
   hipLaunchKernelGGL(prop_encode, dim3((unsigned)((P + kChunk - 1) / kChunk), (unsigned)(2 * npairs)),
-                     dim3(256), 0, st, theta, w.wt, Xn, Yn, P, idx, Q, w.pool);
+                     dim3(256), 0, st, theta, w.wt, Xn, Yn, P, idx, w.pool);
 }
 }  // namespace
 
@@ -647,21 +706,21 @@ hipError_t launch_prop_forward(const float *theta, int npairs, int P, const floa
                                const float *Yn, const double *norm, double *pose, void *ws,
                                hipStream_t st) {
   const PropWs w = prop_ws(ws, npairs, 0);
-  encode_launch(theta, w, npairs, P, Xn, Yn, nullptr, nullptr, st);
+  encode_launch(theta, w, npairs, P, Xn, Yn, nullptr, st);
   hipLaunchKernelGGL(prop_head, dim3((unsigned)npairs), dim3(128), 0, st, theta, w.pool, norm, pose);
   return hipGetLastError();
 }
 
 hipError_t launch_prop_train(float *theta, float *m, float *v, int step, double lr, int npairs,
                              int P, const float *Xn, const float *Yn, const double *norm,
-                             const int *idx, const double *Q, const double *label, double *loss,
-                             int *argmax, float *grad_out, void *ws, hipStream_t st) {
+                             const int *idx, const double *label, double *loss, int *argmax,
+                             float *grad_out, void *ws, hipStream_t st) {
   const PropWs w = prop_ws(ws, npairs, 1);
-  encode_launch(theta, w, npairs, P, Xn, Yn, idx, Q, st);
+  encode_launch(theta, w, npairs, P, Xn, Yn, idx, st);
   hipLaunchKernelGGL(prop_head_train, dim3((unsigned)npairs), dim3(128), 0, st, theta, w.pool, norm,
-                     idx, Q, label, npairs, loss, w.z, w.h4, w.go, w.ga4, w.gz);
+                     idx, label, npairs, loss, w.z, w.h4, w.go, w.ga4, w.gz);
   hipLaunchKernelGGL(prop_encode_back, dim3((unsigned)(2 * npairs)), dim3(256), 0, st, theta, Xn, Yn,
-                     P, idx, Q, w.pool, w.gz, w.part);
+                     P, idx, w.pool, w.gz, w.part);
   hipLaunchKernelGGL(prop_grad_sum, dim3((unsigned)((kNP + 255) / 256)), dim3(256), 0, st, w.part,
                      2 * npairs, w.z, w.h4, w.go, w.ga4, npairs, grad_out ? grad_out : w.grad);
   if (argmax)

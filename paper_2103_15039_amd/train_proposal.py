@@ -1,15 +1,15 @@
 """Trains the learned initial-pose proposal (lsgcpd_proposal_*) and writes its
 parameters.
 
-The training pairs are registered by LSG-CPD itself: each base pair (a scene
-of 2-3 primitives sampled twice, source rotated uniformly on SO(3), noise and
-outliers) is registered from its ground-truth pose by the batched library
-call, and that solution is the pair's label.  Every training example is a
-base pair whose source is rotated once more by a fresh uniform rotation Q;
-its label is the base label composed with Q^-1, exactly (registering Q x
-gives the pose of x composed with Q^-1), so `--rotations` examples come from
-each LSG-CPD solve.  All arithmetic runs in the library's kernels; this
-script draws the random batches and keeps the loop.
+The training pairs are registered by LSG-CPD itself: each pair (a scene of
+2-3 primitives sampled twice, the source rotated uniformly on SO(3), noise
+and outliers) is registered from its ground-truth pose by the batched
+library call, and that solution is the pair's label.  The encoder's inputs
+are each cloud in its own principal-axis frame, which does not change when a
+cloud is rotated, so every pair is one training example (rotating it again
+would give the same example).  The pairs are drawn in worker processes (host
+only) and the arithmetic runs in the library's kernels; this script keeps
+the loop.
 
   python -m paper_2103_15039_amd.train_proposal --out proposal_theta.npy
 
@@ -30,17 +30,6 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
-
-
-def uniform_rotations(rng, n):
-    """n rotations uniform on SO(3) (unit quaternions of four normals)."""
-    q = rng.normal(size=(n, 4))
-    q /= np.linalg.norm(q, axis=1, keepdims=True)
-    w, x, y, z = q.T
-    return np.stack([
-        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
-        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
-        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
 
 
 def init_theta(rng):
@@ -94,12 +83,32 @@ def inputs(L, torch, pairs, P, chunk=1024):
     return torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous(), torch.cat(Ns).contiguous()
 
 
+def _gen(args):
+    """Proposal pairs of one chunk (worker process: host arrays only)."""
+    import datagen
+    n, trial, nmin, nmax = args
+    return [(p.X, p.Y, p.R_gt, p.t_gt) for p in
+            datagen.proposal_pairs(n, split="train", trial=trial, nmin=nmin, nmax=nmax)]
+
+
+def make_pairs(n, seed, nmin, nmax, workers, chunk=1000):
+    """n training pairs, chunk i drawn with trial seed * 100000 + i."""
+    from types import SimpleNamespace
+    jobs = [(min(chunk, n - i0), seed * 100000 + i0 // chunk, nmin, nmax)
+            for i0 in range(0, n, chunk)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            parts = pool.map(_gen, jobs)
+    else:
+        parts = [_gen(j) for j in jobs]
+    return [SimpleNamespace(X=X, Y=Y, R_gt=R, t_gt=t) for part in parts for X, Y, R, t in part]
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--base", type=int, default=6250, help="base pairs registered for labels")
-    ap.add_argument("--rotations", type=int, default=32,
-                    help="training examples per base pair and pass (base x rotations = pairs)")
-    ap.add_argument("--passes", type=float, default=4.0)
+    ap.add_argument("--pairs", type=int, default=50000, help="training pairs (one LSG-CPD solve each)")
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--points", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -107,55 +116,56 @@ def main(argv=None):
     ap.add_argument("--nmin", type=int, default=1000)
     ap.add_argument("--nmax", type=int, default=4000)
     ap.add_argument("--holdout", type=int, default=512)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--log", type=int, default=500)
+    ap.add_argument("--log", type=int, default=1000)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
+    t0 = time.time()
+    pairs = make_pairs(a.pairs, a.seed, a.nmin, a.nmax, a.workers)
+    hold = make_pairs(a.holdout, a.seed + 1, a.nmin, a.nmax, 1)
+    print(json.dumps({"stage": "pairs", "pairs": len(pairs), "s": round(time.time() - t0, 1)}),
+          flush=True)
     import torch
-    import datagen
     import paper_2103_15039_amd as L
 
-    t0 = time.time()
-    pairs = datagen.proposal_pairs(a.base, split="train", trial=a.seed, nmin=a.nmin, nmax=a.nmax)
     Rl, tl = label_pairs(L, torch, pairs, a.label_iters)
     drift = angle_deg(np.stack([p.R_gt for p in pairs]), Rl)
-    print(json.dumps({"stage": "labels", "pairs": len(pairs), "s": round(time.time() - t0, 1),
+    print(json.dumps({"stage": "labels", "s": round(time.time() - t0, 1),
                       "label_vs_truth_deg_median": float(np.median(drift)),
                       "label_vs_truth_deg_max": float(drift.max())}), flush=True)
     Xn, Yn, norm = inputs(L, torch, pairs, a.points)
-    hold = datagen.proposal_pairs(a.holdout, split="train", trial=1000 + a.seed, nmin=a.nmin,
-                                  nmax=a.nmax)
     hX, hY, hN = inputs(L, torch, hold, a.points)
     hR = np.stack([p.R_gt for p in hold])
+    labels = np.concatenate([Rl.reshape(-1, 9), tl], axis=1)
+    del pairs
 
     rng = np.random.default_rng([2103, 15039, a.seed])
     theta = torch.from_numpy(init_theta(rng)).cuda()
     m, v = torch.zeros_like(theta), torch.zeros_like(theta)
-    steps = int(math.ceil(a.passes * a.base * a.rotations / a.batch))
+    n = len(labels)
     hist = []
     t1 = time.time()
-    for step in range(1, steps + 1):
-        idx = rng.integers(0, a.base, a.batch).astype(np.int32)
-        Q = uniform_rotations(rng, a.batch)
-        lab = np.concatenate([(Rl[idx] @ np.transpose(Q, (0, 2, 1))).reshape(a.batch, 9),
-                              tl[idx]], axis=1)
-        lr = a.lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / steps)))
-        loss, _, _ = L.proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, lab, index=idx,
-                                           Q=Q)
+    for step in range(1, a.steps + 1):
+        idx = rng.integers(0, n, a.batch).astype(np.int32)
+        lr = a.lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / a.steps)))
+        loss, _, _ = L.proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, labels[idx],
+                                           index=idx)
         hist.append(float(loss.mean()))
-        if step % a.log == 0 or step == steps:
+        if step % a.log == 0 or step == a.steps:
             pose = L.proposal_forward(theta, hX, hY, hN).cpu().numpy()
             err = angle_deg(hR, pose[:, :9].reshape(-1, 3, 3))
-            print(json.dumps({"step": step, "of": steps, "lr": lr,
+            print(json.dumps({"step": step, "of": a.steps, "lr": lr,
                               "loss": float(np.mean(hist[-a.log:])),
                               "holdout_rot_err_deg_median": float(np.median(err)),
                               "holdout_within_30deg": float(np.mean(err < 30)),
                               "holdout_within_60deg": float(np.mean(err < 60)),
                               "s": round(time.time() - t1, 1)}), flush=True)
     np.save(a.out, theta.cpu().numpy())
-    print(json.dumps({"stage": "done", "out": a.out, "steps": steps,
-                      "pairs_seen": steps * a.batch, "s": round(time.time() - t0, 1)}), flush=True)
+    print(json.dumps({"stage": "done", "out": a.out, "steps": a.steps,
+                      "examples_seen": a.steps * a.batch, "s": round(time.time() - t0, 1)}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -5,14 +5,18 @@ mathematics fixes, on the CPU:
     positive scale of a1 and to adding a multiple of a1 to a2;
   * the forward pass against an independent float64 implementation written
     with torch's own layers (nn.functional.linear, relu, amax);
-  * every gradient of the batch loss against central finite differences;
+  * every gradient of the batch loss against central finite differences,
+    and the loss as least squares on the 6-D outputs (a half-turn label
+    still pulls);
   * Adam: the first update is -lr * g / (|g| + eps) in closed form, and a
     second one against the published recurrences evaluated by hand;
   * normalisation and the pose mapping: a round trip through normalised
-    units returns the pose, the sampled indices are evenly spaced.
+    units returns the pose, the sampled indices are evenly spaced, and the
+    principal-axis frames are the eigenvectors of the covariance in the
+    stated order and signs, rotating with the points.
 A plausible mistake anywhere (a transposed weight, the source and target
-features swapped, a missing ReLU mask, a wrong sign in the Gram-Schmidt
-gradient, an unbiased Adam) fails one of these.
+features swapped, a missing ReLU mask, a target column taken as a row, an
+unbiased Adam) fails one of these.
 """
 import numpy as np
 import pytest
@@ -116,18 +120,26 @@ def test_gradients_against_finite_differences():
     assert checked > 80
 
 
-def test_gram_schmidt_gradient_against_finite_differences():
+def test_loss_is_least_squares_on_the_6d_outputs():
+    """The loss is 0 exactly when the outputs are the label's first two
+    columns and translation, and a half-turn label still has a gradient."""
     rng = np.random.default_rng(5)
-    for _ in range(5):
-        a1, a2, dR = rng.normal(size=3), rng.normal(size=3), rng.normal(size=(3, 3))
-        g1, g2 = PR.gram_schmidt_backward(a1, a2, dR)
-        for k in range(3):
-            e = np.zeros(3)
-            e[k] = 1e-6
-            f1 = (np.sum(dR * PR.gram_schmidt(a1 + e, a2)) - np.sum(dR * PR.gram_schmidt(a1 - e, a2))) / 2e-6
-            f2 = (np.sum(dR * PR.gram_schmidt(a1, a2 + e)) - np.sum(dR * PR.gram_schmidt(a1, a2 - e))) / 2e-6
-            assert g1[k] == pytest.approx(f1, rel=1e-6, abs=1e-9)
-            assert g2[k] == pytest.approx(f2, rel=1e-6, abs=1e-9)
+    theta, X, Y, R_l, t_l = _small_problem(11, B=1)
+    pp = PR.forward_pair(PR.unpack(theta), X[0], Y[0])
+    R = datagen.random_rotation(rng, 2.0)
+    assert PR.pair_loss(pp, R, t_l[0]) == pytest.approx(
+        np.sum((pp.o[:3] - R[:, 0]) ** 2) + np.sum((pp.o[3:6] - R[:, 1]) ** 2)
+        + np.sum((pp.o[6:] - t_l[0]) ** 2))
+    # outputs equal to the target: zero loss
+    R0 = PR.gram_schmidt(pp.o[:3], pp.o[3:6])
+    n1 = np.linalg.norm(pp.o[:3])
+    if abs(n1 - 1.0) < 1e-12 and abs(R0[:, 1] @ pp.o[3:6] - 1.0) < 1e-12:
+        assert PR.pair_loss(pp, R0, pp.o[6:]) == pytest.approx(0.0, abs=1e-20)
+    # the prediction's own rotation turned by a half turn about its first
+    # axis: the second output vector is still pulled towards the label
+    flip = R0 @ np.diag([1.0, -1.0, -1.0])
+    _, g, _ = PR.batch_loss_and_grad(theta, X, Y, flip[None], t_l)
+    assert np.abs(PR.unpack(g)["b5"][3:6]).max() > 0.1
 
 
 def test_inactive_channels_have_no_gradient():
@@ -164,9 +176,10 @@ def test_sampling_and_normalisation_round_trip():
     assert list(PR.sample_indices(10, 5)) == [1, 3, 5, 7, 9]
     assert list(PR.sample_indices(3, 6)) == [0, 0, 1, 1, 2, 2]
     assert list(PR.sample_indices(7, 7)) == list(range(7))
-    # one sample: no spread, unit scale, both inputs at the origin
-    xs1, ys1, (_, _, s1) = PR.normalise(np.ones((5, 3)), np.arange(12.0).reshape(4, 3), 1)
+    # one sample: no spread, unit scale and frame, both inputs at the origin
+    xs1, ys1, (_, _, s1, FX1, FY1) = PR.normalise(np.ones((5, 3)), np.arange(12.0).reshape(4, 3), 1)
     assert s1 == 1.0 and not xs1.any() and not ys1.any()
+    assert np.array_equal(FX1, np.eye(3)) and np.array_equal(FY1, np.eye(3))
     rng = np.random.default_rng(8)
     p = datagen.range_scanner_pair(trial=2, M=900, N=700)
     Q = datagen.random_rotation(rng, 2.0)
@@ -175,11 +188,35 @@ def test_sampling_and_normalisation_round_trip():
     assert np.mean(np.sum(ys ** 2, axis=1)) == pytest.approx(1.0)
     # the pose mapping x' = Q x onto y: R_gt Q^T, t_gt
     R = p.R_gt @ Q.T
-    Rn, tn = PR.label_normalised(R, p.t_gt, norm)
-    R2, t2 = PR.pose_from_prediction(Rn, tn, norm)
+    Rc, tc = PR.label_normalised(R, p.t_gt, norm)
+    R2, t2 = PR.pose_from_prediction(Rc, tc, norm)
     assert np.allclose(R2, R) and np.allclose(t2, p.t_gt, atol=1e-12)
-    # in normalised units the label maps the normalised source onto the
-    # normalised image of the same points
+    # in these units the label maps the source's inputs onto the inputs of
+    # the image of the same points
+    mx, my, s, FX, FY = norm
     raw = np.asarray(p.X, np.float64)[PR.sample_indices(700, 256)] @ Q.T
-    img = ((raw @ R.T + p.t_gt) - norm[1]) / norm[2]
-    np.testing.assert_allclose(xs @ Rn.T + tn, img, atol=1e-12)
+    img = (((raw @ R.T + p.t_gt) - my) @ FY) / s
+    np.testing.assert_allclose(xs @ Rc.T + tc, img, atol=1e-12)
+
+
+def test_principal_frame():
+    """Eigenvectors of the covariance in decreasing order of eigenvalue,
+    right-handed, third moments along e0, e1 non-negative; rotating the
+    points rotates the frame and leaves the inputs unchanged."""
+    rng = np.random.default_rng(9)
+    c = rng.normal(size=(300, 3)) * [3.0, 1.5, 0.5] + rng.exponential(size=(300, 3)) * 0.3
+    c -= c.mean(0)
+    F = PR.principal_frame(c)
+    assert np.allclose(F.T @ F, np.eye(3), atol=1e-12) and np.linalg.det(F) == pytest.approx(1.0)
+    C = c.T @ c / len(c)
+    lam = np.diag(F.T @ C @ F)
+    assert np.all(np.diff(lam) < 0)
+    np.testing.assert_allclose(F.T @ C @ F, np.diag(lam), atol=1e-12 * lam[0])
+    assert np.sum((c @ F[:, 0]) ** 3) >= 0 and np.sum((c @ F[:, 1]) ** 3) >= 0
+    Q = datagen.random_rotation(rng, 2.5)
+    np.testing.assert_allclose(PR.principal_frame(c @ Q.T), Q @ F, atol=1e-10)
+    p = datagen.range_scanner_pair(trial=3, M=800, N=600)
+    xs, ys, _ = PR.normalise(p.X, p.Y, 200)
+    xq, yq, _ = PR.normalise(p.X, p.Y, 200, Q)
+    np.testing.assert_allclose(xq, xs, atol=1e-10)
+    np.testing.assert_allclose(yq, ys, atol=0)
