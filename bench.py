@@ -478,21 +478,24 @@ def cpu_report():
 PROPOSAL_THETA = os.path.join(ROOT, "paper_2103_15039_amd", "proposal_theta.npy")
 
 
-def proposal_main(a, npairs=1024, nsub=64, P=512, accept=0.05):
+def proposal_main(a, npairs=1024, nsub=64, P=512, accepts=(0.1, 0.05)):
     """The learned initial pose (the benchmark spec's M2): 1,024 held-out scene pairs
     (2-3 primitives, M and N log-uniform in [1,000, 30,000], source rotation
     uniform on SO(3)).  Timed, in registrations per second and with the
     success rate (rotation error < 1 deg against the truth):
       * proposed: lsgcpd_register_proposed -- the encoder's poses for all
         pairs, EM from each in one batch, and for the pairs whose final sigma
-        exceeds `accept` times the target's RMS radius, EM from the 24
-        rotations of the cube in one batch (lowest NLL wins);
+        exceeds `accept` times the target's RMS radius, EM from the 4 sign
+        changes of the principal axes, then the other 20 cube rotations
+        (lowest NLL wins); at accept = 0.1 (value: on held-out pairs 0.5 % of
+        the correct registrations end above it) and at 0.05 (nearly every
+        pair takes the fallback: the most thorough setting);
       * plain: lsgcpd_register one pair at a time from the identity (all
         pairs);
       * plain, 24 starts: lsgcpd_register one pair at a time from each of the
-        24 cube rotations (centroids aligned), lowest NLL kept -- the plain
-        single-pair path at the proposal's success rate; timed on the first
-        `nsub` pairs (its rate per pair is what is reported).
+        24 cube rotations (centroids aligned), lowest NLL kept -- the
+        the benchmark spec's multi-start judge; timed on the first `nsub` pairs (its
+        rate per pair is what is reported).
     EM: k = 10, 50 iterations at most, stopping when the relative NLL change
     falls below 1e-6, for every path."""
     import numpy as np
@@ -504,13 +507,23 @@ def proposal_main(a, npairs=1024, nsub=64, P=512, accept=0.05):
     pairs = datagen.proposal_pairs(npairs, split="eval", trial=0)
     dev = [(torch.from_numpy(p.X).cuda(), torch.from_numpy(p.Y).cuda()) for p in pairs]
     kw = dict(k=10, alpha_max=30.0, lam=0.2, w0=0.1, max_iter=EM_ITERS, tol=1e-6)
+
+    def ok(rs, ps):
+        return np.array([rot_err_deg(r.R, p.R_gt) < 1.0 for r, p in zip(rs, ps)])
     torch.cuda.synchronize()
-    L.register_proposed(dev[:8], theta, P=P, accept=accept, **kw)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res, fb = L.register_proposed(dev, theta, P=P, accept=accept, **kw)
-    torch.cuda.synchronize()
-    dt_prop = time.perf_counter() - t0
+    L.register_proposed(dev[:8], theta, P=P, accept=accepts[0], **kw)   # warm-up
+    runs = {}
+    for acc in accepts:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, fb = L.register_proposed(dev, theta, P=P, accept=acc, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        succ = ok(res, pairs)
+        runs[acc] = {"pairs_per_s": npairs / dt, "s": dt, "success_rate": float(succ.mean()),
+                     "successful_pairs_per_s": float(succ.mean()) * npairs / dt,
+                     "fallback_rate": float(np.mean(fb)),
+                     "success_on_the_24_start_subset": float(succ[:nsub].mean())}
     # the encoder alone: its poses and their error
     Xn, Yn, nm = L.proposal_inputs(dev, P)
     torch.cuda.synchronize()
@@ -521,10 +534,6 @@ def proposal_main(a, npairs=1024, nsub=64, P=512, accept=0.05):
     pose = pose.cpu().numpy()
     prop_err = np.array([rot_err_deg(pose[i, :9].reshape(3, 3), p.R_gt)
                          for i, p in enumerate(pairs)])
-
-    def ok(rs, ps):
-        return np.array([rot_err_deg(r.R, p.R_gt) < 1.0 for r, p in zip(rs, ps)])
-    succ_prop = ok(res, pairs)
     t2 = time.perf_counter()
     plain = [L.register(X, Y, **kw) for X, Y in dev]
     torch.cuda.synchronize()
@@ -541,34 +550,37 @@ def proposal_main(a, npairs=1024, nsub=64, P=512, accept=0.05):
     torch.cuda.synchronize()
     dt_multi = time.perf_counter() - t3
     succ_multi = ok(best, pairs[:nsub])
-    rate_prop = npairs / dt_prop
     rate_multi = nsub / dt_multi
+    main_run = runs[accepts[0]]
     out = {
         "metric": "pairs registered/s at rotation error < 1 deg",
-        "value": float(succ_prop.mean()) * rate_prop,
+        "value": main_run["successful_pairs_per_s"],
         "unit": "successful pairs/s",
         "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": dt_prop * 1e3,
+        "ms_per_step": main_run["s"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "proposal1024", "pairs": npairs,
                    "points": "1000-30000 log-uniform", "rotation": "uniform on SO(3)",
-                   "encoder_points": P, "accept_sigma_over_radius": accept,
+                   "encoder_points": P, "accept_sigma_over_radius": accepts[0],
                    "em_max_iters": EM_ITERS, "em_tol": 1e-6, "knn": 10},
-        "proposed": {"pairs_per_s": rate_prop, "success_rate": float(succ_prop.mean()),
-                     "fallback_rate": float(np.mean(fb)),
-                     "encoder_ms_all_pairs": dt_fwd * 1e3,
-                     "proposal_rot_err_deg_median": float(np.median(prop_err)),
-                     "proposal_within_30deg": float(np.mean(prop_err < 30)),
-                     "proposal_within_60deg": float(np.mean(prop_err < 60))},
+        "proposed": {f"accept_{acc}": r for acc, r in runs.items()},
+        "encoder": {"ms_all_pairs": dt_fwd * 1e3,
+                    "rot_err_deg_median": float(np.median(prop_err)),
+                    "within_30deg": float(np.mean(prop_err < 30)),
+                    "within_60deg": float(np.mean(prop_err < 60))},
         "plain_identity": {"pairs_per_s": npairs / dt_plain,
                            "success_rate": float(succ_plain.mean()),
                            "successful_pairs_per_s": float(succ_plain.mean()) * npairs / dt_plain},
         "plain_24_starts": {"pairs_per_s": rate_multi, "success_rate": float(succ_multi.mean()),
                             "pairs_timed": nsub,
                             "successful_pairs_per_s": float(succ_multi.mean()) * rate_multi},
-        "proposed_over_plain_24_starts": rate_prop / rate_multi,
-        "proposed_success_on_the_24_start_subset": float(succ_prop[:nsub].mean()),
+        "proposed_over_plain_24_starts": {
+            f"accept_{acc}": {"pairs_per_s": r["pairs_per_s"] / rate_multi,
+                              "successful_pairs_per_s":
+                                  r["successful_pairs_per_s"] / max(succ_multi.mean() * rate_multi,
+                                                                    1e-30)}
+            for acc, r in runs.items()},
     }
     print(json.dumps(out), flush=True)
 

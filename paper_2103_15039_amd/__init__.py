@@ -593,7 +593,7 @@ def proposal_train_step(theta, m, v, step, lr, Xn, Yn, norm, label, index=None,
     return loss, am, g
 
 
-def register_proposed(pairs, theta, P=512, accept=0.05, k=10, alpha_max=30.0, lam=0.2, w0=0.1,
+def register_proposed(pairs, theta, P=512, accept=0.1, k=10, alpha_max=30.0, lam=0.2, w0=0.1,
                       V=0.0, max_iter=50, tol=0.0, sigma2_init=0.0, newton_max=20, exact=False,
                       eta=None):
     """Registers every (X, Y) of `pairs` from the learned proposal's pose,
