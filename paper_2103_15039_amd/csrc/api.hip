@@ -511,8 +511,8 @@ lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Ba
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_estep_plan(pl, bd, mem.boxes, mem.state, mem.plan, st));
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_pairs(pl, bd, mem.rec, mem.pts, mem.ftab, mem.state, mem.plan,
-                                 mem.partial, st));
+  HIPCHK(lsg::launch_estep_pairs(pl, bd, mem.rec, mem.pts, mem.boxes, mem.ftab, mem.state,
+                                 mem.plan, mem.partial, st));
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_finalize(pl, bd, mem.state, mem.plan, mem.partial, mem.blockstats, colS,
                               colstats, st));

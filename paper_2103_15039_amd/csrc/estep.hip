@@ -37,8 +37,8 @@
 //    instructions of a SIMD do not execute concurrently and the FP64 matrix
 //    rate equals the FP64 vector rate, so this is kept only for comparison.
 // Work items (scalar) or target chunks (LDS, MFMA) give enough blocks for
-// small N; their partial sums are combined in a fixed order by estep_finalize,
-// so results are bitwise reproducible.
+// small N; their partial sums are combined in a fixed order by the
+// finalisation (mstep.hip), so results are bitwise reproducible.
 #include <math.h>
 #include <string.h>
 
@@ -52,10 +52,6 @@ constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kTwoPi = 6.283185307179586477;
 constexpr int kBlock = 256;
 constexpr int kTile = 64;            // targets per LDS tile (LDS back end)
-
-__device__ __forceinline__ double gamma_of(const DevState *s) {
-  return pow(kTwoPi * s->sigma2, 1.5) / s->V;
-}
 
 // sqrt(c) with c = log2(e) / (2 sigma^2)
 __device__ __forceinline__ double sqrt_c_of(const DevState *s) {
@@ -167,9 +163,9 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 //  * cull_groups (one block per group) takes the group's bounding box in
 //    scaled coordinates and lists, in increasing order, the tiles that
 //    box_live cannot rule out (with culling off: every tile);
-//  * cull_items (one block) cuts every group's list into items of L tiles,
-//    with L chosen so that there are at most about `target` items in all, and
-//    writes the item -> group map;
+//  * cull_items (one block per problem) cuts every group's list into items
+//    of L tiles, with L chosen so that there are at most about `target` items
+//    in all, and writes the item -> group map;
 //  * estep_pairs_items runs one block per item: the 4 waves hold the same 128
 //    sources and take every 4th tile of the item.  Per tile, one lane per
 //    target tests the target against the group box, and the wave walks the
@@ -183,7 +179,7 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 // 2 sources per lane measured faster than 4 (tighter group boxes, twice the
 // groups to balance, more waves per SIMD) and than 1 on both benchmark pairs
 constexpr int kSrcPerLane = 2;
-constexpr int kGroup = 64 * kSrcPerLane;
+static_assert(kGroup == 64 * kSrcPerLane, "a group is the two sources of each lane of a wave");
 // the per-half culling (two half boxes per group, slot s of a lane = half s)
 // is written for exactly two sources per lane
 static_assert(kSrcPerLane == 2, "per-half culling assumes two sources per lane");
@@ -200,6 +196,55 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kF3Feat = 16;  // features 0 (the constant 1), 1..10, 11..15 zero
 constexpr double kF3Kappa = 3.0 / 65536.0 + 64.0 / 16777216.0;
 constexpr double kF3MaxDz = 1.0 / 32.0;
+
+// Block order of one problem's work items: block i runs on XCD i mod 8
+// (blocks are handed to the XCDs in turn), so each XCD gets a contiguous run
+// of items -- neighbouring source groups, whose target tiles its own L2 then
+// holds.  When every group has the same number c of items (no tile dropped,
+// as in the dense first E steps, where each group streams all target
+// records), the run is further taken chunk-major: segments of S groups (S c
+// about one XCD's run), and within a segment every group's first item, then
+// every group's second, ..., so that the blocks resident on an XCD at one
+// time read the same target tiles.  A bijection on the item numbers: only the
+// order of execution changes, not any sum.
+__device__ __forceinline__ int item_order(int i, int nitems, int c) {
+  const int x = i % 8, q = nitems / 8, r = nitems % 8;
+  int t = x * q + (x < r ? x : r) + i / 8;
+  if (c > 1) {
+    const int ng = nitems / c;
+    int S = q / c;
+    S = S < 1 ? 1 : S;
+    const int seg = t / (S * c), g0 = seg * S;
+    const int Ss = ng - g0 < S ? ng - g0 : S;
+    const int k = t - seg * S * c;
+    t = (g0 + k % Ss) * c + k / Ss;
+  }
+  return t;
+}
+
+// Whether the BF16 matrix-core kernel takes a work item (group box gbox, its
+// tiles tl[0 .. kn) among the problem's tile boxes bx): its exponent error
+// bound must hold for every pair within scaled distance 2 of either half of
+// the group, kF3Kappa (1 + A) (2 h + 2)^2 <= kF3MaxDz, with h the larger
+// scaled half-diagonal of the two halves' boxes and A the largest alpha of
+// the item's tiles (the `pad` of their boxes).  Evaluated per wave; both pair
+// kernels take the same decision from the same data.
+__device__ bool item_is_f3(const double *gbox, const TBox *bx, const int *tl, int kn) {
+  double h = 0.0;
+  for (int half = 0; half < 2; ++half) {
+    const double *hb = gbox + 6 * half;
+    if (hb[0] <= hb[3]) {  // a half without sources has an empty box
+      const double e0 = hb[3] - hb[0], e1 = hb[4] - hb[1], e2 = hb[5] - hb[2];
+      h = fmax(h, 0.5 * sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+    }
+  }
+  double a = 0.0;
+  for (int q = threadIdx.x & 63; q < kn; q += 64) a = fmax(a, bx[tl[q]].pad);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, 64));
+  const double r = 2.0 * h + 2.0;
+  return kF3Kappa * (1.0 + a) * r * r <= kF3MaxDz;
+}
 
 // Scaled-coordinate bounding box of each source group (kept for the pair
 // kernel), then the live tiles in increasing order.  One block per group of
@@ -281,24 +326,23 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
 
 // Items of one problem (one block per problem): L tiles each (L a multiple
 // of 4, at least 4), about `target` in all.  Without culling every group
-// lists all tiles.  Also clears the problem's counter of evaluated pairs.
+// lists all tiles.  Also clears the problem's counters of evaluated pairs
+// (evcounts[p], and evcounts[npairs + p] for the BF16 matrix-core kernel).
 // Offsets: group g of problem p has its items at off[g_off + p + g] ..
 // off[g_off + p + g + 1] - 1 (local to the problem's item range).
 template <bool CULL>
 __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ slots,
-                                                     DevState *__restrict__ states,
+                                                     const DevState *__restrict__ states,
                                                      const int *__restrict__ counts,
-                                                     const double *__restrict__ gboxes,
-                                                     const TBox *__restrict__ boxes, int f3,
                                                      CullHdr *__restrict__ hdrs,
                                                      int *__restrict__ offs,
                                                      int *__restrict__ maps,
                                                      unsigned long long *__restrict__ evcounts) {
-  const int p = blockIdx.x;
+  const int p = blockIdx.x, npairs = gridDim.x;
   if (states[p].done) return;
   const Slot &sl = slots[p];
   const int ngroups = sl.ngroups, ntiles = sl.ntiles, target = sl.target, cap = sl.item_cap;
-  const int *cnts = counts + sl.g_off;
+  const int *cnts = CULL ? counts + sl.g_off : nullptr;
   int *off = offs + sl.g_off + p;
   int *map = maps + sl.item_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -318,10 +362,15 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
   int64_t L = (tiles + target - 1) / target;
   L = L < 4 ? 4 : (L + 3) / 4 * 4;
   int run = 0;
+  int vmin = 0x7fffffff, vmax = 0;  // items per group
   for (int g0 = 0; g0 < ngroups; g0 += kBlock) {
     const int g = g0 + threadIdx.x;
     const int64_t cnt = g < ngroups ? (CULL ? cnts[g] : ntiles) : 0;
     const int v = (int)((cnt + L - 1) / L);
+    if (g < ngroups) {
+      vmin = v < vmin ? v : vmin;
+      vmax = v > vmax ? v : vmax;
+    }
     scan[threadIdx.x] = v;
     __syncthreads();
     for (int d = 1; d < kBlock; d <<= 1) {  // inclusive Hillis-Steele scan
@@ -338,45 +387,29 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
     run += scan[kBlock - 1];
     __syncthreads();
   }
-  // the BF16 matrix-core kernel runs this E step if its exponent error bound
-  // holds for every source half: largest scaled half-diagonal h of the
-  // halves' boxes, largest alpha of the targets
-  int use_f3 = 0;
-  if (CULL && f3) {
-    double hm = 0.0, am = 0.0;
-    const double *gb = gboxes + (int64_t)sl.g_off * kGBox;
-    for (int g = threadIdx.x; g < 2 * ngroups; g += kBlock) {
-      const double *hb = gb + (int64_t)(g >> 1) * kGBox + 6 * (g & 1);
-      if (hb[0] <= hb[3]) {  // a half without sources has an empty box
-        const double e0 = hb[3] - hb[0], e1 = hb[4] - hb[1], e2 = hb[5] - hb[2];
-        hm = fmax(hm, 0.5 * sqrt(e0 * e0 + e1 * e1 + e2 * e2));
-      }
-    }
-    const TBox *tb = boxes + sl.t_off;
-    for (int t = threadIdx.x; t < ntiles; t += kBlock) am = fmax(am, tb[t].pad);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      hm = fmax(hm, __shfl_xor(hm, o, 64));
-      am = fmax(am, __shfl_xor(am, o, 64));
-    }
-    __shared__ double mx[2][4];
-    if (lane == 0) {
-      mx[0][wave] = hm;
-      mx[1][wave] = am;
-    }
-    __syncthreads();
-    hm = fmax(fmax(mx[0][0], mx[0][1]), fmax(mx[0][2], mx[0][3]));
-    am = fmax(fmax(mx[1][0], mx[1][1]), fmax(mx[1][2], mx[1][3]));
-    const double r = 2.0 * hm + 2.0;
-    use_f3 = kF3Kappa * (1.0 + am) * r * r <= kF3MaxDz ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int a = __shfl_xor(vmin, o, 64), b = __shfl_xor(vmax, o, 64);
+    vmin = a < vmin ? a : vmin;
+    vmax = b > vmax ? b : vmax;
   }
+  __shared__ int mm[2][4];
+  if (lane == 0) {
+    mm[0][wave] = vmin;
+    mm[1][wave] = vmax;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      vmin = mm[0][w] < vmin ? mm[0][w] : vmin;
+      vmax = mm[1][w] > vmax ? mm[1][w] : vmax;
+    }
     off[ngroups] = run;
     hdrs[p].items = run < cap ? run : cap;
     hdrs[p].tiles_per_item = (int)L;
-    hdrs[p].f3 = use_f3;
-    evcounts[p] = 0ull;
-    if (use_f3) states[p].f3_steps += 1;
+    hdrs[p].uniform = vmin == vmax && run <= cap ? vmax : 0;
+    evcounts[p] = 0ull;           // pairs evaluated
+    evcounts[npairs + p] = 0ull;  // of which by the BF16 matrix-core kernel
   }
 }
 
@@ -388,23 +421,17 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
     const TPt *__restrict__ ptss, const CullHdr *__restrict__ hdrs,
     const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
     const int *__restrict__ list, const double *__restrict__ gboxes,
+    const TBox *__restrict__ boxes, int f3,
     unsigned long long *__restrict__ evcounts, double *__restrict__ partial, int xcd_remap) {
   constexpr int S = kSrcPerLane;
   const int p = item_slot[blockIdx.x];
   const DevState *st = states + p;
   if (st->done) return;
-  if (CULL && hdrs[p].f3) return;  // the BF16 matrix-core kernel runs this E step
   const Slot &sl = slots[p];
   const int nitems = hdrs[p].items;
   int item = blockIdx.x - sl.item_off;
   if (item >= nitems) return;
-  if (xcd_remap) {
-    // one problem: blocks go to the 8 XCDs in turn, so block i runs on XCD
-    // i % 8; give each XCD a contiguous run of items (neighbouring sources
-    // and targets, whose records its own L2 then holds) instead of every 8th
-    const int x = item % 8, q = nitems / 8, r = nitems % 8;
-    item = x * q + (x < r ? x : r) + item / 8;
-  }
+  if (xcd_remap) item = item_order(item, nitems, hdrs[p].uniform);
   const int b = sl.item_off + item;
   // the wave index is wave-uniform; readfirstlane tells the compiler so, which
   // keeps the tile loop (and so the record loads) scalar
@@ -422,6 +449,8 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   const int kn = cnt - k0 < L ? cnt - k0 : L;
   const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
   const double *gbox = gboxes + (int64_t)(sl.g_off + g) * kGBox;
+  // an item the BF16 matrix-core kernel takes
+  if (CULL && f3 && item_is_f3(gbox, boxes + sl.t_off, tl, kn)) return;
   double R[9], t[3];
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
@@ -549,12 +578,14 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
 // Error: each product carries about 3 * 2^-16 of its own size, and the
 // terms cancel for nearby pairs, so |dz| <= kF3Kappa (1 + alpha_m)
 // (|u| + |v|)^2 up to the FP32 sums; the centre is the box centre of the
-// wave's 64 sources (|u| <= h, its scaled half-diagonal).  cull_items runs
-// this kernel for an E step only if kF3Kappa (1 + alpha_max) (2 h + 2)^2 <=
-// kF3MaxDz for every source half, i.e. the bound holds for every pair within
-// scaled distance 2 (e at least 2^-4 of its largest possible value) -- the
-// early, large-sigma^2 iterations.  Same items, partial layout and
-// finalisation as the FP64 kernel; not a parity path (errors ~1e-4 in z).
+// wave's 64 sources (|u| <= h, its scaled half-diagonal).  A work item runs
+// here (item_is_f3) only if kF3Kappa (1 + alpha_max) (2 h + 2)^2 <= kF3MaxDz
+// for both source halves of its group and the largest alpha of its tiles,
+// i.e. the bound holds for every pair within scaled distance 2 (e at least
+// 2^-4 of its largest possible value) -- the early, large-sigma^2
+// iterations; the FP64 kernel takes the other items.  Same items, partial
+// layout and finalisation as the FP64 kernel; not a parity path (errors
+// ~1e-4 in z).
 
 __device__ __forceinline__ void split_bf16(double v, __bf16 &hi, __bf16 &lo) {
   const float f = (float)v;
@@ -631,18 +662,16 @@ __global__ __launch_bounds__(kBlock, 2) void estep_pairs_f3(
     const __bf16 *__restrict__ ftabs, const CullHdr *__restrict__ hdrs,
     const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
     const int *__restrict__ list, const double *__restrict__ gboxes,
-    unsigned long long *__restrict__ evcounts, double *__restrict__ partial, int xcd_remap) {
+    const TBox *__restrict__ boxes, unsigned long long *__restrict__ evcounts,
+    unsigned long long *__restrict__ f3counts, double *__restrict__ partial, int xcd_remap) {
   const int p = item_slot[blockIdx.x];
   const DevState *st = states + p;
-  if (st->done || !hdrs[p].f3) return;
+  if (st->done) return;
   const Slot &sl = slots[p];
   const int nitems = hdrs[p].items;
   int item = blockIdx.x - sl.item_off;
   if (item >= nitems) return;
-  if (xcd_remap) {
-    const int x = item % 8, q = nitems / 8, r = nitems % 8;
-    item = x * q + (x < r ? x : r) + item / 8;
-  }
+  if (xcd_remap) item = item_order(item, nitems, hdrs[p].uniform);
   const int b = sl.item_off + item;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -657,6 +686,7 @@ __global__ __launch_bounds__(kBlock, 2) void estep_pairs_f3(
   const int cnt = counts[sl.g_off + g];
   const int kn = cnt - k0 < L ? cnt - k0 : L;
   const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
+  if (!item_is_f3(gboxes + (int64_t)(sl.g_off + g) * kGBox, boxes + sl.t_off, tl, kn)) return;
   const double *hb = gboxes + (int64_t)(sl.g_off + g) * kGBox + 6 * half;
   const int rest = N - g * kGroup - half * 64;
   const int nv = rest < 0 ? 0 : rest < 64 ? rest : 64;  // sources of this half
@@ -816,8 +846,10 @@ __global__ __launch_bounds__(kBlock, 2) void estep_pairs_f3(
 #pragma unroll
       for (int i = 0; i < 4; ++i) dst[16 * sb + 4 * lq + i] = tot[sb][i] + red[half][sb][i][lane];
   }
-  if (lane == 0 && nv > 0 && done > 0)
+  if (lane == 0 && nv > 0 && done > 0) {
     atomicAdd(evcounts + p, (unsigned long long)nv * (unsigned long long)done);
+    atomicAdd(f3counts + p, (unsigned long long)nv * (unsigned long long)done);
+  }
 }
 
 // LDS back end: the block stages tiles of target records in LDS and every
@@ -927,154 +959,6 @@ __global__ __launch_bounds__(kBlock) void estep_mfma(const float *__restrict__ X
   }
 }
 
-// ------------------------------------------------------------- finalisation
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-constexpr int kFinBlock = 64;
-
-// ITEMS: partials per work item ([item][feature][kGroup]; the items of
-// source group g of problem p are its items off[g_off + p + g] ..
-// off[g_off + p + g + 1] - 1), summed by 4 waves per block (wave q takes items
-// q, q + 4, ...; the 4 sums are added in a fixed order); otherwise per target
-// chunk ([chunk][feature][N], one problem), one wave per block.  Block b
-// belongs to problem fin_slot[b]; its statistics go to the problem's
-// stat-major rows.
-template <bool ITEMS>
-__global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
-    const Slot *__restrict__ slots, const int *__restrict__ fin_slot,
-    const DevState *__restrict__ states, const double *__restrict__ partial, int nsplit,
-    const int *__restrict__ offs, double *__restrict__ blockstats, double *__restrict__ colS,
-    double *__restrict__ colstats) {
-  const int ps = fin_slot[blockIdx.x];
-  const DevState *st = states + ps;
-  if (st->done) return;
-  const Slot &sl = slots[ps];
-  const int N = sl.N;
-  const float *X = sl.X;
-  const float *w = sl.w;
-  const float *phi = sl.phi;
-  const int fb = blockIdx.x - sl.fin_off;
-  const int l = threadIdx.x & (kFinBlock - 1);
-  const int part = threadIdx.x / kFinBlock;  // 0 without ITEMS
-  const int n = fb * kFinBlock + l;
-  double p = 0.0, W[6] = {0, 0, 0, 0, 0, 0}, B[3] = {0, 0, 0}, C = 0.0, lg = 0.0, outl = 0.0,
-         logw = 0.0;
-  double xt[4] = {0.0, 0.0, 0.0, 0.0};
-  double T[kFeatUsed];
-#pragma unroll
-  for (int c = 0; c < kFeatUsed; ++c) T[c] = 0.0;
-  if (ITEMS) {
-    if (n < N) {
-      // this wave's items in increasing order, the loads of 4 issued together
-      const int g = n / kGroup, j = n % kGroup;
-      const int *off = offs + sl.g_off + ps;
-      const int i1 = sl.item_off + off[g + 1];
-      int it = sl.item_off + off[g] + part;
-      for (; it + 12 < i1; it += 16) {
-        double v[4][kFeatUsed];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int c = 0; c < kFeatUsed; ++c)
-            v[u][c] = partial[((size_t)(it + 4 * u) * kFeatUsed + c) * kGroup + j];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int c = 0; c < kFeatUsed; ++c) T[c] += v[u][c];
-      }
-      for (; it < i1; it += 4)
-#pragma unroll
-        for (int c = 0; c < kFeatUsed; ++c)
-          T[c] += partial[((size_t)it * kFeatUsed + c) * kGroup + j];
-    }
-    __shared__ double tr[3][kFeatUsed][kFinBlock];
-    if (part > 0)
-#pragma unroll
-      for (int c = 0; c < kFeatUsed; ++c) tr[part - 1][c][l] = T[c];
-    __syncthreads();
-    if (part == 0)
-#pragma unroll
-      for (int c = 0; c < kFeatUsed; ++c) T[c] = ((T[c] + tr[0][c][l]) + tr[1][c][l]) + tr[2][c][l];
-  } else if (n < N) {
-    for (int sp = 0; sp < nsplit; ++sp)
-#pragma unroll
-      for (int c = 0; c < kFeatUsed; ++c) T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
-  }
-  if (part == 0 && n < N) {
-    // Sec. 3.3: w_n = 1 - (1 - w0) phi(x_n) under confidence filtering
-    const double wn = w ? (double)w[n] : phi ? 1.0 - (1.0 - st->w0) * (double)phi[n] : st->w0;
-    const double rho = (1.0 - wn) / wn;
-    const double gam = gamma_of(st);
-    const double den = rho * T[0];
-    const double inv = 1.0 / (den + gam);
-    const double sc = rho * inv;
-    p = den * inv;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) W[i] = sc * T[1 + i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) B[i] = sc * T[7 + i];
-    C = sc * T[10];
-    lg = log(den + gam);
-    outl = gam * inv;
-    logw = log(wn);
-    if (colS) colS[sl.x_off + n] = T[0];
-    if (colstats) {
-      double *cs = colstats + (size_t)(sl.x_off + n) * kColStats;
-      cs[0] = T[0];
-      cs[1] = den;
-      cs[2] = p;
-      for (int i = 0; i < 6; ++i) cs[3 + i] = W[i];
-      for (int i = 0; i < 3; ++i) cs[9 + i] = B[i];
-      cs[12] = C;
-      cs[13] = lg;
-      cs[14] = outl;
-      cs[15] = 0.0;
-    }
-    xt[0] = (double)X[3 * n];
-    xt[1] = (double)X[3 * n + 1];
-    xt[2] = (double)X[3 * n + 2];
-    xt[3] = 1.0;
-  }
-  double xx[10];
-  {
-    int o = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = i; j < 4; ++j) xx[o++] = xt[i] * xt[j];
-  }
-  // statistic i of this source (layout documented with the public header),
-  // written to LDS and summed over the block's sources in a fixed order
-  __shared__ double red[kStats][kFinBlock + 1];
-  if (part == 0) {
-#pragma unroll
-    for (int i = 0; i < 10; ++i) red[i][l] = p * xx[i];
-#pragma unroll
-    for (int ab = 0; ab < 6; ++ab)
-#pragma unroll
-      for (int i = 0; i < 10; ++i) red[10 + 10 * ab + i][l] = W[ab] * xx[i];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) red[70 + 4 * a + j][l] = B[a] * xt[j];
-    red[82][l] = C;
-    red[83][l] = lg;
-    red[84][l] = outl;
-    red[85][l] = logw;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kStats; i += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < kFinBlock; ++k) s += red[i][k];
-    blockstats[(size_t)kStats * sl.fin_off + (size_t)i * sl.nfin + fb] = s;  // stat-major
-  }
-}
-
-// Test aid: writes P (M x N, float32) from the same per-pair exponent.
 __global__ void dump_P(const float *__restrict__ X, int N, const TRec *__restrict__ rec,
                        int64_t M, const float *__restrict__ w, const DevState *__restrict__ st,
                        const double *__restrict__ colS, float *__restrict__ P) {
@@ -1375,8 +1259,8 @@ size_t estep_partial_bytes(const BatchPlan &pl) {
   return (size_t)pl.nsplit * kFeatUsed * (size_t)pl.slots[0].N * sizeof(double);
 }
 
-// Work-item plan layout: CullHdr[npairs], evaluated-pair counters[npairs],
-// counts[groups], off[groups + npairs], map[items], gbox[groups][8],
+// Work-item plan layout: CullHdr[npairs], evaluated-pair counters[2 npairs],
+// counts[groups], off[groups + npairs], map[items], gbox[groups][kGBox],
 // list[list_ints].
 namespace {
 struct PlanPtrs {
@@ -1391,7 +1275,7 @@ PlanPtrs plan_ptrs(const BatchPlan &pl, void *ws) {
   q.hdr = (CullHdr *)p;
   p += align256((size_t)pl.npairs * sizeof(CullHdr));
   q.evcount = (unsigned long long *)p;
-  p += align256((size_t)pl.npairs * sizeof(unsigned long long));
+  p += align256((size_t)2 * pl.npairs * sizeof(unsigned long long));
   q.counts = (int *)p;
   p += align256((size_t)pl.groups * sizeof(int));
   q.off = (int *)p;
@@ -1405,10 +1289,14 @@ PlanPtrs plan_ptrs(const BatchPlan &pl, void *ws) {
 }
 }  // namespace
 
+const int *estep_plan_offsets(const BatchPlan &pl, const void *plan_ws) {
+  return pl.backend == kBackendScalar ? plan_ptrs(pl, (void *)plan_ws).off : nullptr;
+}
+
 size_t estep_plan_bytes(const BatchPlan &pl) {
   if (pl.backend != kBackendScalar) return 256;
   return align256((size_t)pl.npairs * sizeof(CullHdr)) +
-         align256((size_t)pl.npairs * sizeof(unsigned long long)) +
+         align256((size_t)2 * pl.npairs * sizeof(unsigned long long)) +
          align256((size_t)pl.groups * sizeof(int)) +
          align256((size_t)(pl.groups + pl.npairs) * sizeof(int)) +
          align256((size_t)pl.items * sizeof(int)) +
@@ -1427,32 +1315,33 @@ hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox
     hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.groups), dim3(kBlock), 0, st, bd.slots,
                        bd.grp_slot, s, boxes, q.counts, q.gbox, q.list);
     hipLaunchKernelGGL(cull_items<true>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st, bd.slots,
-                       s, q.counts, q.gbox, boxes, pl.f3, q.hdr, q.off, q.map, q.evcount);
+                       s, q.counts, q.hdr, q.off, q.map, q.evcount);
   } else {
     hipLaunchKernelGGL(cull_items<false>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st,
-                       bd.slots, s, q.counts, q.gbox, boxes, 0, q.hdr, q.off, q.map, q.evcount);
+                       bd.slots, s, q.counts, q.hdr, q.off, q.map, q.evcount);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRec *rec,
-                              const TPt *pts, const void *ftab, DevState *s, void *plan_ws,
-                              double *partial, hipStream_t st) {
+                              const TPt *pts, const TBox *boxes, const void *ftab, DevState *s,
+                              void *plan_ws, double *partial, hipStream_t st) {
   if (pl.backend == kBackendScalar) {
     const PlanPtrs q = plan_ptrs(pl, plan_ws);
     if (pl.cull) {
+      const int f3 = pl.f3 ? 1 : 0;
       hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                          bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
-                         q.list, q.gbox, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
-      if (pl.f3)
+                         q.list, q.gbox, boxes, f3, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
+      if (f3)
         hipLaunchKernelGGL(estep_pairs_f3, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                            bd.slots, bd.item_slot, s, rec, (const __bf16 *)ftab, q.hdr, q.counts,
-                           q.off, q.map, q.list, q.gbox, q.evcount, partial,
-                           pl.npairs == 1 ? 1 : 0);
+                           q.off, q.map, q.list, q.gbox, boxes, q.evcount, q.evcount + pl.npairs,
+                           partial, pl.npairs == 1 ? 1 : 0);
     } else
       hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
                          bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
-                         q.list, q.gbox, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
+                         q.list, q.gbox, boxes, 0, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
     return hipGetLastError();
   }
   // one problem: its records start at rec + 0
@@ -1464,21 +1353,6 @@ hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRe
   else
     hipLaunchKernelGGL(estep_pairs_lds<kPairS>, grid, dim3(kBlock), 0, st, sl.X, sl.N, rec,
                        (int64_t)sl.M, s, pl.mchunk, pl.nsplit, partial);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
-                           const void *plan_ws, const double *partial, double *blockstats,
-                           double *colS, double *colstats, hipStream_t st) {
-  if (pl.backend == kBackendScalar)
-    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.fins), dim3(4 * kFinBlock), 0, st,
-                       bd.slots, bd.fin_slot, s, partial, 0,
-                       (const int *)plan_ptrs(pl, (void *)plan_ws).off, blockstats, colS,
-                       colstats);
-  else
-    hipLaunchKernelGGL(estep_finalize<false>, dim3((unsigned)pl.fins), dim3(kFinBlock), 0, st,
-                       bd.slots, bd.fin_slot, s, partial, pl.nsplit, (const int *)nullptr,
-                       blockstats, colS, colstats);
   return hipGetLastError();
 }
 

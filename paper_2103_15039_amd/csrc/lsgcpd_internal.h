@@ -42,6 +42,8 @@ struct TPt {
 constexpr int kFeatUsed = 11;   // feature 0 (= 1) and f[0..9]
 constexpr int kStats = 86;
 constexpr int kColStats = 16;
+constexpr int kGroup = 128;     // sources per group of the scalar pair kernel
+constexpr int kFinBlock = 64;   // sources per finalisation block
 
 // Device-resident EM state.  Written by the set-up kernels and the M-step
 // kernel, read by every E-step kernel, so that an EM iteration needs no host
@@ -79,9 +81,15 @@ struct DevState {
   int32_t numeric_error;
   int32_t newton_max;
   int32_t max_iter;
-  int32_t f3_steps;   // E steps that ran the BF16 matrix-core pair kernel
+  int32_t f3_steps;   // E steps in which the BF16 matrix-core kernel took items
   int32_t pad;
 };
+
+// gamma = (2 pi sigma^2)^{3/2} / V: the outlier term of the posterior's
+// denominator relative to the component normaliser (Eq. 9)
+__device__ inline double gamma_of(const DevState *s) {
+  return pow(6.283185307179586477 * s->sigma2, 1.5) / s->V;
+}
 
 // Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations (FP64).
 // On return a holds the eigenvalues on its diagonal and v the eigenvectors as
@@ -236,7 +244,7 @@ struct BatchDev {
 struct CullHdr {
   int items;           // work items of the problem
   int tiles_per_item;
-  int f3;              // 1: this E step runs the BF16 matrix-core pair kernel
+  int uniform;         // items per group if every group has as many, else 0
   int pad;
 };
 
@@ -255,19 +263,24 @@ size_t estep_partial_bytes(const BatchPlan &pl);
 // evaluated pairs inside it (scalar back end; null otherwise).
 size_t estep_plan_bytes(const BatchPlan &pl);
 unsigned long long *estep_plan_counter(const BatchPlan &pl, void *plan_ws);
+// Item offsets per source group inside the plan workspace (scalar back end;
+// null otherwise): the finalisation finds each source's item partials there.
+const int *estep_plan_offsets(const BatchPlan &pl, const void *plan_ws);
 
 // The work-item plan of the scalar back end (no-op for the others), then the
 // pair kernel, then the per-source finalisation into stat-major block rows
 // (problem p: rows at kStats * fin_off, nfin per row).
-// With pl.f3 the plan decides per E step and problem whether the BF16
-// matrix-core pair kernel runs (its exponent error bound holds at the
-// current sigma^2 and source groups) or the FP64 one; both are launched and
-// the one not chosen returns at once.  ftab: the tables of launch_prep_targets.
+// With pl.f3 each work item runs on the BF16 matrix-core pair kernel if its
+// exponent error bound holds at the current sigma^2 for the item's source
+// group and tiles, else on the FP64 one; both kernels are launched and each
+// skips the other's items.  ftab and boxes: as launch_prep_targets wrote
+// them.  The counters (estep_plan_counter) hold, per problem, the pairs
+// evaluated and then, at npairs + p, those of the BF16 kernel.
 hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox *boxes,
                              DevState *s, void *plan_ws, hipStream_t st);
 hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRec *rec,
-                              const TPt *pts, const void *ftab, DevState *s, void *plan_ws,
-                              double *partial, hipStream_t st);
+                              const TPt *pts, const TBox *boxes, const void *ftab, DevState *s,
+                              void *plan_ws, double *partial, hipStream_t st);
 hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
                            const void *plan_ws, const double *partial, double *blockstats,
                            double *colS, double *colstats, hipStream_t st);
@@ -278,7 +291,8 @@ hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, 
 // derive only (gradient, Hessian, next pose into the *_next fields); mode 1:
 // EM update of the state (pose, sigma2, iteration, convergence).  nll_trace:
 // null or trace_stride doubles per problem.  evcounts (may be null): pairs the
-// pair kernel evaluated, added to s[p].evaluated_pairs.
+// pair kernels evaluated, added to s[p].evaluated_pairs, and at npairs + p
+// those of the BF16 kernel (a nonzero count adds one to s[p].f3_steps).
 hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *blockstats,
                                DevState *s, double *nll_trace, int trace_stride,
                                const unsigned long long *evcounts, int mode, hipStream_t st);

@@ -13,11 +13,15 @@
 // steps are halved until D does not grow beyond a rounding allowance (the
 // change of D is evaluated as the exact difference of the quadratic).  After
 // the pose, sigma^2 = D(G_new) / (3 N_P) (Sec. 3.5, last paragraph).
-// reduce_stats sums the block statistics with one block per statistic and
-// problem; reduce_mstep runs the Newton iteration of each problem of a batch
-// in one block, whose threads share the 12 x 12 products and the entries of
-// the gradient and Hessian while thread 0 does the 6 x 6 Cholesky solve and
-// the exponential map.
+// The finalisation turns each source's summed exponentials into its
+// posterior weights (Eq. 9) and its terms of the 86 statistics, one block per
+// 64 sources; reduce_stats (one block per statistic and problem) and
+// reduce_mstep sum the block statistics in a fixed order and run the M step
+// of each problem.
+// The M step (mstep_wave) runs the Newton iteration of a problem on one
+// wave, whose lanes share the 12 x 12 products and the entries of the
+// gradient and Hessian, and each of which then takes the 6 x 6 Cholesky solve
+// and the exponential map itself.
 #include <math.h>
 
 #include "lsgcpd_internal.h"
@@ -29,17 +33,25 @@ namespace {
 constexpr double kTwoPi = 6.283185307179586477;
 
 // SE(3) exponential of the twist xi = (omega, v): Rodrigues rotation and the
-// left Jacobian of SO(3) for the translation.
-__device__ void se3_exp(const double xi[6], double Rx[3][3], double tx[3]) {
+// left Jacobian of SO(3) for the translation,
+//   A = sin(th)/th,  B = (1 - cos th)/th^2,  C = (th - sin th)/th^3.
+// For th < 1/4 (every Newton step but the first few of a registration) the
+// three are their Taylor series in th^2 to the th^10 term; the first omitted
+// term is below 1e-17 of each, under half an FP64 ulp.
+__device__ __forceinline__ void se3_exp(const double xi[6], double Rx[3][3], double tx[3]) {
   const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
   const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
-  const double th = sqrt(th2);
   double A, B, C;
-  if (th < 1e-6) {
-    A = 1.0 - th2 / 6.0;
-    B = 0.5 - th2 / 24.0;
-    C = 1.0 / 6.0 - th2 / 120.0;
+  if (th2 < 0.0625) {
+    // sum_k (-th^2)^k / (2k+1)!, / (2k+2)!, / (2k+3)!  for k = 0..5
+    A = 1.0 + th2 * (-1.0 / 6 + th2 * (1.0 / 120 + th2 * (-1.0 / 5040 + th2 * (1.0 / 362880 +
+        th2 * (-1.0 / 39916800)))));
+    B = 0.5 + th2 * (-1.0 / 24 + th2 * (1.0 / 720 + th2 * (-1.0 / 40320 + th2 * (1.0 / 3628800 +
+        th2 * (-1.0 / 479001600)))));
+    C = 1.0 / 6 + th2 * (-1.0 / 120 + th2 * (1.0 / 5040 + th2 * (-1.0 / 362880 +
+        th2 * (1.0 / 39916800 + th2 * (-1.0 / 6227020800.0)))));
   } else {
+    const double th = sqrt(th2);
     double sn, cs;
     sincos(th, &sn, &cs);
     const double it = 1.0 / th, it2 = it * it;
@@ -66,7 +78,7 @@ __device__ void se3_exp(const double xi[6], double Rx[3][3], double tx[3]) {
 }
 
 // g_out = vec(G exp(xi^)) for g = vec(G), G = [R | t] (3 x 4 row-major)
-__device__ void compose(const double *g, const double xi[6], double *gout) {
+__device__ __forceinline__ void compose(const double *g, const double xi[6], double *gout) {
   double Rx[3][3], tx[3];
   se3_exp(xi, Rx, tx);
   for (int a = 0; a < 3; ++a) {
@@ -76,34 +88,34 @@ __device__ void compose(const double *g, const double xi[6], double *gout) {
   }
 }
 
-// Cholesky solve of the 6x6 system A x = -g; false if A is not positive
+// Cholesky solve of the 6x6 system A x = -g, factoring the lower triangle
+// of A in place (the upper one is not read); false if A is not positive
 // definite.  One reciprocal per column: the divisions are the long-latency
 // steps of this serial code.
-__device__ bool chol_solve6(const double A[6][6], const double g[6], double x[6]) {
-  double L[6][6], inv[6];
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) L[i][j] = 0.0;
+__device__ __forceinline__ bool chol_solve6(double A[6][6], const double g[6], double x[6]) {
+  double inv[6];
   for (int j = 0; j < 6; ++j) {
     double d = A[j][j];
-    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
     if (!(d > 0.0)) return false;
-    L[j][j] = sqrt(d);
-    inv[j] = 1.0 / L[j][j];
+    const double l = sqrt(d);
+    A[j][j] = l;
+    inv[j] = 1.0 / l;
     for (int i = j + 1; i < 6; ++i) {
       double s = A[i][j];
-      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-      L[i][j] = s * inv[j];
+      for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k];
+      A[i][j] = s * inv[j];
     }
   }
   double y[6];
   for (int i = 0; i < 6; ++i) {
     double s = -g[i];
-    for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+    for (int k = 0; k < i; ++k) s -= A[i][k] * y[k];
     y[i] = s * inv[i];
   }
   for (int i = 5; i >= 0; --i) {
     double s = y[i];
-    for (int k = i + 1; k < 6; ++k) s -= L[k][i] * x[k];
+    for (int k = i + 1; k < 6; ++k) s -= A[k][i] * x[k];
     x[i] = s * inv[i];
   }
   return true;
@@ -114,8 +126,17 @@ __device__ bool chol_solve6(const double A[6][6], const double g[6], double x[6]
 // source point, whose rotations about itself are free): eigen-decomposition by cyclic Jacobi rotations, then
 //   x = -sum_i (v_i . g / lambda_i) v_i  over |lambda_i| > 6 eps max|lambda|,
 // the pseudo-inverse a singular-value solve with that cutoff gives (for a
-// symmetric matrix the singular values are the |lambda_i|).  False if A is 0.
-__device__ bool pinv_solve6(const double Ain[6][6], const double g[6], double x[6]) {
+// symmetric matrix the singular values are the |lambda_i|).  ok = 0 if A is
+// 0.  Kept out of line (only degenerate inputs reach it), with the result
+// returned by value so that the caller's arrays stay in registers.
+struct Sol6 {
+  double x[6];
+  int ok;
+};
+__device__ __noinline__ Sol6 pinv_solve6(const double (*Ain)[6], const double *g) {
+  Sol6 res;
+  double *x = res.x;
+  res.ok = 0;
   double a[6][6], v[6][6];
   for (int r = 0; r < 6; ++r)
     for (int c = 0; c < 6; ++c) {
@@ -159,7 +180,7 @@ __device__ bool pinv_solve6(const double Ain[6][6], const double g[6], double x[
   }
   double mx = 0.0;
   for (int i = 0; i < 6; ++i) mx = fmax(mx, fabs(a[i][i]));
-  if (!(mx > 0.0) || !isfinite(mx)) return false;
+  if (!(mx > 0.0) || !isfinite(mx)) return res;
   const double cut = 6.0 * 2.220446049250313e-16 * mx;
   for (int i = 0; i < 6; ++i) x[i] = 0.0;
   for (int j = 0; j < 6; ++j) {
@@ -170,26 +191,20 @@ __device__ bool pinv_solve6(const double Ain[6][6], const double g[6], double x[
     const double f = -d / lam;
     for (int k = 0; k < 6; ++k) x[k] += f * v[k][j];
   }
-  return true;
+  res.ok = 1;
+  return res;
 }
 
-// Shared state of the block-parallel M step.
+// LDS of the wave-parallel M step.
 struct MSh {
   double H[12][12];   // H[4a+i][4b+j] = delta_ab S0[i][j] + S1[ab][i][j]
   double b[12];       // vec(S2)
-  double c;           // S3
   double g[12];       // vec(G), the current pose
-  double gn[12];      // trial pose
-  double J[6][12];    // vec(G E_i) of the six generators
-  double HJ[6][12];
+  double HJ[6][12];   // H vec(G E_j) of the six generators
   double Hg[12];
   double GN[6][6];
   double Q[3][3], w[3];   // R^T (H g - b), split as the second-order term uses it
   double Hs[6][6], Hgn[6][6], grad[6];
-  double xi[6];
-  double cur, val, step;
-  int go;             // 1 while Newton continues
-  int accept;
 };
 
 __device__ __forceinline__ int pair_index(int a, int b) {
@@ -204,19 +219,152 @@ __device__ __forceinline__ int tri4(int i, int j) {
   return base[lo] + hi - lo;
 }
 
-// D(vec) = v^T H v - 2 b^T v + c with the block's threads: rows in parallel.
-__device__ double block_quad(MSh &m, const double *v, double *rowbuf) {
-  const int tid = threadIdx.x;
-  if (tid < 12) {
-    double s = 0.0;
-    for (int k = 0; k < 12; ++k) s = fma(m.H[tid][k], v[k], s);
-    rowbuf[tid] = v[tid] * (s - 2.0 * m.b[tid]);
+// ------------------------------------------------------------- finalisation
+// ITEMS: partials per work item ([item][feature][kGroup]; the items of
+// source group g of problem p are its items off[g_off + p + g] ..
+// off[g_off + p + g + 1] - 1), summed by 4 waves per block (wave q takes items
+// q, q + 4, ...; the 4 sums are added in a fixed order); otherwise per target
+// chunk ([chunk][feature][N], one problem), one wave per block.  Block b
+// belongs to problem fin_slot[b]; its statistics go to the problem's
+// stat-major rows (row i of problem p: blockstats[kStats fin_off + i nfin ..]).
+template <bool ITEMS>
+__device__ void finalize_block(const Slot &sl, int ps, const DevState *__restrict__ st,
+                               const double *__restrict__ partial, int nsplit,
+                               const int *__restrict__ offs, double *__restrict__ blockstats,
+                               double *__restrict__ colS, double *__restrict__ colstats) {
+  const int N = sl.N;
+  const float *X = sl.X;
+  const float *w = sl.w;
+  const float *phi = sl.phi;
+  const int fb = blockIdx.x - sl.fin_off;
+  const int l = threadIdx.x & (kFinBlock - 1);
+  const int part = threadIdx.x / kFinBlock;  // 0 without ITEMS
+  const int n = fb * kFinBlock + l;
+  double p = 0.0, W[6] = {0, 0, 0, 0, 0, 0}, B[3] = {0, 0, 0}, C = 0.0, lg = 0.0, outl = 0.0,
+         logw = 0.0;
+  double xt[4] = {0.0, 0.0, 0.0, 0.0};
+  double T[kFeatUsed];
+#pragma unroll
+  for (int c = 0; c < kFeatUsed; ++c) T[c] = 0.0;
+  if (ITEMS) {
+    if (n < N) {
+      // this wave's items in increasing order, the loads of 4 issued together
+      const int g = n / kGroup, j = n % kGroup;
+      const int *off = offs + sl.g_off + ps;
+      const int i1 = sl.item_off + off[g + 1];
+      int it = sl.item_off + off[g] + part;
+      for (; it + 12 < i1; it += 16) {
+        double v[4][kFeatUsed];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < kFeatUsed; ++c)
+            v[u][c] = partial[((size_t)(it + 4 * u) * kFeatUsed + c) * kGroup + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < kFeatUsed; ++c) T[c] += v[u][c];
+      }
+      for (; it < i1; it += 4)
+#pragma unroll
+        for (int c = 0; c < kFeatUsed; ++c)
+          T[c] += partial[((size_t)it * kFeatUsed + c) * kGroup + j];
+    }
+    __shared__ double tr[3][kFeatUsed][kFinBlock];
+    if (part > 0)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) tr[part - 1][c][l] = T[c];
+    __syncthreads();
+    if (part == 0)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) T[c] = ((T[c] + tr[0][c][l]) + tr[1][c][l]) + tr[2][c][l];
+  } else if (n < N) {
+    for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+      for (int c = 0; c < kFeatUsed; ++c) T[c] += partial[((size_t)sp * kFeatUsed + c) * N + n];
+  }
+  if (part == 0 && n < N) {
+    // Sec. 3.3: w_n = 1 - (1 - w0) phi(x_n) under confidence filtering
+    const double wn = w ? (double)w[n] : phi ? 1.0 - (1.0 - st->w0) * (double)phi[n] : st->w0;
+    const double rho = (1.0 - wn) / wn;
+    const double gam = gamma_of(st);
+    const double den = rho * T[0];
+    const double inv = 1.0 / (den + gam);
+    const double sc = rho * inv;
+    p = den * inv;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) W[i] = sc * T[1 + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) B[i] = sc * T[7 + i];
+    C = sc * T[10];
+    lg = log(den + gam);
+    outl = gam * inv;
+    logw = log(wn);
+    if (colS) colS[sl.x_off + n] = T[0];
+    if (colstats) {
+      double *cs = colstats + (size_t)(sl.x_off + n) * kColStats;
+      cs[0] = T[0];
+      cs[1] = den;
+      cs[2] = p;
+      for (int i = 0; i < 6; ++i) cs[3 + i] = W[i];
+      for (int i = 0; i < 3; ++i) cs[9 + i] = B[i];
+      cs[12] = C;
+      cs[13] = lg;
+      cs[14] = outl;
+      cs[15] = 0.0;
+    }
+    xt[0] = (double)X[3 * n];
+    xt[1] = (double)X[3 * n + 1];
+    xt[2] = (double)X[3 * n + 2];
+    xt[3] = 1.0;
+  }
+  double xx[10];
+  {
+    int o = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i; j < 4; ++j) xx[o++] = xt[i] * xt[j];
+  }
+  // statistic i of this source (layout documented with the public header),
+  // written to LDS and summed over the block's sources in a fixed order
+  __shared__ double red[kStats][kFinBlock + 1];
+  if (part == 0) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) red[i][l] = p * xx[i];
+#pragma unroll
+    for (int ab = 0; ab < 6; ++ab)
+#pragma unroll
+      for (int i = 0; i < 10; ++i) red[10 + 10 * ab + i][l] = W[ab] * xx[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[70 + 4 * a + j][l] = B[a] * xt[j];
+    red[82][l] = C;
+    red[83][l] = lg;
+    red[84][l] = outl;
+    red[85][l] = logw;
   }
   __syncthreads();
-  double tot = m.c;
-  for (int r = 0; r < 12; ++r) tot += rowbuf[r];
-  __syncthreads();
-  return tot;
+  for (int i = threadIdx.x; i < kStats; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < kFinBlock; ++k) s += red[i][k];
+    blockstats[(size_t)kStats * sl.fin_off + (size_t)i * sl.nfin + fb] = s;  // stat-major
+  }
+}
+
+// Test aid: writes P (M x N, float32) from the same per-pair exponent.
+
+template <bool ITEMS>
+__global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
+    const Slot *__restrict__ slots, const int *__restrict__ fin_slot,
+    const DevState *__restrict__ states, const double *__restrict__ partial, int nsplit,
+    const int *__restrict__ offs, double *__restrict__ blockstats, double *__restrict__ colS,
+    double *__restrict__ colstats) {
+  const int ps = fin_slot[blockIdx.x];
+  const DevState *st = states + ps;
+  if (st->done) return;
+  finalize_block<ITEMS>(slots[ps], ps, st, partial, nsplit, offs, blockstats, colS, colstats);
 }
 
 // Problems with at most this many finalisation blocks (64 sources each) are
@@ -257,24 +405,305 @@ __global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slo
   if (tid == 0) s->stats[i] = r[0];
 }
 
-// The M step from the 86 statistics in s->stats.
+// Values of the state the M step reads, loaded before anything writes it
+// (every block of the launch loads them; the state changes only in the M
+// step itself).
+struct MIn {
+  double g[12];  // vec(G) = rows of [R | t]
+  double sigma2, V, tol, nll_prev, sigma2_floor;
+  int iter, newton_max, N;
+};
+
+__device__ __forceinline__ MIn load_min(const DevState *s, int N) {
+  MIn in;
+  for (int a = 0; a < 3; ++a) {
+    for (int c = 0; c < 3; ++c) in.g[4 * a + c] = s->R[3 * a + c];
+    in.g[4 * a + 3] = s->t[a];
+  }
+  in.sigma2 = s->sigma2;
+  in.V = s->V;
+  in.tol = s->tol;
+  in.nll_prev = s->nll_prev;
+  in.sigma2_floor = s->sigma2_floor;
+  in.iter = s->iter;
+  in.newton_max = s->newton_max;
+  in.N = N;
+  return in;
+}
+
+// Orders the LDS stores of one wave's lanes before the loads that follow
+// (the lanes of a wave execute in lockstep; this keeps the compiler from
+// moving memory operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Sum over lanes 0..15 (the others bring 0), the same value on every lane.
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+  return __shfl(v, 0, 64);
+}
+
+// v[lane] for lane < 12 (a selection, so that v stays in registers)
+__device__ __forceinline__ double pick12(const double (&v)[12], int lane) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r = lane == k ? v[k] : r;
+  return r;
+}
+
+// The M step of problem pidx (of npairs), run by the 64 lanes of one wave
+// from the 86 statistics in S (LDS, visible to the wave) and the state values
+// in `in`.  The 12 x 12 products and the gradient and Hessian entries are
+// spread over the lanes; every lane then solves the 6 x 6 system and takes
+// the exponential map itself, so that the step and the trial pose need no
+// exchange between lanes, and the change of D is a 12-lane sum.
+__device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
+                           DevState *__restrict__ states, double *__restrict__ traces,
+                           int trace_stride, const unsigned long long *__restrict__ evcounts,
+                           int mode) {
+  DevState *s = states + pidx;
+  const int lane = threadIdx.x & 63;
+  __shared__ MSh m;
+  if (evcounts && lane == 0) {
+    const unsigned long long evc = evcounts[pidx], f3c = evcounts[npairs + pidx];
+    s->evaluated_pairs += (int64_t)evc;
+    if (f3c) s->f3_steps += 1;
+  }
+  s->stats[lane] = S[lane];
+  if (lane < kStats - 64) s->stats[64 + lane] = S[64 + lane];
+  // the quadratic and the pose
+  for (int e = lane; e < 144; e += 64) {
+    const int r = e / 12, cc = e % 12;
+    const int a = r >> 2, i = r & 3, bb = cc >> 2, k = cc & 3;
+    double v = S[10 + 10 * pair_index(a, bb) + tri4(i, k)];
+    if (a == bb) v += S[tri4(i, k)];
+    m.H[r][cc] = v;
+  }
+  if (lane < 12) {
+    m.b[lane] = S[70 + lane];
+    m.g[lane] = pick12(in.g, lane);
+  }
+  wave_sync();
+  double g[12];
+#pragma unroll
+  for (int r = 0; r < 12; ++r) g[r] = in.g[r];
+  // D(g) = sum_r g_r ((H g)_r - 2 b_r) + c
+  double cur;
+  {
+    double t = 0.0;
+    if (lane < 12) {
+      double hg = 0.0;
+      for (int k = 0; k < 12; ++k) hg = fma(m.H[lane][k], g[k], hg);
+      t = pick12(g, lane) * (hg - 2.0 * m.b[lane]);
+    }
+    cur = S[82] + sum16(t);
+  }
+  const double x2 = kTwoPi * in.sigma2;
+  const double inv_s2 = 1.0 / in.sigma2;
+  const double Np = S[9];
+  const double nll = -(S[85] + S[83] - 1.5 * (double)in.N * log(x2));
+  if (lane == 0) {
+    s->gamma = x2 * sqrt(x2) / in.V;
+    s->nll = nll;
+    s->pd = cur;
+  }
+  if (mode == 1) {
+    if (lane == 0 && traces) traces[(size_t)pidx * trace_stride + in.iter] = nll;
+    if (in.tol > 0.0 && in.iter > 0 && fabs(nll - in.nll_prev) <= in.tol * fabs(nll)) {
+      if (lane == 0) {
+        s->done = 1;
+        s->converged = 1;
+      }
+      return;  // EM stopped by the tolerance
+    }
+    if (lane == 0) s->nll_prev = nll;
+  }
+  if (mode == 0 && Np <= 0.0 && lane < 42) {
+    if (lane < 36) s->hess[lane] = 0.0;
+    else s->grad[lane - 36] = 0.0;
+  }
+
+  int iters = 0, gnf = 0;
+  bool go = Np > 0.0;
+  for (int itn = 0; itn < in.newton_max && go; ++itn) {
+    ++iters;
+    // H J_i and H g.  J_i = vec(G E_i): rotation i -> [R [e_i]x | 0] (in row
+    // a: +g(a, w) at column u, -g(a, u) at column w, (u, w) = (i+1, i+2) mod
+    // 3), translation i -> [0 | R e_i] (g(a, i) at column 3)
+    for (int e = lane; e < 84; e += 64) {
+      if (e < 72) {
+        const int i = e / 12, r = e % 12;
+        double acc = 0.0;
+        if (i < 3) {
+          const int u = (i + 1) % 3, w = (i + 2) % 3;
+          for (int a = 0; a < 3; ++a)
+            acc = fma(m.H[r][4 * a + u], m.g[4 * a + w], fma(-m.H[r][4 * a + w], m.g[4 * a + u], acc));
+        } else {
+          for (int a = 0; a < 3; ++a) acc = fma(m.H[r][4 * a + 3], m.g[4 * a + i - 3], acc);
+        }
+        m.HJ[i][r] = acc;
+      } else {
+        const int r = e - 72;
+        double acc = 0.0;
+        for (int k = 0; k < 12; ++k) acc = fma(m.H[r][k], m.g[k], acc);
+        m.Hg[r] = acc;
+      }
+    }
+    wave_sync();
+    // J_i^T H J_j, and Q = R^T V[:, 0:3], w = R^T V[:, 3] with V = H g - b
+    if (lane < 36) {
+      const int i = lane / 6, j = lane % 6;
+      double acc = 0.0;
+      if (i < 3) {
+        const int u = (i + 1) % 3, w = (i + 2) % 3;
+        for (int a = 0; a < 3; ++a)
+          acc = fma(m.g[4 * a + w], m.HJ[j][4 * a + u], fma(-m.g[4 * a + u], m.HJ[j][4 * a + w], acc));
+      } else {
+        for (int a = 0; a < 3; ++a) acc = fma(m.g[4 * a + i - 3], m.HJ[j][4 * a + 3], acc);
+      }
+      m.GN[i][j] = acc;
+    } else if (lane < 48) {
+      const int e = lane - 36;
+      if (e < 9) {
+        const int l = e / 3, k = e % 3;
+        m.Q[l][k] = m.g[l] * (m.Hg[k] - m.b[k]) + m.g[4 + l] * (m.Hg[4 + k] - m.b[4 + k]) +
+                    m.g[8 + l] * (m.Hg[8 + k] - m.b[8 + k]);
+      } else {
+        const int l = e - 9;
+        m.w[l] = m.g[l] * (m.Hg[3] - m.b[3]) + m.g[4 + l] * (m.Hg[7] - m.b[7]) +
+                 m.g[8 + l] * (m.Hg[11] - m.b[11]);
+      }
+    }
+    wave_sync();
+    // gradient and symmetrised Hessian, one entry per lane.  Second-order
+    // term 2 <V, G (E_i E_j + E_j E_i)/2>: rot-rot Q_ij + Q_ji - 2 delta_ij tr Q,
+    // rot i / trans j  w . (e_i x e_j)
+    if (lane < 36) {
+      const int i = lane / 6, j = lane % 6;
+      double t2 = 0.0;
+      if (i < 3 && j < 3) {
+        const double trQ = m.Q[0][0] + m.Q[1][1] + m.Q[2][2];
+        t2 = m.Q[i][j] + m.Q[j][i] - (i == j ? 2.0 * trQ : 0.0);
+      } else if ((i < 3) != (j < 3)) {
+        const int ir = i < 3 ? i : j, jt = (i < 3 ? j : i) - 3;
+        if (ir != jt) {
+          const int k = 3 - ir - jt;
+          t2 = ((jt - ir + 3) % 3 == 1 ? 1.0 : -1.0) * m.w[k];
+        }
+      }
+      const double gn = 0.5 * (m.GN[i][j] + m.GN[j][i]);
+      const double hs = (2.0 * gn + t2) * inv_s2;
+      m.Hgn[i][j] = 2.0 * gn * inv_s2;
+      m.Hs[i][j] = hs;
+      if (itn == 0 && mode == 0) s->hess[lane] = hs;
+    } else if (lane < 42) {
+      const int i = lane - 36;
+      const double gr = i < 3 ? 2.0 * (m.Q[(i + 2) % 3][(i + 1) % 3] - m.Q[(i + 1) % 3][(i + 2) % 3]) *
+                                    inv_s2
+                              : 2.0 * m.w[i - 3] * inv_s2;
+      m.grad[i] = gr;
+      if (itn == 0 && mode == 0) s->grad[i] = gr;
+    }
+    wave_sync();
+    // the Newton step, on every lane
+    double xi[6];
+    {
+      double A[6][6], gr[6];
+      for (int i = 0; i < 6; ++i) {
+        gr[i] = m.grad[i];
+        for (int j = 0; j <= i; ++j) A[i][j] = m.Hs[i][j];
+      }
+      if (!chol_solve6(A, gr, xi)) {
+        ++gnf;
+        // least squares, as a singular Gauss-Newton matrix (degenerate
+        // inputs) can pass a Cholesky factorisation by rounding alone
+        const Sol6 r = pinv_solve6(m.Hgn, m.grad);
+        if (!r.ok) break;
+        for (int i = 0; i < 6; ++i) xi[i] = r.x[i];
+      }
+    }
+    // halve the step until D does not grow beyond a rounding allowance.  The
+    // change of D is computed as  dD = d^T (2 (H g - b) + H d),  d = g' - g,
+    // which is exact for the quadratic and free of the cancellation between
+    // the large terms of D itself
+    const double vr = lane < 12 ? 2.0 * (m.Hg[lane] - m.b[lane]) : 0.0;
+    double step = 1.0, gn[12];
+    bool accept = false;
+    for (int h = 0; h < 31; ++h) {
+      double xs[6];
+      for (int i = 0; i < 6; ++i) xs[i] = step * xi[i];
+      compose(g, xs, gn);
+      double d[12];
+#pragma unroll
+      for (int r = 0; r < 12; ++r) d[r] = gn[r] - g[r];
+      double t = 0.0;
+      if (lane < 12) {
+        double hd = 0.0;
+        for (int k = 0; k < 12; ++k) hd = fma(m.H[lane][k], d[k], hd);
+        t = pick12(d, lane) * (vr + hd);
+      }
+      const double dD = sum16(t);
+      if (dD <= 1e-12 * fabs(cur)) {
+        accept = true;
+        cur += dD;
+        break;
+      }
+      step *= 0.5;
+    }
+    if (!accept) break;
+    double mxs = 0.0;
+    for (int i = 0; i < 6; ++i) mxs = fmax(mxs, fabs(step * xi[i]));
+#pragma unroll
+    for (int r = 0; r < 12; ++r) g[r] = gn[r];
+    if (lane < 12) m.g[lane] = pick12(g, lane);
+    wave_sync();
+    if (mxs < 1e-12) go = false;
+  }
+  if (lane != 0) return;
+  const double s2n = Np > 0.0 ? fmax(cur / (3.0 * Np), in.sigma2_floor) : in.sigma2;
+  bool finite = isfinite(s2n);
+  for (int r = 0; r < 12; ++r) finite = finite && isfinite(g[r]);
+  s->newton_iters = iters;
+  s->gn_fallbacks += gnf;
+  for (int a = 0; a < 3; ++a) {
+    for (int c = 0; c < 3; ++c) s->R_next[3 * a + c] = g[4 * a + c];
+    s->t_next[a] = g[4 * a + 3];
+  }
+  s->sigma2_next = s2n;
+  if (mode == 1) {
+    if (!finite) {
+      s->numeric_error = 1;
+      s->done = 1;
+      return;
+    }
+    for (int a = 0; a < 3; ++a) {
+      for (int c = 0; c < 3; ++c) s->R[3 * a + c] = g[4 * a + c];
+      s->t[a] = g[4 * a + 3];
+    }
+    s->sigma2 = s2n;
+    s->iter += 1;
+  } else if (!finite) {
+    s->numeric_error = 1;
+  }
+}
+
+// The M step from the block statistics: summed here for problems with few
+// finalisation blocks, else by reduce_stats into s->stats.
 __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slots,
                                                     const double *__restrict__ blockstats,
                                                     DevState *__restrict__ states,
                                                     double *__restrict__ traces, int trace_stride,
                                                     const unsigned long long *__restrict__ evcounts,
                                                     int mode) {
-  const int pidx = blockIdx.x;
-  DevState *s = states + pidx;
-  const int tid = threadIdx.x;
-  // every value of the state this kernel reads, loaded together (the done
-  // flag included) before the first write to the state, which would order
-  // later loads after it: one round trip instead of a chain of them
-  const int done = s->done;
-  const int N = slots[pidx].N, nfin = slots[pidx].nfin, fin_off = slots[pidx].fin_off;
-  const double sigma2 = s->sigma2, V = s->V, tol = s->tol, nll_prev = s->nll_prev;
-  const double sigma2_floor = s->sigma2_floor;
-  const int it0 = s->iter, newton_max = s->newton_max;
+  const int pidx = blockIdx.x, tid = threadIdx.x;
+  const DevState *st = states + pidx;
+  if (st->done) return;
+  const MIn in = load_min(st, slots[pidx].N);
+  const int nfin = slots[pidx].nfin, fin_off = slots[pidx].fin_off;
   double stat = 0.0;
   if (tid < kStats) {
     if (nfin <= kFewBlocks) {
@@ -288,235 +717,14 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
         for (int k = 0; k < 8; ++k) stat += v[k];
       }
     } else {
-      stat = s->stats[tid];
+      stat = states[pidx].stats[tid];
     }
   }
-  double g0 = 0.0;
-  if (tid < 12) {
-    const int a = tid >> 2, j = tid & 3;
-    g0 = j < 3 ? s->R[3 * a + j] : s->t[a];
-  }
-  const unsigned long long evc = evcounts && tid == 0 ? evcounts[pidx] : 0ull;
-  if (done) return;
-  double *trace = traces ? traces + (size_t)pidx * trace_stride : nullptr;
-  if (evcounts && tid == 0) s->evaluated_pairs += (int64_t)evc;
   __shared__ double S[kStats];
-  __shared__ MSh m;
-  __shared__ double rowbuf[12];
-  if (tid < kStats) {
-    S[tid] = stat;
-    if (nfin <= kFewBlocks) s->stats[tid] = stat;
-  }
+  if (tid < kStats) S[tid] = stat;
   __syncthreads();
-  // the quadratic and the pose
-  for (int e = tid; e < 144; e += blockDim.x) {
-    const int r = e / 12, cc = e % 12;
-    const int a = r >> 2, i = r & 3, bb = cc >> 2, k = cc & 3;
-    double v = S[10 + 10 * pair_index(a, bb) + tri4(i, k)];
-    if (a == bb) v += S[tri4(i, k)];
-    m.H[r][cc] = v;
-  }
-  if (tid < 12) {
-    m.b[tid] = S[70 + tid];
-    m.g[tid] = g0;
-  }
-  if (tid == 0) m.c = S[82];
-  __syncthreads();
-
-  const double inv_s2 = 1.0 / sigma2;
-  const double Np = S[9];
-  const double nll = -(S[85] + S[83] - 1.5 * (double)N * log(kTwoPi * sigma2));
-  double cur = block_quad(m, m.g, rowbuf);
-  if (tid == 0) {
-    s->gamma = pow(kTwoPi * sigma2, 1.5) / V;
-    s->nll = nll;
-    s->pd = cur;
-    m.cur = cur;
-    m.go = Np > 0.0 ? 1 : 0;
-    if (mode == 1) {
-      const int it = it0;
-      if (trace) trace[it] = nll;
-      if (tol > 0.0 && it > 0 && fabs(nll - nll_prev) <= tol * fabs(nll)) {
-        s->done = 1;
-        s->converged = 1;
-        m.go = -1;
-      } else {
-        s->nll_prev = nll;
-      }
-    }
-    if (mode == 0 && Np <= 0.0) {
-      for (int i = 0; i < 6; ++i) s->grad[i] = 0.0;
-      for (int i = 0; i < 36; ++i) s->hess[i] = 0.0;
-    }
-  }
-  __syncthreads();
-  if (m.go < 0) return;  // EM stopped by the tolerance (uniform)
-
-  int iters = 0, gnf = 0;
-  for (int itn = 0; itn < newton_max && m.go == 1; ++itn) {
-    ++iters;
-    // generators J_i = vec(G E_i): rotation i -> [R [e_i]x | 0], translation i -> [0 | R e_i]
-    if (tid < 72) {
-      const int i = tid / 12, r = tid % 12, a = r >> 2, c = r & 3;
-      double v = 0.0;
-      if (i < 3) {
-        const int u = (i + 1) % 3, w = (i + 2) % 3;  // [e_i]x: (w, u) = 1, (u, w) = -1
-        if (c == u) v = m.g[4 * a + w];
-        else if (c == w) v = -m.g[4 * a + u];
-      } else if (c == 3) {
-        v = m.g[4 * a + (i - 3)];
-      }
-      m.J[i][r] = v;
-    }
-    __syncthreads();
-    if (tid < 72) {
-      const int i = tid / 12, r = tid % 12;
-      double acc = 0.0;
-      for (int k = 0; k < 12; ++k) acc = fma(m.H[r][k], m.J[i][k], acc);
-      m.HJ[i][r] = acc;
-    } else if (tid >= 96 && tid < 108) {
-      const int r = tid - 96;
-      double acc = 0.0;
-      for (int k = 0; k < 12; ++k) acc = fma(m.H[r][k], m.g[k], acc);
-      m.Hg[r] = acc;
-    }
-    __syncthreads();
-    if (tid < 36) {
-      const int i = tid / 6, j = tid % 6;
-      double acc = 0.0;
-      for (int r = 0; r < 12; ++r) acc = fma(m.J[i][r], m.HJ[j][r], acc);
-      m.GN[i][j] = acc;
-    } else if (tid >= 64 && tid < 76) {
-      // V = H g - b;  Q = R^T V[:, 0:3],  w = R^T V[:, 3]
-      const int e = tid - 64;
-      if (e < 9) {
-        const int l = e / 3, k = e % 3;
-        m.Q[l][k] = m.g[l] * (m.Hg[k] - m.b[k]) + m.g[4 + l] * (m.Hg[4 + k] - m.b[4 + k]) +
-                    m.g[8 + l] * (m.Hg[8 + k] - m.b[8 + k]);
-      } else {
-        const int l = e - 9;
-        m.w[l] = m.g[l] * (m.Hg[3] - m.b[3]) + m.g[4 + l] * (m.Hg[7] - m.b[7]) +
-                 m.g[8 + l] * (m.Hg[11] - m.b[11]);
-      }
-    }
-    __syncthreads();
-    // gradient and symmetrised Hessian, one entry per thread.  Second-order
-    // term 2 <V, G (E_i E_j + E_j E_i)/2>: rot-rot Q_ij + Q_ji - 2 delta_ij tr Q,
-    // rot i / trans j  w . (e_i x e_j)
-    if (tid < 36) {
-      const int i = tid / 6, j = tid % 6;
-      double t2 = 0.0;
-      if (i < 3 && j < 3) {
-        const double trQ = m.Q[0][0] + m.Q[1][1] + m.Q[2][2];
-        t2 = m.Q[i][j] + m.Q[j][i] - (i == j ? 2.0 * trQ : 0.0);
-      } else if ((i < 3) != (j < 3)) {
-        const int ir = i < 3 ? i : j, jt = (i < 3 ? j : i) - 3;
-        if (ir != jt) {
-          const int k = 3 - ir - jt;
-          t2 = ((jt - ir + 3) % 3 == 1 ? 1.0 : -1.0) * m.w[k];
-        }
-      }
-      const double gn = 0.5 * (m.GN[i][j] + m.GN[j][i]);
-      m.Hgn[i][j] = 2.0 * gn * inv_s2;
-      m.Hs[i][j] = (2.0 * gn + t2) * inv_s2;
-    } else if (tid >= 64 && tid < 70) {
-      const int i = tid - 64;
-      m.grad[i] = i < 3 ? 2.0 * (m.Q[(i + 2) % 3][(i + 1) % 3] - m.Q[(i + 1) % 3][(i + 2) % 3]) *
-                              inv_s2
-                        : 2.0 * m.w[i - 3] * inv_s2;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      if (itn == 0 && mode == 0) {
-        for (int i = 0; i < 6; ++i) s->grad[i] = m.grad[i];
-        for (int i = 0; i < 6; ++i)
-          for (int j = 0; j < 6; ++j) s->hess[6 * i + j] = m.Hs[i][j];
-      }
-      double xi[6];
-      bool ok = chol_solve6(m.Hs, m.grad, xi);
-      if (!ok) {
-        ++gnf;
-        // least squares, as a singular Gauss-Newton matrix (degenerate
-        // inputs) can pass a Cholesky factorisation by rounding alone
-        ok = pinv_solve6(m.Hgn, m.grad, xi);
-      }
-      for (int i = 0; i < 6; ++i) m.xi[i] = ok ? xi[i] : 0.0;
-      m.go = ok ? 1 : 0;
-      m.step = 1.0;
-      m.accept = 0;
-    }
-    __syncthreads();
-    if (m.go != 1) break;
-    // halve the step until D does not grow beyond a rounding allowance.  The
-    // change of D is computed as  dD = d^T (2 (H g - b) + H d),  d = g' - g,
-    // which is exact for the quadratic and free of the cancellation between
-    // the large terms of D itself
-    for (int h = 0; h < 31; ++h) {
-      if (tid == 0) {
-        double xs[6];
-        for (int i = 0; i < 6; ++i) xs[i] = m.step * m.xi[i];
-        compose(m.g, xs, m.gn);
-      }
-      __syncthreads();
-      if (tid < 12) {
-        double hd = 0.0;
-        for (int k = 0; k < 12; ++k) hd = fma(m.H[tid][k], m.gn[k] - m.g[k], hd);
-        rowbuf[tid] = (m.gn[tid] - m.g[tid]) * (2.0 * (m.Hg[tid] - m.b[tid]) + hd);
-      }
-      __syncthreads();
-      if (tid == 0) {
-        double dD = 0.0;
-        for (int r = 0; r < 12; ++r) dD += rowbuf[r];
-        if (dD <= 1e-12 * fabs(m.cur)) {
-          m.accept = 1;
-          m.val = m.cur + dD;
-        } else {
-          m.step *= 0.5;
-        }
-      }
-      __syncthreads();
-      if (m.accept) break;
-    }
-    if (tid == 0) {
-      if (!m.accept) {
-        m.go = 0;
-      } else {
-        double mxs = 0.0;
-        for (int i = 0; i < 6; ++i) mxs = fmax(mxs, fabs(m.step * m.xi[i]));
-        for (int r = 0; r < 12; ++r) m.g[r] = m.gn[r];
-        m.cur = m.val;
-        if (mxs < 1e-12) m.go = 0;
-      }
-    }
-    __syncthreads();
-  }
-  if (tid != 0) return;
-  cur = m.cur;
-  const double s2n = Np > 0.0 ? fmax(cur / (3.0 * Np), sigma2_floor) : sigma2;
-  bool finite = isfinite(s2n);
-  for (int r = 0; r < 12; ++r) finite = finite && isfinite(m.g[r]);
-  s->newton_iters = iters;
-  s->gn_fallbacks += gnf;
-  for (int a = 0; a < 3; ++a) {
-    for (int c = 0; c < 3; ++c) s->R_next[3 * a + c] = m.g[4 * a + c];
-    s->t_next[a] = m.g[4 * a + 3];
-  }
-  s->sigma2_next = s2n;
-  if (mode == 1) {
-    if (!finite) {
-      s->numeric_error = 1;
-      s->done = 1;
-      return;
-    }
-    for (int a = 0; a < 3; ++a) {
-      for (int c = 0; c < 3; ++c) s->R[3 * a + c] = m.g[4 * a + c];
-      s->t[a] = m.g[4 * a + 3];
-    }
-    s->sigma2 = s2n;
-    s->iter += 1;
-  } else if (!finite) {
-    s->numeric_error = 1;
-  }
+  if (tid >= 64) return;
+  mstep_wave(pidx, gridDim.x, S, in, states, traces, trace_stride, evcounts, mode);
 }
 
 // Completes the state after the moments of Y (and X at the initial pose):
@@ -566,6 +774,20 @@ hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *
   hipLaunchKernelGGL(reduce_mstep, dim3((unsigned)pl.npairs), dim3(256), 0, st, bd.slots,
                      (const double *)blockstats, s,
                      nll_trace, trace_stride, evcounts, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
+                           const void *plan_ws, const double *partial, double *blockstats,
+                           double *colS, double *colstats, hipStream_t st) {
+  if (pl.backend == kBackendScalar)
+    hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.fins), dim3(4 * kFinBlock), 0, st,
+                       bd.slots, bd.fin_slot, s, partial, 0, estep_plan_offsets(pl, plan_ws),
+                       blockstats, colS, colstats);
+  else
+    hipLaunchKernelGGL(estep_finalize<false>, dim3((unsigned)pl.fins), dim3(kFinBlock), 0, st,
+                       bd.slots, bd.fin_slot, s, partial, pl.nsplit, (const int *)nullptr,
+                       blockstats, colS, colstats);
   return hipGetLastError();
 }
 
