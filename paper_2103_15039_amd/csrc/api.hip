@@ -57,6 +57,12 @@ constexpr int kMaxBatch = 1 << 16;
 // The set-up of a batch (sorting, neighbour search and records of every
 // cloud: a few small kernels per cloud) runs on this many streams at once.
 constexpr int kSetupLanes = 4;
+// A single pair with at most this many source-target pairs is registered
+// without culling: its E step is too small to fill the GPU either way, and
+// the two plan kernels per iteration (the group boxes and live-tile lists,
+// then the items) cost more than the exact zeros they skip.  The dense plan
+// does not change between iterations and is laid out once.
+constexpr int64_t kDenseAutoPairs = (int64_t)1 << 22;
 
 struct Buf {
   void *p = nullptr;
@@ -503,13 +509,14 @@ lsgcpd_status prof_collect(lsgcpd_ctx *ctx, int64_t evaluated) {
 }
 
 // One E step (plan, accumulation, finalisation) + reduction/M step in
-// `mode`, for every problem of the batch.
+// `mode`, for every problem of the batch.  first: the first E step of the
+// call (a dense plan is laid out only then; a culled one every E step).
 lsgcpd_status run_estep(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::BatchDev &bd,
                         const EstepMem &mem, double *colS, double *colstats, double *trace,
-                        int trace_stride, int mode, hipStream_t st) {
+                        int trace_stride, int mode, hipStream_t st, bool first = true) {
   lsgcpd_status s = LSGCPD_OK;
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
-  HIPCHK(lsg::launch_estep_plan(pl, bd, mem.boxes, mem.state, mem.plan, st));
+  if (first || pl.cull) HIPCHK(lsg::launch_estep_plan(pl, bd, mem.boxes, mem.state, mem.plan, st));
   if (mem.timed && (s = prof_record(ctx, st)) != LSGCPD_OK) return s;
   HIPCHK(lsg::launch_estep_pairs(pl, bd, mem.rec, mem.pts, mem.boxes, mem.ftab, mem.state,
                                  mem.plan, mem.partial, st));
@@ -536,7 +543,7 @@ lsgcpd_status run_em(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Batch
   if (!graph || ctx->prof || max_iter < 1) {
     for (int it = 0; it < max_iter; ++it)
       RETURN_IF(run_estep(ctx, pl, bd, ctx_mem(ctx), nullptr, nullptr, (double *)ctx->trace.p,
-                                stride, 1, st));
+                                stride, 1, st, it == 0));
     return LSGCPD_OK;
   }
   if (!ctx->gstream) {
@@ -565,7 +572,7 @@ lsgcpd_status run_em(lsgcpd_ctx *ctx, const lsg::BatchPlan &pl, const lsg::Batch
     lsgcpd_status s = LSGCPD_OK;
     for (int it = 0; it < max_iter && s == LSGCPD_OK; ++it)
       s = run_estep(ctx, pl, bd, ctx_mem(ctx), nullptr, nullptr, (double *)ctx->trace.p,
-                    stride, 1, gs);
+                    stride, 1, gs, it == 0);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(gs, &g);
     if (s != LSGCPD_OK || e != hipSuccess) {
@@ -675,8 +682,10 @@ lsgcpd_status register_problems(lsgcpd_ctx *ctx, int npairs, const float *const 
   const int backend = backend_of(p->flags);
   if (npairs > 1 && backend != lsg::kBackendScalar)
     return fail(ctx, LSGCPD_E_UNSUPPORTED, "batches use the default pair kernel only");
+  const bool small = npairs == 1 && backend == lsg::kBackendScalar &&
+                     !(p->flags & LSGCPD_BF16_CROSS) && N[0] * M[0] <= kDenseAutoPairs;
   lsg::BatchPlan pl =
-      lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) ? 0 : 1,
+      lsg::batch_plan(npairs, N, M, backend, (p->flags & LSGCPD_DENSE) || small ? 0 : 1,
                       items_for(ctx, npairs, N, M));
   pl.f3 = (p->flags & LSGCPD_BF16_CROSS) && pl.cull ? 1 : 0;
   const int lanes = npairs < kSetupLanes ? npairs : kSetupLanes;

@@ -324,8 +324,8 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
   if (threadIdx.x == 0) counts[b] = base;
 }
 
-// Items of one problem (one block per problem): L tiles each (L a multiple
-// of 4, at least 4), about `target` in all.  Without culling every group
+// Items of one problem (one block per problem): L tiles each (1, 2 or a
+// multiple of 4), about `target` in all.  Without culling every group
 // lists all tiles.  Also clears the problem's counters of evaluated pairs
 // (evcounts[p], and evcounts[npairs + p] for the BF16 matrix-core kernel).
 // Offsets: group g of problem p has its items at off[g_off + p + g] ..
@@ -359,8 +359,13 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
   } else {
     tiles = (int64_t)ngroups * ntiles;
   }
+  // Each wave takes every 4th tile of its item (L a multiple of 4 keeps the
+  // waves even).  Where items of 4 tiles would leave a single problem with
+  // fewer than 512 blocks (two per CU), items of 1 or 2 tiles instead, whose
+  // tiles the block's 4 waves share target by target.
   int64_t L = (tiles + target - 1) / target;
-  L = L < 4 ? 4 : (L + 3) / 4 * 4;
+  const bool few = npairs == 1 && (tiles + 3) / 4 < 512;
+  L = few && L <= 2 ? (L < 1 ? 1 : L) : L < 4 ? 4 : (L + 3) / 4 * 4;
   int run = 0;
   int vmin = 0x7fffffff, vmax = 0;  // items per group
   for (int g0 = 0; g0 < ngroups; g0 += kBlock) {
@@ -473,16 +478,20 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
       bhi1[a] = gbox[9 + a];
     }
   const int Mi = (int)M;  // M < 2^27: 32-bit scalar loop arithmetic
-  // the wave's tiles are j = wave, wave + 4, ...; their indices are fetched 64
-  // at a time, one per lane, and read back with readlane
-  const int nt = kn > wave ? (kn - wave + 3) / 4 : 0;
+  // the wave's tiles are j = wave, wave + 4, ... (items of 1 or 2 tiles:
+  // every tile, and of its targets those with index = wave mod 4); their
+  // indices are fetched 64 at a time, one per lane, and read back with
+  // readlane
+  const bool split = L < 4;
+  const uint64_t sel = split ? 0x1111111111111111ull << wave : ~0ull;
+  const int nt = split ? kn : kn > wave ? (kn - wave + 3) / 4 : 0;
   int tv = 0;
   int done = 0;   // targets this wave evaluated (for every source of the group)
   int done0 = 0, done1 = 0;  // the same for each half of the group (culled)
   if constexpr (CULL) {
     for (int q = 0; q < nt; ++q) {
       if ((q & 63) == 0) {
-        const int jl = wave + 4 * (q + lane);
+        const int jl = split ? q + lane : wave + 4 * (q + lane);
         tv = jl < kn ? tl[jl] : 0;
       }
       const int ti = __builtin_amdgcn_readlane(tv, q & 63);
@@ -497,7 +506,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
         on0 = box_live(p.y, p.y, p.l, blo0, bhi0, sc);
         on1 = box_live(p.y, p.y, p.l, blo1, bhi1, sc);
       }
-      const uint64_t m0 = __ballot(on0), m1 = __ballot(on1);
+      const uint64_t m0 = __ballot(on0) & sel, m1 = __ballot(on1) & sel;
       done0 += __popcll(m0);
       done1 += __popcll(m1);
       const TRec *tr = rec + (int64_t)ti * kCullTile;
@@ -512,16 +521,20 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
     }
   } else {
     for (int q = 0; q < nt; ++q) {
-      if ((q & 63) == 0) tv = k0 + wave + 4 * (q + lane);
+      if ((q & 63) == 0) tv = split ? k0 + q + lane : k0 + wave + 4 * (q + lane);
       const int ti = __builtin_amdgcn_readlane(tv, q & 63);
       const TRec *tr = rec + (int64_t)ti * kCullTile;
       const int n1 = Mi - ti * kCullTile < kCullTile ? Mi - ti * kCullTile : kCullTile;
-      done += n1;
-      int m = 0;
-      // a tile is never empty; a do-while keeps one set of accumulators
-      do {
-        accumulate<S>(x, tr[m], negsc, acc);
-      } while (++m < n1);
+      // targets m0, m0 + dm, ... of the tile; a do-while keeps one set of
+      // accumulators
+      const int m0 = split ? wave : 0, dm = split ? 4 : 1;
+      if (m0 < n1) {
+        done += (n1 - m0 + dm - 1) / dm;
+        int m = m0;
+        do {
+          accumulate<S>(x, tr[m], negsc, acc);
+        } while ((m += dm) < n1);
+      }
     }
   }
   __shared__ int wdone[3][4];

@@ -292,10 +292,11 @@ hipError_t launch_dump_P(const float *X, int64_t N, const TRec *rec, int64_t M, 
 // EM update of the state (pose, sigma2, iteration, convergence).  nll_trace:
 // null or trace_stride doubles per problem.  evcounts (may be null): pairs the
 // pair kernels evaluated, added to s[p].evaluated_pairs, and at npairs + p
-// those of the BF16 kernel (a nonzero count adds one to s[p].f3_steps).
+// those of the BF16 kernel (a nonzero count adds one to s[p].f3_steps);
+// both are cleared for the next E step.
 hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *blockstats,
                                DevState *s, double *nll_trace, int trace_stride,
-                               const unsigned long long *evcounts, int mode, hipStream_t st);
+                               unsigned long long *evcounts, int mode, hipStream_t st);
 
 // ---------------------------------------------------- pose proposal (f2)
 // Encoder parameters (flat float32, see proposal.hip) and the most points

@@ -88,22 +88,30 @@ __device__ __forceinline__ void compose(const double *g, const double xi[6], dou
   }
 }
 
-// Cholesky solve of the 6x6 system A x = -g, factoring the lower triangle
-// of A in place (the upper one is not read); false if A is not positive
-// definite.  One reciprocal per column: the divisions are the long-latency
-// steps of this serial code.
+// 1/d by the hardware reciprocal and two Newton steps (each squares the
+// relative error; the first estimate is good to far better than 2^-20).
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// Solve of the 6x6 system A x = -g by the factorisation A = L D L^T (unit
+// lower L, diagonal D > 0), computed in place in the lower triangle of A
+// (the upper one is not read); false if a pivot is not positive, i.e. A is
+// not positive definite.  One reciprocal per column and no square roots:
+// the long-latency steps of this serial code.
 __device__ __forceinline__ bool chol_solve6(double A[6][6], const double g[6], double x[6]) {
   double inv[6];
   for (int j = 0; j < 6; ++j) {
     double d = A[j][j];
-    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k] * A[k][k];
     if (!(d > 0.0)) return false;
-    const double l = sqrt(d);
-    A[j][j] = l;
-    inv[j] = 1.0 / l;
+    A[j][j] = d;
+    inv[j] = recip(d);
     for (int i = j + 1; i < 6; ++i) {
       double s = A[i][j];
-      for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k];
+      for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k] * A[k][k];
       A[i][j] = s * inv[j];
     }
   }
@@ -111,12 +119,12 @@ __device__ __forceinline__ bool chol_solve6(double A[6][6], const double g[6], d
   for (int i = 0; i < 6; ++i) {
     double s = -g[i];
     for (int k = 0; k < i; ++k) s -= A[i][k] * y[k];
-    y[i] = s * inv[i];
+    y[i] = s;
   }
   for (int i = 5; i >= 0; --i) {
-    double s = y[i];
+    double s = y[i] * inv[i];
     for (int k = i + 1; k < 6; ++k) s -= A[k][i] * x[k];
-    x[i] = s * inv[i];
+    x[i] = s;
   }
   return true;
 }
@@ -411,11 +419,19 @@ __global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slo
 struct MIn {
   double g[12];  // vec(G) = rows of [R | t]
   double sigma2, V, tol, nll_prev, sigma2_floor;
-  int iter, newton_max, N;
+  int iter, newton_max, N, f3_steps;
+  int64_t evaluated_pairs;
+  unsigned long long evc, f3c;  // this E step's evaluated pairs, of them BF16 (or 0)
 };
 
-__device__ __forceinline__ MIn load_min(const DevState *s, int N) {
+__device__ __forceinline__ MIn load_min(const DevState *s, int N,
+                                        const unsigned long long *evcounts, int pidx,
+                                        int npairs) {
   MIn in;
+  in.evaluated_pairs = s->evaluated_pairs;
+  in.f3_steps = s->f3_steps;
+  in.evc = evcounts ? evcounts[pidx] : 0ull;
+  in.f3c = evcounts ? evcounts[npairs + pidx] : 0ull;
   for (int a = 0; a < 3; ++a) {
     for (int c = 0; c < 3; ++c) in.g[4 * a + c] = s->R[3 * a + c];
     in.g[4 * a + 3] = s->t[a];
@@ -440,11 +456,24 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Sum over lanes 0..15 (the others bring 0), the same value on every lane.
+// v of lane l - n within each row of 16 lanes (0 for l mod 16 < n): a DPP
+// row shift (ctrl 0x110 + n) of both halves of the double
+template <int CTRL>
+__device__ __forceinline__ double row_shr(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over lanes 0..15 (lanes 12..15 bring 0): running sums along the row,
+// whose last lane then holds the total, read back as a wave-uniform value.
 __device__ __forceinline__ double sum16(double v) {
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-  return __shfl(v, 0, 64);
+  v += row_shr<0x111>(v);
+  v += row_shr<0x112>(v);
+  v += row_shr<0x114>(v);
+  v += row_shr<0x118>(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 15),
+                          __builtin_amdgcn_readlane(__double2loint(v), 15));
 }
 
 // v[lane] for lane < 12 (a selection, so that v stays in registers)
@@ -469,9 +498,8 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
   const int lane = threadIdx.x & 63;
   __shared__ MSh m;
   if (evcounts && lane == 0) {
-    const unsigned long long evc = evcounts[pidx], f3c = evcounts[npairs + pidx];
-    s->evaluated_pairs += (int64_t)evc;
-    if (f3c) s->f3_steps += 1;
+    s->evaluated_pairs = in.evaluated_pairs + (int64_t)in.evc;
+    if (in.f3c) s->f3_steps = in.f3_steps + 1;
   }
   s->stats[lane] = S[lane];
   if (lane < kStats - 64) s->stats[64 + lane] = S[64 + lane];
@@ -491,16 +519,18 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
   double g[12];
 #pragma unroll
   for (int r = 0; r < 12; ++r) g[r] = in.g[r];
+  // lane r < 12 keeps row r of H and b_r in registers for the whole M step
+  double hrow[12], br = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) hrow[k] = lane < 12 ? m.H[lane][k] : 0.0;
+  if (lane < 12) br = m.b[lane];
   // D(g) = sum_r g_r ((H g)_r - 2 b_r) + c
   double cur;
   {
-    double t = 0.0;
-    if (lane < 12) {
-      double hg = 0.0;
-      for (int k = 0; k < 12; ++k) hg = fma(m.H[lane][k], g[k], hg);
-      t = pick12(g, lane) * (hg - 2.0 * m.b[lane]);
-    }
-    cur = S[82] + sum16(t);
+    double hg = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) hg = fma(hrow[k], g[k], hg);
+    cur = S[82] + sum16(lane < 12 ? pick12(g, lane) * (hg - 2.0 * br) : 0.0);
   }
   const double x2 = kTwoPi * in.sigma2;
   const double inv_s2 = 1.0 / in.sigma2;
@@ -531,26 +561,30 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
   bool go = Np > 0.0;
   for (int itn = 0; itn < in.newton_max && go; ++itn) {
     ++iters;
-    // H J_i and H g.  J_i = vec(G E_i): rotation i -> [R [e_i]x | 0] (in row
-    // a: +g(a, w) at column u, -g(a, u) at column w, (u, w) = (i+1, i+2) mod
-    // 3), translation i -> [0 | R e_i] (g(a, i) at column 3)
-    for (int e = lane; e < 84; e += 64) {
-      if (e < 72) {
-        const int i = e / 12, r = e % 12;
+    // H J_i and H g, lane r < 12 taking row r.  J_i = vec(G E_i): rotation
+    // i -> [R [e_i]x | 0] (in row a: +g(a, w) at column u, -g(a, u) at column
+    // w, (u, w) = (i+1, i+2) mod 3), translation i -> [0 | R e_i] (g(a, i)
+    // at column 3)
+    if (lane < 12) {
+      double hg = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hg = fma(hrow[k], g[k], hg);
+      m.Hg[lane] = hg;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int u = (i + 1) % 3, w = (i + 2) % 3;
         double acc = 0.0;
-        if (i < 3) {
-          const int u = (i + 1) % 3, w = (i + 2) % 3;
-          for (int a = 0; a < 3; ++a)
-            acc = fma(m.H[r][4 * a + u], m.g[4 * a + w], fma(-m.H[r][4 * a + w], m.g[4 * a + u], acc));
-        } else {
-          for (int a = 0; a < 3; ++a) acc = fma(m.H[r][4 * a + 3], m.g[4 * a + i - 3], acc);
-        }
-        m.HJ[i][r] = acc;
-      } else {
-        const int r = e - 72;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          acc = fma(hrow[4 * a + u], g[4 * a + w], fma(-hrow[4 * a + w], g[4 * a + u], acc));
+        m.HJ[i][lane] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
         double acc = 0.0;
-        for (int k = 0; k < 12; ++k) acc = fma(m.H[r][k], m.g[k], acc);
-        m.Hg[r] = acc;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc = fma(hrow[4 * a + 3], g[4 * a + i], acc);
+        m.HJ[3 + i][lane] = acc;
       }
     }
     wave_sync();
@@ -630,7 +664,7 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
     // change of D is computed as  dD = d^T (2 (H g - b) + H d),  d = g' - g,
     // which is exact for the quadratic and free of the cancellation between
     // the large terms of D itself
-    const double vr = lane < 12 ? 2.0 * (m.Hg[lane] - m.b[lane]) : 0.0;
+    const double vr = lane < 12 ? 2.0 * (m.Hg[lane] - br) : 0.0;
     double step = 1.0, gn[12];
     bool accept = false;
     for (int h = 0; h < 31; ++h) {
@@ -640,13 +674,10 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
       double d[12];
 #pragma unroll
       for (int r = 0; r < 12; ++r) d[r] = gn[r] - g[r];
-      double t = 0.0;
-      if (lane < 12) {
-        double hd = 0.0;
-        for (int k = 0; k < 12; ++k) hd = fma(m.H[lane][k], d[k], hd);
-        t = pick12(d, lane) * (vr + hd);
-      }
-      const double dD = sum16(t);
+      double hd = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hd = fma(hrow[k], d[k], hd);
+      const double dD = sum16(lane < 12 ? pick12(d, lane) * (vr + hd) : 0.0);
       if (dD <= 1e-12 * fabs(cur)) {
         accept = true;
         cur += dD;
@@ -697,24 +728,28 @@ __global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slo
                                                     const double *__restrict__ blockstats,
                                                     DevState *__restrict__ states,
                                                     double *__restrict__ traces, int trace_stride,
-                                                    const unsigned long long *__restrict__ evcounts,
+                                                    unsigned long long *__restrict__ evcounts,
                                                     int mode) {
   const int pidx = blockIdx.x, tid = threadIdx.x;
   const DevState *st = states + pidx;
   if (st->done) return;
-  const MIn in = load_min(st, slots[pidx].N);
+  const MIn in = load_min(st, slots[pidx].N, evcounts, pidx, gridDim.x);
+  if (evcounts && tid == 0) {  // read: cleared for the next E step
+    evcounts[pidx] = 0ull;
+    evcounts[gridDim.x + pidx] = 0ull;
+  }
   const int nfin = slots[pidx].nfin, fin_off = slots[pidx].fin_off;
   double stat = 0.0;
   if (tid < kStats) {
     if (nfin <= kFewBlocks) {
-      // the block partials of statistic tid, in order, the loads of 8 in flight
+      // the block partials of statistic tid, in order, the loads of 32 in flight
       const double *row = blockstats + (size_t)kStats * fin_off + (size_t)tid * nfin;
-      for (int b0 = 0; b0 < nfin; b0 += 8) {
-        double v[8];
+      for (int b0 = 0; b0 < nfin; b0 += 32) {
+        double v[32];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = b0 + k < nfin ? row[b0 + k] : 0.0;
+        for (int k = 0; k < 32; ++k) v[k] = b0 + k < nfin ? row[b0 + k] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) stat += v[k];
+        for (int k = 0; k < 32; ++k) stat += v[k];
       }
     } else {
       stat = states[pidx].stats[tid];
@@ -765,7 +800,7 @@ __global__ void init_state(DevState *__restrict__ s, const double *__restrict__ 
 
 hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *blockstats,
                                DevState *s, double *nll_trace, int trace_stride,
-                               const unsigned long long *evcounts, int mode, hipStream_t st) {
+                               unsigned long long *evcounts, int mode, hipStream_t st) {
   bool many = false;
   for (const Slot &sl : pl.slots) many = many || sl.nfin > kFewBlocks;
   if (many)
