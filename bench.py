@@ -17,9 +17,11 @@ Prints one JSON line:
   roofline    = the E-step pair kernel, timed live with HIP events on its
                 stream over a second run of the same K steps (the events
                 are kept out of the steps that give `value`), credited with
-                the 40 FP64 flops it executes per (target, source) pair it
-                evaluates (pairs proven to hold exact-zero exponentials are
-                dropped and not credited), against the 78.6 TFLOP/s FP64
+                the method's 38 flops per (target, source) pair it evaluates
+                (residual 3, squared norm 5, plane term 5, their sum 2, the
+                exponent 2, the normaliser 1, the 10 weighted features 20;
+                pairs proven to hold exact-zero exponentials are dropped and
+                not credited), in FP64, against the 78.6 TFLOP/s FP64
                 vector peak of MI355X; traffic = HBM bytes per launch from the
                 committed rocprofv3 counter summary of the same kernel source
   cpu_baseline= the FP64 C oracle (one full E step of the same pair) on the
@@ -35,7 +37,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_PAIR = 40          # FP64 flops per evaluated (m, n) pair
+FLOPS_PER_PAIR = 38          # the method's flops per evaluated (m, n) pair
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
 EM_ITERS = 50
 

@@ -134,6 +134,44 @@ __device__ __forceinline__ void accumulate1(const Src &x, const TRec &t, double 
   for (int c = 1; c < kFeatUsed; ++c) acc[c] = fma(e, t.f[c - 1], acc[c]);
 }
 
+// The same exponent with both points taken relative to a centre o of the
+// source group (scaled coordinates): u = s_n - o, v = sqrt(c) y_m - o,
+//   z = l_m - |u - v|^2 - (a_m . (u - v))^2
+//     = (l_m - |v|^2) - |u|^2 + u . (2 v) - (a_m . u - a_m . v)^2.
+// Per target the pair kernel stages T = [2 v, l_m - |v|^2, -a_m . v] once
+// per tile; per source it keeps u and |u|^2, so that a pair costs 8 FP64
+// operations for the exponent instead of 10, on values of the size of the
+// group's neighbourhood rather than of the clouds' coordinates.
+struct SrcRel {
+  double u0, u1, u2, uu;
+};
+
+__device__ __forceinline__ double rel_z(const SrcRel &x, const double *T, const double *a) {
+  const double q = fma(x.u0, T[0], fma(x.u1, T[1], fma(x.u2, T[2], T[3] - x.uu)));
+  const double p = fma(a[0], x.u0, fma(a[1], x.u1, fma(a[2], x.u2, T[4])));
+  return fma(-p, p, q);
+}
+
+template <int S>
+__device__ __forceinline__ void accumulate_rel(const SrcRel (&x)[S], const double *T,
+                                               const TRec &t, double (&acc)[S][kFeatUsed]) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double e = exp2_of(rel_z(x[s], T, t.a));
+    acc[s][0] += e;
+#pragma unroll
+    for (int c = 1; c < kFeatUsed; ++c) acc[s][c] = fma(e, t.f[c - 1], acc[s][c]);
+  }
+}
+
+__device__ __forceinline__ void accumulate1_rel(const SrcRel &x, const double *T, const TRec &t,
+                                                double (&acc)[kFeatUsed]) {
+  const double e = exp2_of(rel_z(x, T, t.a));
+  acc[0] += e;
+#pragma unroll
+  for (int c = 1; c < kFeatUsed; ++c) acc[c] = fma(e, t.f[c - 1], acc[c]);
+}
+
 // Exact culling.  For sources whose scaled positions lie in the box
 // [blo, bhi] and targets whose positions lie in [lo, hi] with log-priors
 // <= lmax, every pair has |r|^2 >= d2 = sum_a gap_a^2 (gap_a = distance between
@@ -186,6 +224,9 @@ static_assert(kSrcPerLane == 2, "per-half culling assumes two sources per lane")
 // Per source group: the boxes of its two halves of 64 sources (the sources
 // of slot 0 and slot 1 of the pair kernel's lanes), lo and hi each.
 constexpr int kGBox = 16;
+// Per-target terms of the pair kernel's centred exponent (2 v, l - |v|^2,
+// -a . v, and a pad to keep rows 16-byte aligned).
+constexpr int kRelT = 6;
 // BF16 matrix-core pair kernel (estep_pairs_f3, below): operand types, the
 // feature count of its accumulation, and its exponent error bound: |dz| <=
 // kF3Kappa (1 + alpha_m) (|u| + |v|)^2 (3 products of BF16 halves, each off
@@ -418,6 +459,49 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
   }
 }
 
+// A lane's target of a tile: position, log-prior and plane vector (zeros
+// past the end of the cloud).
+struct TIn {
+  double y[3], l, a[3];
+};
+
+__device__ __forceinline__ TIn load_tin(const TPt *pts, const TRec *rec, int ti, int Mi) {
+  const int m = ti * kCullTile + (int)(threadIdx.x & 63);
+  TIn t = {};
+  if (m < Mi) {
+    const TPt &p = pts[m];
+    for (int a = 0; a < 3; ++a) {
+      t.y[a] = p.y[a];
+      t.a[a] = rec[m].a[a];
+    }
+    t.l = p.l;
+  }
+  return t;
+}
+
+// Lane j < n1 (its target's values in q) stages target j of a tile:
+// T = [2 v, l - |v|^2, -a . v] with v = sqrt(c) y - o.  Made visible to the
+// rest of the wave before return.
+__device__ __forceinline__ void stage_tile(double (*T)[kRelT], const TIn &q, int n1, double sc,
+                                           const double (&o)[3]) {
+  const int lane = threadIdx.x & 63;
+  // the walk over the previous tile's rows is done before they are replaced
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < n1) {
+    const double v0 = fma(sc, q.y[0], -o[0]), v1 = fma(sc, q.y[1], -o[1]),
+                 v2 = fma(sc, q.y[2], -o[2]);
+    T[lane][0] = 2.0 * v0;
+    T[lane][1] = 2.0 * v1;
+    T[lane][2] = 2.0 * v2;
+    T[lane][3] = fma(-v0, v0, fma(-v1, v1, fma(-v2, v2, q.l)));
+    T[lane][4] = -fma(q.a[0], v0, fma(q.a[1], v1, q.a[2] * v2));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool CULL>
 // 4 waves per SIMD (at most 128 VGPRs) hide the scalar-load latency
 __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
@@ -460,10 +544,35 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
   const double sc = sqrt_c_of(st);
-  const double negsc = -sc;
   Src x[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) x[s] = load_src(X, g * kGroup + s * 64 + lane, N, R, t, sc);
+  // the centre: that of the group's box (culled), else the group's first
+  // source (any point of the group bounds |u| by the group's extent)
+  double o[3];
+  if constexpr (CULL) {
+    const bool two = gbox[6] <= gbox[9];  // an empty half has an empty box
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double lo = two ? fmin(gbox[a], gbox[6 + a]) : gbox[a];
+      const double hi = two ? fmax(gbox[3 + a], gbox[9 + a]) : gbox[3 + a];
+      o[a] = 0.5 * (lo + hi);
+    }
+  } else {
+    o[0] = __shfl(x[0].x0, 0, 64);
+    o[1] = __shfl(x[0].x1, 0, 64);
+    o[2] = __shfl(x[0].x2, 0, 64);
+  }
+  SrcRel xr[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    xr[s].u0 = x[s].x0 - o[0];
+    xr[s].u1 = x[s].x1 - o[1];
+    xr[s].u2 = x[s].x2 - o[2];
+    xr[s].uu = fma(xr[s].u0, xr[s].u0, fma(xr[s].u1, xr[s].u1, xr[s].u2 * xr[s].u2));
+  }
+  // the current tile's target terms, one row of kRelT per target (wave-private)
+  __shared__ __align__(16) double trel[4][kCullTile][kRelT];
   double acc[S][kFeatUsed];
 #pragma unroll
   for (int s = 0; s < S; ++s)
@@ -500,24 +609,33 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
       // rule out: one lane per target tests it against both, and the two
       // ballots are (wave-uniform) masks; each half of the lanes' sources
       // takes only its own targets
+      const TIn cur = load_tin(pts, rec, ti, Mi);
       bool on0 = false, on1 = false;
       if (lane < n1) {
-        const TPt &p = pts[(int64_t)ti * kCullTile + lane];
-        on0 = box_live(p.y, p.y, p.l, blo0, bhi0, sc);
-        on1 = box_live(p.y, p.y, p.l, blo1, bhi1, sc);
+        on0 = box_live(cur.y, cur.y, cur.l, blo0, bhi0, sc);
+        on1 = box_live(cur.y, cur.y, cur.l, blo1, bhi1, sc);
       }
       const uint64_t m0 = __ballot(on0) & sel, m1 = __ballot(on1) & sel;
       done0 += __popcll(m0);
       done1 += __popcll(m1);
+      if ((m0 | m1) == 0) continue;
       const TRec *tr = rec + (int64_t)ti * kCullTile;
+      stage_tile(trel[wave], cur, n1, sc, o);
       // targets live for both halves go through the interleaved two-source
       // path (its independent chains keep the FP64 pipeline full), the others
       // through one source each
-      for (uint64_t mk = m0 & m1; mk; mk &= mk - 1) accumulate<S>(x, tr[__builtin_ctzll(mk)], negsc, acc);
-      for (uint64_t mk = m0 & ~m1; mk; mk &= mk - 1)
-        accumulate1(x[0], tr[__builtin_ctzll(mk)], negsc, acc[0]);
-      for (uint64_t mk = m1 & ~m0; mk; mk &= mk - 1)
-        accumulate1(x[1], tr[__builtin_ctzll(mk)], negsc, acc[1]);
+      for (uint64_t mk = m0 & m1; mk; mk &= mk - 1) {
+        const int j = __builtin_ctzll(mk);
+        accumulate_rel<S>(xr, trel[wave][j], tr[j], acc);
+      }
+      for (uint64_t mk = m0 & ~m1; mk; mk &= mk - 1) {
+        const int j = __builtin_ctzll(mk);
+        accumulate1_rel(xr[0], trel[wave][j], tr[j], acc[0]);
+      }
+      for (uint64_t mk = m1 & ~m0; mk; mk &= mk - 1) {
+        const int j = __builtin_ctzll(mk);
+        accumulate1_rel(xr[1], trel[wave][j], tr[j], acc[1]);
+      }
     }
   } else {
     for (int q = 0; q < nt; ++q) {
@@ -529,10 +647,11 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
       // accumulators
       const int m0 = split ? wave : 0, dm = split ? 4 : 1;
       if (m0 < n1) {
+        stage_tile(trel[wave], load_tin(pts, rec, ti, Mi), n1, sc, o);
         done += (n1 - m0 + dm - 1) / dm;
         int m = m0;
         do {
-          accumulate<S>(x, tr[m], negsc, acc);
+          accumulate_rel<S>(xr, trel[wave][m], tr[m], acc);
         } while ((m += dm) < n1);
       }
     }
