@@ -401,12 +401,16 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
     tiles = (int64_t)ngroups * ntiles;
   }
   // Each wave takes every 4th tile of its item (L a multiple of 4 keeps the
-  // waves even).  Where items of 4 tiles would leave a single problem with
-  // fewer than 512 blocks (two per CU), items of 1 or 2 tiles instead, whose
-  // tiles the block's 4 waves share target by target.
+  // waves even), or, in a split item, the block's 4 waves share each tile
+  // target by target (wave w takes targets w, w + 4, ...).  Split, for a
+  // single problem: when its records outgrow an XCD's 4 MB L2 (the waves of
+  // a block then stream one tile instead of four), and where items of 4
+  // tiles would leave fewer than 512 blocks (two per CU).
   int64_t L = (tiles + target - 1) / target;
-  const bool few = npairs == 1 && (tiles + 3) / 4 < 512;
-  L = few && L <= 2 ? (L < 1 ? 1 : L) : L < 4 ? 4 : (L + 3) / 4 * 4;
+  const bool big = npairs == 1 && (int64_t)sl.M * (int64_t)sizeof(TRec) > ((int64_t)4 << 20);
+  const bool few = npairs == 1 && (tiles + 3) / 4 < 512 && L <= 2;
+  const bool split = big || few;
+  L = split ? (L < 1 ? 1 : L) : L < 4 ? 4 : (L + 3) / 4 * 4;
   int run = 0;
   int vmin = 0x7fffffff, vmax = 0;  // items per group
   for (int g0 = 0; g0 < ngroups; g0 += kBlock) {
@@ -454,6 +458,7 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
     hdrs[p].items = run < cap ? run : cap;
     hdrs[p].tiles_per_item = (int)L;
     hdrs[p].uniform = vmin == vmax && run <= cap ? vmax : 0;
+    hdrs[p].split = split ? 1 : 0;
     evcounts[p] = 0ull;           // pairs evaluated
     evcounts[npairs + p] = 0ull;  // of which by the BF16 matrix-core kernel
   }
@@ -591,7 +596,7 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   // every tile, and of its targets those with index = wave mod 4); their
   // indices are fetched 64 at a time, one per lane, and read back with
   // readlane
-  const bool split = L < 4;
+  const bool split = hdrs[p].split != 0;
   const uint64_t sel = split ? 0x1111111111111111ull << wave : ~0ull;
   const int nt = split ? kn : kn > wave ? (kn - wave + 3) / 4 : 0;
   int tv = 0;

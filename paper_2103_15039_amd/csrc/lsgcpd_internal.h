@@ -245,7 +245,7 @@ struct CullHdr {
   int items;           // work items of the problem
   int tiles_per_item;
   int uniform;         // items per group if every group has as many, else 0
-  int pad;
+  int split;           // 1: the 4 waves of a block share each tile of its item
 };
 
 // Plans a batch of sizes N[p], M[p]: work items about target_items in all,
