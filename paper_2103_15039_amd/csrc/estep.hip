@@ -366,8 +366,8 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
   if (threadIdx.x == 0) counts[b] = base;
 }
 
-// Items of one problem (one block per problem): L tiles each (1, 2 or a
-// multiple of 4), about `target` in all.  Without culling every group
+// Items of one problem (one block per problem): L tiles each (a multiple of
+// 4, or any L >= 1 when the items are split), about `target` in all.  Without culling every group
 // lists all tiles.  Also clears the problem's counters of evaluated pairs
 // (evcounts[p], and evcounts[npairs + p] for the BF16 matrix-core kernel).
 // Offsets: group g of problem p has its items at off[g_off + p + g] ..
@@ -593,10 +593,9 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
       bhi1[a] = gbox[9 + a];
     }
   const int Mi = (int)M;  // M < 2^27: 32-bit scalar loop arithmetic
-  // the wave's tiles are j = wave, wave + 4, ... (items of 1 or 2 tiles:
-  // every tile, and of its targets those with index = wave mod 4); their
-  // indices are fetched 64 at a time, one per lane, and read back with
-  // readlane
+  // the wave's tiles are j = wave, wave + 4, ... (split items: every tile,
+  // and of its targets those with index = wave mod 4); their indices are
+  // fetched 64 at a time, one per lane, and read back with readlane
   const bool split = hdrs[p].split != 0;
   const uint64_t sel = split ? 0x1111111111111111ull << wave : ~0ull;
   const int nt = split ? kn : kn > wave ? (kn - wave + 3) / 4 : 0;

@@ -20,7 +20,7 @@
 // of each problem.
 // The M step (mstep_wave) runs the Newton iteration of a problem on one
 // wave, whose lanes share the 12 x 12 products and the entries of the
-// gradient and Hessian, and each of which then takes the 6 x 6 Cholesky solve
+// gradient and Hessian, and each of which then takes the 6 x 6 LDL^T solve
 // and the exponential map itself.
 #include <math.h>
 
@@ -88,8 +88,8 @@ __device__ __forceinline__ void compose(const double *g, const double xi[6], dou
   }
 }
 
-// 1/d by the hardware reciprocal and two Newton steps (each squares the
-// relative error; the first estimate is good to far better than 2^-20).
+// 1/d from the hardware's reciprocal estimate and two Newton steps, each of
+// which squares the relative error.
 __device__ __forceinline__ double recip(double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(r, fma(-d, r, 1.0), r);
@@ -413,9 +413,8 @@ __global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slo
   if (tid == 0) s->stats[i] = r[0];
 }
 
-// Values of the state the M step reads, loaded before anything writes it
-// (every block of the launch loads them; the state changes only in the M
-// step itself).
+// Values of the state the M step reads, loaded together at the start of
+// reduce_mstep, before anything writes the state (only the M step does).
 struct MIn {
   double g[12];  // vec(G) = rows of [R | t]
   double sigma2, V, tol, nll_prev, sigma2_floor;
@@ -447,13 +446,15 @@ __device__ __forceinline__ MIn load_min(const DevState *s, int N,
   return in;
 }
 
-// Orders the LDS stores of one wave's lanes before the loads that follow
-// (the lanes of a wave execute in lockstep; this keeps the compiler from
-// moving memory operations across the point).
+// Orders the LDS stores of one wave's lanes before the loads that follow.
+// A wave's LDS operations are performed in order, so no wait is needed: the
+// wavefront-scope fences only keep the compiler from moving memory
+// operations across the point (a workgroup-scope fence would also wait for
+// the wave's outstanding global stores).
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // v of lane l - n within each row of 16 lanes (0 for l mod 16 < n): a DPP
@@ -474,6 +475,17 @@ __device__ __forceinline__ double sum16(double v) {
   v += row_shr<0x118>(v);
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 15),
                           __builtin_amdgcn_readlane(__double2loint(v), 15));
+}
+
+// sum_k h_k v_k over the 12 entries as three independent chains (one per
+// row of G) added at the end: a quarter of the dependent latency of one chain
+__device__ __forceinline__ double dot12(const double (&h)[12], const double (&v)[12]) {
+  double s[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    s[a] = fma(h[4 * a], v[4 * a], fma(h[4 * a + 1], v[4 * a + 1],
+                                       fma(h[4 * a + 2], v[4 * a + 2], h[4 * a + 3] * v[4 * a + 3])));
+  return (s[0] + s[1]) + s[2];
 }
 
 // v[lane] for lane < 12 (a selection, so that v stays in registers)
@@ -527,9 +539,7 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
   // D(g) = sum_r g_r ((H g)_r - 2 b_r) + c
   double cur;
   {
-    double hg = 0.0;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) hg = fma(hrow[k], g[k], hg);
+    const double hg = dot12(hrow, g);
     cur = S[82] + sum16(lane < 12 ? pick12(g, lane) * (hg - 2.0 * br) : 0.0);
   }
   const double x2 = kTwoPi * in.sigma2;
@@ -566,40 +576,36 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
     // w, (u, w) = (i+1, i+2) mod 3), translation i -> [0 | R e_i] (g(a, i)
     // at column 3)
     if (lane < 12) {
-      double hg = 0.0;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) hg = fma(hrow[k], g[k], hg);
-      m.Hg[lane] = hg;
+      m.Hg[lane] = dot12(hrow, g);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const int u = (i + 1) % 3, w = (i + 2) % 3;
-        double acc = 0.0;
+        double t[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-          acc = fma(hrow[4 * a + u], g[4 * a + w], fma(-hrow[4 * a + w], g[4 * a + u], acc));
-        m.HJ[i][lane] = acc;
+          t[a] = fma(hrow[4 * a + u], g[4 * a + w], -hrow[4 * a + w] * g[4 * a + u]);
+        m.HJ[i][lane] = (t[0] + t[1]) + t[2];
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) acc = fma(hrow[4 * a + 3], g[4 * a + i], acc);
-        m.HJ[3 + i][lane] = acc;
+        m.HJ[3 + i][lane] = fma(hrow[3], g[i], fma(hrow[7], g[4 + i], hrow[11] * g[8 + i]));
       }
     }
     wave_sync();
     // J_i^T H J_j, and Q = R^T V[:, 0:3], w = R^T V[:, 3] with V = H g - b
     if (lane < 36) {
       const int i = lane / 6, j = lane % 6;
-      double acc = 0.0;
+      double t[3];
       if (i < 3) {
         const int u = (i + 1) % 3, w = (i + 2) % 3;
+#pragma unroll
         for (int a = 0; a < 3; ++a)
-          acc = fma(m.g[4 * a + w], m.HJ[j][4 * a + u], fma(-m.g[4 * a + u], m.HJ[j][4 * a + w], acc));
+          t[a] = fma(m.g[4 * a + w], m.HJ[j][4 * a + u], -m.g[4 * a + u] * m.HJ[j][4 * a + w]);
       } else {
-        for (int a = 0; a < 3; ++a) acc = fma(m.g[4 * a + i - 3], m.HJ[j][4 * a + 3], acc);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[a] = m.g[4 * a + i - 3] * m.HJ[j][4 * a + 3];
       }
-      m.GN[i][j] = acc;
+      m.GN[i][j] = (t[0] + t[1]) + t[2];
     } else if (lane < 48) {
       const int e = lane - 36;
       if (e < 9) {
@@ -674,9 +680,7 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
       double d[12];
 #pragma unroll
       for (int r = 0; r < 12; ++r) d[r] = gn[r] - g[r];
-      double hd = 0.0;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) hd = fma(hrow[k], d[k], hd);
+      const double hd = dot12(hrow, d);
       const double dD = sum16(lane < 12 ? pick12(d, lane) * (vr + hd) : 0.0);
       if (dD <= 1e-12 * fabs(cur)) {
         accept = true;
