@@ -249,7 +249,7 @@ constexpr double kF3MaxDz = 1.0 / 32.0;
 // every group's second, ..., so that the blocks resident on an XCD at one
 // time read the same target tiles.  A bijection on the item numbers: only the
 // order of execution changes, not any sum.
-__device__ __forceinline__ int item_order(int i, int nitems, int c) {
+__host__ __device__ __forceinline__ int item_order(int i, int nitems, int c) {
   const int x = i % 8, q = nitems / 8, r = nitems % 8;
   int t = x * q + (x < r ? x : r) + i / 8;
   if (c > 1) {
