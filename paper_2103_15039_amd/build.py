@@ -26,6 +26,10 @@ def command(out=LIB):
              "-fvisibility=hidden", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              # keep MFMA accumulators in VGPRs (no AGPR round trips in the E-step loop)
              "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+             # the first kernel arguments arrive in SGPRs at dispatch (no kernarg load
+             # before a block's first dependent load; code for dispatchers without
+             # preloading loads them itself)
+             "-mllvm", "-amdgpu-kernarg-preload-count=16",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
             + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", out])
 

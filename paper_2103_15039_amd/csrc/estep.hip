@@ -62,14 +62,15 @@ struct Src {
   double x0, x1, x2;  // sqrt(c) * g(x_n)
 };
 
+// Source n (zeros past the end, n >= N).  The load itself is unconditional,
+// from an index clamped to the cloud (N >= 1 wherever a block runs), so that
+// it issues as soon as the address is known.
 __device__ __forceinline__ Src load_src(const float *__restrict__ X, int n, int N,
                                         const double *R, const double *t, double sc) {
-  double x = 0.0, y = 0.0, z = 0.0;
-  if (n < N) {
-    x = X[3 * n];
-    y = X[3 * n + 1];
-    z = X[3 * n + 2];
-  }
+  const int k = n < N ? n : N - 1;
+  const float fx = X[3 * k], fy = X[3 * k + 1], fz = X[3 * k + 2];
+  const double x = n < N ? (double)fx : 0.0, y = n < N ? (double)fy : 0.0,
+               z = n < N ? (double)fz : 0.0;
   Src o;
   o.x0 = sc * fma(R[0], x, fma(R[1], y, fma(R[2], z, t[0])));
   o.x1 = sc * fma(R[3], x, fma(R[4], y, fma(R[5], z, t[1])));
@@ -228,6 +229,20 @@ constexpr int kGBox = 16;
 // Per-target terms of the pair kernel's centred exponent (2 v, l - |v|^2,
 // -a . v, and a pad to keep rows 16-byte aligned).
 constexpr int kRelT = 6;
+// A work item: its source group g and its tiles, positions k0 .. k0 + kn - 1
+// of the group's live-tile list (one 16-byte load for the pair kernels).
+struct __align__(16) Item {
+  int g, k0, kn, pad;
+};
+static_assert(sizeof(CullHdr) == 16, "the plan header is read as one 16-byte load");
+
+// The plan header of problem p in one 16-byte load: its item count decides
+// whether a block has work, its other fields the block's item, so all four
+// arrive together.
+__device__ __forceinline__ CullHdr load_hdr(const CullHdr *h, int p) {
+  const int4 v = reinterpret_cast<const int4 *>(h)[p];
+  return CullHdr{v.x, v.y, v.z, v.w};
+}
 // BF16 matrix-core pair kernel (estep_pairs_f3, below): operand types, the
 // feature count of its accumulation, and its exponent error bound: |dz| <=
 // kF3Kappa (1 + alpha_m) (|u| + |v|)^2 (3 products of BF16 halves, each off
@@ -291,7 +306,7 @@ __device__ bool item_is_f3(const double *gbox, const TBox *bx, const int *tl, in
 // Scaled-coordinate bounding box of each source group (kept for the pair
 // kernel), then the live tiles in increasing order.  One block per group of
 // every problem of the batch.
-__global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ slots,
+__global__ __launch_bounds__(kBlock) void cull_groups(int single, const Slot *__restrict__ slots,
                                                       const int *__restrict__ grp_slot,
                                                       const DevState *__restrict__ states,
                                                       const TBox *__restrict__ boxes,
@@ -299,27 +314,38 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
                                                       double *__restrict__ gbox,
                                                       int *__restrict__ list) {
   const int b = blockIdx.x;
-  const int p = grp_slot[b];
+  const int p = single ? 0 : grp_slot[b];  // one problem: no table lookup
   const DevState *st = states + p;
-  if (st->done) return;
+  // the slot and sigma^2 load with the done flag: every load here is issued
+  // before any arithmetic on its value
   const Slot &sl = slots[p];
-  const int g = b - sl.g_off, N = sl.N, ntiles = sl.ntiles;
+  const int done = st->done;
+  const int g_off = sl.g_off, N = sl.N, ntiles = sl.ntiles, t_off = sl.t_off;
   const float *X = sl.X;
-  const TBox *bx_t = boxes + sl.t_off;
+  const int64_t list_off = sl.list_off;
+  const double s2 = st->sigma2;
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::"s"(done), "s"(g_off), "s"(N), "s"(ntiles), "s"(t_off), "s"(X),
+               "s"(list_off), "s"(s2));
+  if (done) return;
+  const int g = b - g_off;
+  const int n = g * kGroup + threadIdx.x;
+  const bool mine = threadIdx.x < kGroup && n < N;
+  // the source (index clamped to the cloud, N >= 1) and the pose, together
+  const int nc = n < N ? n : N - 1;
+  const float fx = X[3 * nc], fy = X[3 * nc + 1], fz = X[3 * nc + 2];
+  const TBox *bx_t = boxes + t_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double R[9], t[3];
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
-  const double sc = sqrt_c_of(st);
-  const int n = g * kGroup + threadIdx.x;
-  const bool mine = threadIdx.x < kGroup && n < N;
-  const Src x = load_src(X, mine ? n : N, N, R, t, sc);
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (mine) {
-    lo[0] = hi[0] = x.x0;
-    lo[1] = hi[1] = x.x1;
-    lo[2] = hi[2] = x.x2;
-  }
+  const double sc = sqrt(kLog2e / (2.0 * s2));  // sqrt_c_of
+  const double x0 = fx, x1 = fy, x2 = fz;
+  const double c0 = sc * fma(R[0], x0, fma(R[1], x1, fma(R[2], x2, t[0])));
+  const double c1 = sc * fma(R[3], x0, fma(R[4], x1, fma(R[5], x2, t[1])));
+  const double c2 = sc * fma(R[6], x0, fma(R[7], x1, fma(R[8], x2, t[2])));
+  double lo[3] = {mine ? c0 : INFINITY, mine ? c1 : INFINITY, mine ? c2 : INFINITY};
+  double hi[3] = {mine ? c0 : -INFINITY, mine ? c1 : -INFINITY, mine ? c2 : -INFINITY};
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
@@ -348,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
     const int h = threadIdx.x / 6, c = threadIdx.x % 6;
     gbox[(int64_t)b * kGBox + threadIdx.x] = bx[h][c];
   }
-  int *out = list + sl.list_off + (int64_t)g * ntiles;
+  int *out = list + list_off + (int64_t)g * ntiles;
   int base = 0;
   for (int t0 = 0; t0 < ntiles; t0 += kBlock) {
     const int ti = t0 + threadIdx.x;
@@ -367,32 +393,48 @@ __global__ __launch_bounds__(kBlock) void cull_groups(const Slot *__restrict__ s
 }
 
 // Items of one problem (one block per problem): L tiles each (a multiple of
-// 4, or any L >= 1 when the items are split), about `target` in all.  Without culling every group
-// lists all tiles.  Also clears the problem's counters of evaluated pairs
-// (evcounts[p], and evcounts[npairs + p] for the BF16 matrix-core kernel).
-// Offsets: group g of problem p has its items at off[g_off + p + g] ..
-// off[g_off + p + g + 1] - 1 (local to the problem's item range).
+// 4, or any L >= 1 when the items are split), about `target` in all.  Without
+// culling every group lists all tiles.  Also clears the problem's counters of
+// evaluated pairs (evcounts[p], and evcounts[npairs + p] for the BF16
+// matrix-core kernel).  Offsets: group g of problem p has its items at
+// off[g_off + p + g] .. off[g_off + p + g + 1] - 1 (local to the problem's item
+// range); item i of the problem is items[item_off + i].
 template <bool CULL>
 __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ slots,
                                                      const DevState *__restrict__ states,
                                                      const int *__restrict__ counts,
                                                      CullHdr *__restrict__ hdrs,
                                                      int *__restrict__ offs,
-                                                     int *__restrict__ maps,
+                                                     Item *__restrict__ items,
                                                      unsigned long long *__restrict__ evcounts) {
   const int p = blockIdx.x, npairs = gridDim.x;
-  if (states[p].done) return;
+  // the slot loads with the done flag
   const Slot &sl = slots[p];
-  const int ngroups = sl.ngroups, ntiles = sl.ntiles, target = sl.target, cap = sl.item_cap;
-  const int *cnts = CULL ? counts + sl.g_off : nullptr;
-  int *off = offs + sl.g_off + p;
-  int *map = maps + sl.item_off;
+  const int done = states[p].done;
+  const int ngroups = sl.ngroups, ntiles = sl.ntiles, target = sl.target, cap = sl.item_cap,
+            g_off = sl.g_off, item_off = sl.item_off, M = sl.M;
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::"s"(done), "s"(ngroups), "s"(ntiles), "s"(target), "s"(cap), "s"(g_off),
+               "s"(item_off), "s"(M));
+  if (done) return;
+  const int *cnts = CULL ? counts + g_off : nullptr;
+  int *off = offs + g_off + p;
+  Item *its = items + item_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ int64_t red[4];
-  __shared__ int scan[kBlock];
+  __shared__ int wsum[4];
   int64_t tiles = 0;
   if (CULL) {
-    for (int g = threadIdx.x; g < ngroups; g += kBlock) tiles += cnts[g];
+    for (int g0 = 0; g0 < ngroups; g0 += 4 * kBlock) {  // 4 loads in flight
+      int c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = g0 + u * kBlock + (int)threadIdx.x;
+        c[u] = g < ngroups ? cnts[g] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tiles += c[u];
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tiles += __shfl_xor(tiles, o, 64);
     if (lane == 0) red[wave] = tiles;
@@ -408,34 +450,41 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
   // a block then stream one tile instead of four), and where items of 4
   // tiles would leave fewer than 512 blocks (two per CU).
   int64_t L = (tiles + target - 1) / target;
-  const bool big = npairs == 1 && (int64_t)sl.M * (int64_t)sizeof(TRec) > ((int64_t)4 << 20);
+  const bool big = npairs == 1 && (int64_t)M * (int64_t)sizeof(TRec) > ((int64_t)4 << 20);
   const bool few = npairs == 1 && (tiles + 3) / 4 < 512 && L <= 2;
   const bool split = big || few;
   L = split ? (L < 1 ? 1 : L) : L < 4 ? 4 : (L + 3) / 4 * 4;
+  const int Li = (int)L;
   int run = 0;
   int vmin = 0x7fffffff, vmax = 0;  // items per group
   for (int g0 = 0; g0 < ngroups; g0 += kBlock) {
     const int g = g0 + threadIdx.x;
-    const int64_t cnt = g < ngroups ? (CULL ? cnts[g] : ntiles) : 0;
-    const int v = (int)((cnt + L - 1) / L);
+    const int cnt = g < ngroups ? (CULL ? cnts[g] : ntiles) : 0;
+    const int v = (cnt + Li - 1) / Li;
     if (g < ngroups) {
       vmin = v < vmin ? v : vmin;
       vmax = v > vmax ? v : vmax;
     }
-    scan[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < kBlock; d <<= 1) {  // inclusive Hillis-Steele scan
-      const int add = threadIdx.x >= d ? scan[threadIdx.x - d] : 0;
-      __syncthreads();
-      scan[threadIdx.x] += add;
-      __syncthreads();
+    // exclusive prefix of v over the block: within the wave by shuffles,
+    // then the totals of the waves before
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      incl += lane >= d ? y : 0;
     }
-    const int first = run + scan[threadIdx.x] - v;
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int first = run + incl - v;
+    for (int w = 0; w < wave; ++w) first += wsum[w];
     if (g < ngroups) {
       off[g] = first;
-      for (int k = 0; k < v && first + k < cap; ++k) map[first + k] = g;
+      for (int k = 0; k < v && first + k < cap; ++k) {
+        const int k0 = k * Li;
+        its[first + k] = Item{g, k0, cnt - k0 < Li ? cnt - k0 : Li, 0};
+      }
     }
-    run += scan[kBlock - 1];
+    run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
   }
 #pragma unroll
@@ -457,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
     }
     off[ngroups] = run;
     hdrs[p].items = run < cap ? run : cap;
-    hdrs[p].tiles_per_item = (int)L;
+    hdrs[p].tiles_per_item = Li;
     hdrs[p].uniform = vmin == vmax && run <= cap ? vmax : 0;
     hdrs[p].split = split ? 1 : 0;
     evcounts[p] = 0ull;           // pairs evaluated
@@ -509,59 +558,101 @@ __device__ __forceinline__ void stage_tile(double (*T)[kRelT], const TIn &q, int
 }
 
 template <bool CULL>
-// 4 waves per SIMD (at most 128 VGPRs) hide the scalar-load latency
-__global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
-    const Slot *__restrict__ slots, const int *__restrict__ item_slot,
-    const DevState *__restrict__ states, const TRec *__restrict__ recs,
-    const TPt *__restrict__ ptss, const CullHdr *__restrict__ hdrs,
-    const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
-    const int *__restrict__ list, const double *__restrict__ gboxes,
-    const TBox *__restrict__ boxes, int f3,
-    unsigned long long *__restrict__ evcounts, double *__restrict__ partial, int xcd_remap) {
+// 5 waves per SIMD (at most 96 VGPRs; the LDS holds 5 blocks per CU) hide
+// the scalar-load and FP64 latencies
+__global__ __launch_bounds__(kBlock, 5) void estep_pairs_items(
+    int single, const Slot *__restrict__ slots, const int *__restrict__ item_slot,
+    const DevState *__restrict__ states, const CullHdr *__restrict__ hdrs,
+    const Item *__restrict__ items, const TRec *__restrict__ recs,
+    const TPt *__restrict__ ptss, const int *__restrict__ list,
+    const double *__restrict__ gboxes, const TBox *__restrict__ boxes, int f3,
+    unsigned long long *__restrict__ evcounts, double *__restrict__ partial) {
   constexpr int S = kSrcPerLane;
-  const int p = item_slot[blockIdx.x];
+  // one problem (single): p = 0 without a table lookup, and the blocks take
+  // the items in XCD order.  The done flag, the slot and the plan header are
+  // independent loads; the exit test needs all three.  (The arguments the
+  // first loads need come first, where the dispatch can preload them.)
+  const int p = single ? 0 : item_slot[blockIdx.x];
   const DevState *st = states + p;
-  if (st->done) return;
   const Slot &sl = slots[p];
-  const int nitems = hdrs[p].items;
-  int item = blockIdx.x - sl.item_off;
-  if (item >= nitems) return;
-  if (xcd_remap) item = item_order(item, nitems, hdrs[p].uniform);
-  const int b = sl.item_off + item;
+  const int stopped = st->done;
+  const CullHdr hd = load_hdr(hdrs, p);
+  const int item_off = sl.item_off, N = sl.N, ntiles = sl.ntiles, g_off = sl.g_off,
+            t_off = sl.t_off;
+  const int64_t M = sl.M, y_off = sl.y_off, list_off = sl.list_off;
+  // every load above is issued before any arithmetic on its value (see ready_s)
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::"s"(stopped), "s"(item_off), "s"(hd.items), "s"(hd.uniform),
+               "s"(hd.split), "s"(N), "s"(ntiles), "s"(g_off), "s"(t_off), "s"(M), "s"(y_off),
+               "s"(list_off));
+  int item = blockIdx.x - item_off;
+  const float *X = sl.X;
+  const TRec *rec = recs + y_off + p;  // the problem's records, sentinel at rec[M]
+  const TPt *pts = ptss + y_off;
+  if ((stopped != 0) | (item >= hd.items)) return;
+  if (single) item = item_order(item, hd.items, hd.uniform);
+  const Item wi = items[item_off + item];
+  const int b = item_off + item;
   // the wave index is wave-uniform; readfirstlane tells the compiler so, which
   // keeps the tile loop (and so the record loads) scalar
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int N = sl.N, ntiles = sl.ntiles;
-  const int64_t M = sl.M;
-  const float *X = sl.X;
-  const TRec *rec = recs + sl.y_off + p;  // the problem's records, sentinel at rec[M]
-  const TPt *pts = ptss + sl.y_off;
-  const int g = maps[b];
-  const int L = hdrs[p].tiles_per_item;
-  const int k0 = (item - offs[sl.g_off + p + g]) * L;
-  const int cnt = CULL ? counts[sl.g_off + g] : ntiles;
-  const int kn = cnt - k0 < L ? cnt - k0 : L;
-  const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
-  const double *gbox = gboxes + (int64_t)(sl.g_off + g) * kGBox;
-  // an item the BF16 matrix-core kernel takes
-  if (CULL && f3 && item_is_f3(gbox, boxes + sl.t_off, tl, kn)) return;
+  const int g = wi.g, k0 = wi.k0, kn = wi.kn;
+  const int *tl = list + list_off + (int64_t)g * ntiles + k0;
+  const double *gbox = gboxes + (int64_t)(g_off + g) * kGBox;
+  const bool split = hd.split != 0;
+  const int nt = split ? kn : kn > wave ? (kn - wave + 3) / 4 : 0;
+  // Everything the item needs next loads in one round trip: the lane's
+  // sources (index clamped to the cloud), the group's two half boxes, the
+  // pose and the first 64 of the wave's tiles; the scalar values are made
+  // ready before the BF16 kernel's exit test.
+  float xf[S][3];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int n = g * kGroup + s * 64 + lane, k = n < N ? n : N - 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xf[s][c] = X[3 * k + c];
+  }
+  double gb[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) gb[k] = CULL ? gbox[k] : 0.0;
   double R[9], t[3];
+#pragma unroll
   for (int i = 0; i < 9; ++i) R[i] = st->R[i];
+#pragma unroll
   for (int i = 0; i < 3; ++i) t[i] = st->t[i];
-  const double sc = sqrt_c_of(st);
+  const double s2 = st->sigma2;
+  int tv = 0;  // tile indices of the wave, 64 at a time, one per lane
+  if (CULL) {
+    const int jl = split ? lane : wave + 4 * lane;
+    tv = jl < kn ? tl[jl] : 0;
+  }
+  asm volatile("" ::"s"(gb[0]), "s"(gb[1]), "s"(gb[2]), "s"(gb[3]), "s"(gb[4]), "s"(gb[5]),
+               "s"(gb[6]), "s"(gb[7]), "s"(gb[8]), "s"(gb[9]), "s"(gb[10]), "s"(gb[11]));
+  asm volatile("" ::"s"(R[0]), "s"(R[1]), "s"(R[2]), "s"(R[3]), "s"(R[4]), "s"(R[5]), "s"(R[6]),
+               "s"(R[7]), "s"(R[8]), "s"(t[0]), "s"(t[1]), "s"(t[2]), "s"(s2));
+  // an item the BF16 matrix-core kernel takes
+  if (CULL && f3 && item_is_f3(gbox, boxes + t_off, tl, kn)) return;
+  const double sc = sqrt(kLog2e / (2.0 * s2));  // sqrt_c_of
   Src x[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) x[s] = load_src(X, g * kGroup + s * 64 + lane, N, R, t, sc);
+  for (int s = 0; s < S; ++s) {
+    const int n = g * kGroup + s * 64 + lane;
+    const double x0 = n < N ? (double)xf[s][0] : 0.0, x1 = n < N ? (double)xf[s][1] : 0.0,
+                 x2 = n < N ? (double)xf[s][2] : 0.0;
+    x[s].x0 = sc * fma(R[0], x0, fma(R[1], x1, fma(R[2], x2, t[0])));
+    x[s].x1 = sc * fma(R[3], x0, fma(R[4], x1, fma(R[5], x2, t[1])));
+    x[s].x2 = sc * fma(R[6], x0, fma(R[7], x1, fma(R[8], x2, t[2])));
+  }
   // the centre: that of the group's box (culled), else the group's first
   // source (any point of the group bounds |u| by the group's extent)
   double o[3];
   if constexpr (CULL) {
-    const bool two = gbox[6] <= gbox[9];  // an empty half has an empty box
+    const bool two = gb[6] <= gb[9];  // an empty half has an empty box
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double lo = two ? fmin(gbox[a], gbox[6 + a]) : gbox[a];
-      const double hi = two ? fmax(gbox[3 + a], gbox[9 + a]) : gbox[3 + a];
+      const double lo = two ? fmin(gb[a], gb[6 + a]) : gb[a];
+      const double hi = two ? fmax(gb[3 + a], gb[9 + a]) : gb[3 + a];
       o[a] = 0.5 * (lo + hi);
     }
   } else {
@@ -587,24 +678,21 @@ __global__ __launch_bounds__(kBlock, 4) void estep_pairs_items(
   double blo0[3], bhi0[3], blo1[3], bhi1[3];
   if constexpr (CULL)
     for (int a = 0; a < 3; ++a) {
-      blo0[a] = gbox[a];
-      bhi0[a] = gbox[3 + a];
-      blo1[a] = gbox[6 + a];
-      bhi1[a] = gbox[9 + a];
+      blo0[a] = gb[a];
+      bhi0[a] = gb[3 + a];
+      blo1[a] = gb[6 + a];
+      bhi1[a] = gb[9 + a];
     }
   const int Mi = (int)M;  // M < 2^27: 32-bit scalar loop arithmetic
   // the wave's tiles are j = wave, wave + 4, ... (split items: every tile,
   // and of its targets those with index = wave mod 4); their indices are
   // fetched 64 at a time, one per lane, and read back with readlane
-  const bool split = hdrs[p].split != 0;
   const uint64_t sel = split ? 0x1111111111111111ull << wave : ~0ull;
-  const int nt = split ? kn : kn > wave ? (kn - wave + 3) / 4 : 0;
-  int tv = 0;
   int done = 0;   // targets this wave evaluated (for every source of the group)
   int done0 = 0, done1 = 0;  // the same for each half of the group (culled)
   if constexpr (CULL) {
     for (int q = 0; q < nt; ++q) {
-      if ((q & 63) == 0) {
+      if ((q & 63) == 0 && q > 0) {
         const int jl = split ? q + lane : wave + 4 * (q + lane);
         tv = jl < kn ? tl[jl] : 0;
       }
@@ -794,21 +882,25 @@ __device__ __forceinline__ void lifted32(const double (&w)[10], bool target, __b
 // every second tile of the item (starting at w >> 1); the two waves of a half
 // add their sums through LDS in a fixed order.
 __global__ __launch_bounds__(kBlock, 2) void estep_pairs_f3(
-    const Slot *__restrict__ slots, const int *__restrict__ item_slot,
-    const DevState *__restrict__ states, const TRec *__restrict__ recs,
-    const __bf16 *__restrict__ ftabs, const CullHdr *__restrict__ hdrs,
-    const int *__restrict__ counts, const int *__restrict__ offs, const int *__restrict__ maps,
-    const int *__restrict__ list, const double *__restrict__ gboxes,
-    const TBox *__restrict__ boxes, unsigned long long *__restrict__ evcounts,
-    unsigned long long *__restrict__ f3counts, double *__restrict__ partial, int xcd_remap) {
-  const int p = item_slot[blockIdx.x];
+    int single, const Slot *__restrict__ slots, const int *__restrict__ item_slot,
+    const DevState *__restrict__ states, const CullHdr *__restrict__ hdrs,
+    const Item *__restrict__ items, const TRec *__restrict__ recs,
+    const __bf16 *__restrict__ ftabs, const int *__restrict__ list,
+    const double *__restrict__ gboxes, const TBox *__restrict__ boxes,
+    unsigned long long *__restrict__ evcounts, unsigned long long *__restrict__ f3counts,
+    double *__restrict__ partial) {
+  // the same item as the FP64 kernel's block of this index
+  const int p = single ? 0 : item_slot[blockIdx.x];
   const DevState *st = states + p;
-  if (st->done) return;
   const Slot &sl = slots[p];
-  const int nitems = hdrs[p].items;
+  const CullHdr hd = load_hdr(hdrs, p);
+  const int stopped = st->done;
   int item = blockIdx.x - sl.item_off;
-  if (item >= nitems) return;
-  if (xcd_remap) item = item_order(item, nitems, hdrs[p].uniform);
+  ready_s(hd.uniform);
+  ready_s(hd.split);
+  if ((stopped != 0) | (item >= hd.items)) return;
+  if (single) item = item_order(item, hd.items, hd.uniform);
+  const Item wi = items[sl.item_off + item];
   const int b = sl.item_off + item;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -817,11 +909,7 @@ __global__ __launch_bounds__(kBlock, 2) void estep_pairs_f3(
   const int N = sl.N, ntiles = sl.ntiles, Mi = sl.M;
   const TRec *rec = recs + sl.y_off + p;
   const __bf16 *ftab = ftabs + (int64_t)sl.t_off * (2 * kF3Feat * kCullTile);
-  const int g = maps[b];
-  const int L = hdrs[p].tiles_per_item;
-  const int k0 = (item - offs[sl.g_off + p + g]) * L;
-  const int cnt = counts[sl.g_off + g];
-  const int kn = cnt - k0 < L ? cnt - k0 : L;
+  const int g = wi.g, k0 = wi.k0, kn = wi.kn;
   const int *tl = list + sl.list_off + (int64_t)g * ntiles + k0;
   if (!item_is_f3(gboxes + (int64_t)(sl.g_off + g) * kGBox, boxes + sl.t_off, tl, kn)) return;
   const double *hb = gboxes + (int64_t)(sl.g_off + g) * kGBox + 6 * half;
@@ -1397,13 +1485,14 @@ size_t estep_partial_bytes(const BatchPlan &pl) {
 }
 
 // Work-item plan layout: CullHdr[npairs], evaluated-pair counters[2 npairs],
-// counts[groups], off[groups + npairs], map[items], gbox[groups][kGBox],
+// counts[groups], off[groups + npairs], Item[items], gbox[groups][kGBox],
 // list[list_ints].
 namespace {
 struct PlanPtrs {
   CullHdr *hdr;
   unsigned long long *evcount;
-  int *counts, *off, *map, *list;
+  int *counts, *off, *list;
+  Item *items;
   double *gbox;
 };
 PlanPtrs plan_ptrs(const BatchPlan &pl, void *ws) {
@@ -1417,8 +1506,8 @@ PlanPtrs plan_ptrs(const BatchPlan &pl, void *ws) {
   p += align256((size_t)pl.groups * sizeof(int));
   q.off = (int *)p;
   p += align256((size_t)(pl.groups + pl.npairs) * sizeof(int));
-  q.map = (int *)p;
-  p += align256((size_t)pl.items * sizeof(int));
+  q.items = (Item *)p;
+  p += align256((size_t)pl.items * sizeof(Item));
   q.gbox = (double *)p;
   p += align256((size_t)pl.groups * kGBox * sizeof(double));
   q.list = (int *)p;
@@ -1436,7 +1525,7 @@ size_t estep_plan_bytes(const BatchPlan &pl) {
          align256((size_t)2 * pl.npairs * sizeof(unsigned long long)) +
          align256((size_t)pl.groups * sizeof(int)) +
          align256((size_t)(pl.groups + pl.npairs) * sizeof(int)) +
-         align256((size_t)pl.items * sizeof(int)) +
+         align256((size_t)pl.items * sizeof(Item)) +
          align256((size_t)pl.groups * kGBox * sizeof(double)) + (size_t)pl.list_ints * sizeof(int);
 }
 
@@ -1449,13 +1538,14 @@ hipError_t launch_estep_plan(const BatchPlan &pl, const BatchDev &bd, const TBox
   if (pl.backend != kBackendScalar) return hipSuccess;
   const PlanPtrs q = plan_ptrs(pl, plan_ws);
   if (pl.cull) {
-    hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.groups), dim3(kBlock), 0, st, bd.slots,
-                       bd.grp_slot, s, boxes, q.counts, q.gbox, q.list);
+    hipLaunchKernelGGL(cull_groups, dim3((unsigned)pl.groups), dim3(kBlock), 0, st,
+                       pl.npairs == 1 ? 1 : 0, bd.slots, bd.grp_slot, s, boxes, q.counts, q.gbox,
+                       q.list);
     hipLaunchKernelGGL(cull_items<true>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st, bd.slots,
-                       s, q.counts, q.hdr, q.off, q.map, q.evcount);
+                       s, q.counts, q.hdr, q.off, q.items, q.evcount);
   } else {
     hipLaunchKernelGGL(cull_items<false>, dim3((unsigned)pl.npairs), dim3(kBlock), 0, st,
-                       bd.slots, s, q.counts, q.hdr, q.off, q.map, q.evcount);
+                       bd.slots, s, q.counts, q.hdr, q.off, q.items, q.evcount);
   }
   return hipGetLastError();
 }
@@ -1465,20 +1555,20 @@ hipError_t launch_estep_pairs(const BatchPlan &pl, const BatchDev &bd, const TRe
                               void *plan_ws, double *partial, hipStream_t st) {
   if (pl.backend == kBackendScalar) {
     const PlanPtrs q = plan_ptrs(pl, plan_ws);
+    const int single = pl.npairs == 1 ? 1 : 0;
     if (pl.cull) {
       const int f3 = pl.f3 ? 1 : 0;
       hipLaunchKernelGGL(estep_pairs_items<true>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
-                         bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
-                         q.list, q.gbox, boxes, f3, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
+                         single, bd.slots, bd.item_slot, s, q.hdr, q.items, rec, pts, q.list,
+                         q.gbox, boxes, f3, q.evcount, partial);
       if (f3)
-        hipLaunchKernelGGL(estep_pairs_f3, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
-                           bd.slots, bd.item_slot, s, rec, (const __bf16 *)ftab, q.hdr, q.counts,
-                           q.off, q.map, q.list, q.gbox, boxes, q.evcount, q.evcount + pl.npairs,
-                           partial, pl.npairs == 1 ? 1 : 0);
+        hipLaunchKernelGGL(estep_pairs_f3, dim3((unsigned)pl.items), dim3(kBlock), 0, st, single,
+                           bd.slots, bd.item_slot, s, q.hdr, q.items, rec, (const __bf16 *)ftab,
+                           q.list, q.gbox, boxes, q.evcount, q.evcount + pl.npairs, partial);
     } else
       hipLaunchKernelGGL(estep_pairs_items<false>, dim3((unsigned)pl.items), dim3(kBlock), 0, st,
-                         bd.slots, bd.item_slot, s, rec, pts, q.hdr, q.counts, q.off, q.map,
-                         q.list, q.gbox, boxes, 0, q.evcount, partial, pl.npairs == 1 ? 1 : 0);
+                         single, bd.slots, bd.item_slot, s, q.hdr, q.items, rec, pts, q.list,
+                         q.gbox, boxes, 0, q.evcount, partial);
     return hipGetLastError();
   }
   // one problem: its records start at rec + 0

@@ -85,6 +85,18 @@ struct DevState {
   int32_t pad;
 };
 
+// Makes v ready at this point: an empty asm that takes v as an operand, so
+// the load that produces v is issued and waited for before it.  A few of
+// these before a block's exit test (its problem is done) keep the loads the
+// block needs next in the same memory round trip as the test's own load; the
+// compiler would otherwise issue them after the test, one round trip later.
+// The "s" forms are for wave-uniform values.
+__device__ __forceinline__ void ready_s(int v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void ready_s(long long v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void ready_s(double v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void ready_s(const void *v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void ready_v(double v) { asm volatile("" ::"v"(v)); }
+
 // gamma = (2 pi sigma^2)^{3/2} / V: the outlier term of the posterior's
 // denominator relative to the component normaliser (Eq. 9)
 __device__ inline double gamma_of(const DevState *s) {
@@ -241,7 +253,7 @@ struct BatchDev {
 };
 
 // Written on the device by each E step of the scalar back end, per problem.
-struct CullHdr {
+struct alignas(16) CullHdr {
   int items;           // work items of the problem
   int tiles_per_item;
   int uniform;         // items per group if every group has as many, else 0

@@ -235,19 +235,51 @@ __device__ __forceinline__ int tri4(int i, int j) {
 // chunk ([chunk][feature][N], one problem), one wave per block.  Block b
 // belongs to problem fin_slot[b]; its statistics go to the problem's
 // stat-major rows (row i of problem p: blockstats[kStats fin_off + i nfin ..]).
+static_assert(kGroup % kFinBlock == 0, "a finalisation block lies in one source group");
+
 template <bool ITEMS>
 __device__ void finalize_block(const Slot &sl, int ps, const DevState *__restrict__ st,
-                               const double *__restrict__ partial, int nsplit,
+                               int single, const double *__restrict__ partial, int nsplit,
                                const int *__restrict__ offs, double *__restrict__ blockstats,
                                double *__restrict__ colS, double *__restrict__ colstats) {
-  const int N = sl.N;
+  // One problem (single): every offset of its slot is 0, so the item range
+  // of the block's source group loads with the done flag and the slot.  (A
+  // block lies in one group; the group's item count has an entry for every
+  // block of the problem.)
+  const int done = st->done;
+  const int N = sl.N, nfin = sl.nfin;
   const float *X = sl.X;
   const float *w = sl.w;
   const float *phi = sl.phi;
-  const int fb = blockIdx.x - sl.fin_off;
+  const int64_t x_off = sl.x_off;
+  int fin_off = 0, i0 = 0, i1 = 0;
+  if (single) {
+    if (ITEMS) {
+      const int g = blockIdx.x * kFinBlock / kGroup;
+      i0 = offs[g];
+      i1 = offs[g + 1];
+    }
+  } else {
+    fin_off = sl.fin_off;
+    if (ITEMS) {
+      const int g = (blockIdx.x - fin_off) * kFinBlock / kGroup;
+      const int *off = offs + sl.g_off + ps;
+      i0 = sl.item_off + off[g];
+      i1 = sl.item_off + off[g + 1];
+    }
+  }
+  // every load above is issued before any arithmetic on its value
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::"s"(done), "s"(N), "s"(nfin), "s"(X), "s"(fin_off), "s"(i0), "s"(i1));
+  if (done) return;
+  const int fb = blockIdx.x - fin_off;
   const int l = threadIdx.x & (kFinBlock - 1);
   const int part = threadIdx.x / kFinBlock;  // 0 without ITEMS
   const int n = fb * kFinBlock + l;
+  // the source's coordinates, with the partial sums (index clamped to the
+  // cloud, N >= 1)
+  const int nc = n < N ? n : N - 1;
+  const float fx = X[3 * nc], fy = X[3 * nc + 1], fz = X[3 * nc + 2];
   double p = 0.0, W[6] = {0, 0, 0, 0, 0, 0}, B[3] = {0, 0, 0}, C = 0.0, lg = 0.0, outl = 0.0,
          logw = 0.0;
   double xt[4] = {0.0, 0.0, 0.0, 0.0};
@@ -257,10 +289,8 @@ __device__ void finalize_block(const Slot &sl, int ps, const DevState *__restric
   if (ITEMS) {
     if (n < N) {
       // this wave's items in increasing order, the loads of 4 issued together
-      const int g = n / kGroup, j = n % kGroup;
-      const int *off = offs + sl.g_off + ps;
-      const int i1 = sl.item_off + off[g + 1];
-      int it = sl.item_off + off[g] + part;
+      const int j = n % kGroup;
+      int it = i0 + part;
       for (; it + 12 < i1; it += 16) {
         double v[4][kFeatUsed];
 #pragma unroll
@@ -308,9 +338,9 @@ __device__ void finalize_block(const Slot &sl, int ps, const DevState *__restric
     lg = log(den + gam);
     outl = gam * inv;
     logw = log(wn);
-    if (colS) colS[sl.x_off + n] = T[0];
+    if (colS) colS[x_off + n] = T[0];
     if (colstats) {
-      double *cs = colstats + (size_t)(sl.x_off + n) * kColStats;
+      double *cs = colstats + (size_t)(x_off + n) * kColStats;
       cs[0] = T[0];
       cs[1] = den;
       cs[2] = p;
@@ -321,9 +351,9 @@ __device__ void finalize_block(const Slot &sl, int ps, const DevState *__restric
       cs[14] = outl;
       cs[15] = 0.0;
     }
-    xt[0] = (double)X[3 * n];
-    xt[1] = (double)X[3 * n + 1];
-    xt[2] = (double)X[3 * n + 2];
+    xt[0] = (double)fx;
+    xt[1] = (double)fy;
+    xt[2] = (double)fz;
     xt[3] = 1.0;
   }
   double xx[10];
@@ -357,22 +387,22 @@ __device__ void finalize_block(const Slot &sl, int ps, const DevState *__restric
   for (int i = threadIdx.x; i < kStats; i += blockDim.x) {
     double s = 0.0;
     for (int k = 0; k < kFinBlock; ++k) s += red[i][k];
-    blockstats[(size_t)kStats * sl.fin_off + (size_t)i * sl.nfin + fb] = s;  // stat-major
+    blockstats[(size_t)kStats * fin_off + (size_t)i * nfin + fb] = s;  // stat-major
   }
 }
 
 // Test aid: writes P (M x N, float32) from the same per-pair exponent.
 
+// single: the batch is one problem (p = 0 without a table lookup).
 template <bool ITEMS>
 __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
-    const Slot *__restrict__ slots, const int *__restrict__ fin_slot,
-    const DevState *__restrict__ states, const double *__restrict__ partial, int nsplit,
-    const int *__restrict__ offs, double *__restrict__ blockstats, double *__restrict__ colS,
-    double *__restrict__ colstats) {
-  const int ps = fin_slot[blockIdx.x];
-  const DevState *st = states + ps;
-  if (st->done) return;
-  finalize_block<ITEMS>(slots[ps], ps, st, partial, nsplit, offs, blockstats, colS, colstats);
+    int single, const Slot *__restrict__ slots, const int *__restrict__ fin_slot,
+    const DevState *__restrict__ states, const int *__restrict__ offs,
+    const double *__restrict__ partial, int nsplit, double *__restrict__ blockstats,
+    double *__restrict__ colS, double *__restrict__ colstats) {
+  const int ps = single ? 0 : fin_slot[blockIdx.x];
+  finalize_block<ITEMS>(slots[ps], ps, states + ps, single, partial, nsplit, offs, blockstats,
+                        colS, colstats);
 }
 
 // Problems with at most this many finalisation blocks (64 sources each) are
@@ -384,24 +414,38 @@ constexpr int kFewBlocks = 64;
 // statistic and problem, so that the reads are spread over many CUs): thread
 // t adds the partials t, t + 256, ... in order, then a fixed tree adds the
 // threads.  The result does not depend on timing.
-__global__ __launch_bounds__(256) void reduce_stats(const Slot *__restrict__ slots,
+// nfin1: the block count of the batch's only problem (its rows then start at
+// 0, and the first partials load with the done flag), 0 for a batch.
+__global__ __launch_bounds__(256) void reduce_stats(int nfin1, const Slot *__restrict__ slots,
                                                      const double *__restrict__ blockstats,
                                                      DevState *__restrict__ states) {
   const int p = blockIdx.x / kStats, i = blockIdx.x % kStats, tid = threadIdx.x;
   DevState *s = states + p;
-  const int nblk = slots[p].nfin;
-  if (s->done || nblk <= kFewBlocks) return;  // reduce_mstep sums those itself
-  const double *row = blockstats + (size_t)kStats * slots[p].fin_off + (size_t)i * nblk;
+  const int done = s->done;
+  const int nblk = nfin1 ? nfin1 : slots[p].nfin;
+  const double *row =
+      blockstats + (nfin1 ? (size_t)0 : (size_t)kStats * slots[p].fin_off) + (size_t)i * nblk;
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int b = k * 256 + tid;
+    v[k] = b < nblk ? row[b] : 0.0;
+  }
+  ready_s(done);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ready_v(v[k]);
+  if (done || nblk <= kFewBlocks) return;  // reduce_mstep sums those itself
   double a = 0.0;
-  for (int c0 = 0; c0 < nblk; c0 += 8 * 256) {
-    double v[8];
+  for (int c0 = 0;;) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a += v[k];
+    c0 += 8 * 256;
+    if (c0 >= nblk) break;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int b = c0 + k * 256 + tid;
       v[k] = b < nblk ? row[b] : 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a += v[k];
   }
   __shared__ double r[256];
   r[tid] = a;
@@ -444,6 +488,24 @@ __device__ __forceinline__ MIn load_min(const DevState *s, int N,
   in.newton_max = s->newton_max;
   in.N = N;
   return in;
+}
+
+// Every value of `in` ready (loaded) at this point.
+__device__ __forceinline__ void ready_min(const MIn &in) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) ready_s(in.g[k]);
+  ready_s(in.sigma2);
+  ready_s(in.V);
+  ready_s(in.tol);
+  ready_s(in.nll_prev);
+  ready_s(in.sigma2_floor);
+  ready_s(in.iter);
+  ready_s(in.newton_max);
+  ready_s(in.N);
+  ready_s(in.f3_steps);
+  ready_s((long long)in.evaluated_pairs);
+  ready_s((long long)in.evc);
+  ready_s((long long)in.f3c);
 }
 
 // Orders the LDS stores of one wave's lanes before the loads that follow.
@@ -727,43 +789,60 @@ __device__ void mstep_wave(int pidx, int npairs, const double *S, const MIn &in,
 }
 
 // The M step from the block statistics: summed here for problems with few
-// finalisation blocks, else by reduce_stats into s->stats.
-__global__ __launch_bounds__(256) void reduce_mstep(const Slot *__restrict__ slots,
+// finalisation blocks, else by reduce_stats into s->stats.  ONE: the batch is
+// one problem, of nfin1 blocks (its rows start at 0, so its first partials
+// load with the done flag and the state).
+template <bool ONE>
+__global__ __launch_bounds__(256) void reduce_mstep(int nfin1, const Slot *__restrict__ slots,
                                                     const double *__restrict__ blockstats,
                                                     DevState *__restrict__ states,
                                                     double *__restrict__ traces, int trace_stride,
                                                     unsigned long long *__restrict__ evcounts,
                                                     int mode) {
   const int pidx = blockIdx.x, tid = threadIdx.x;
+  const int npairs = ONE ? 1 : (int)gridDim.x;
   const DevState *st = states + pidx;
-  if (st->done) return;
-  const MIn in = load_min(st, slots[pidx].N, evcounts, pidx, gridDim.x);
+  const int done = st->done;
+  const MIn in = load_min(st, slots[pidx].N, evcounts, pidx, npairs);
+  const int nfin = ONE ? nfin1 : slots[pidx].nfin;
+  const int fin_off = ONE ? 0 : slots[pidx].fin_off;
+  // statistic tid: its first 32 block partials in order (few blocks), else
+  // the sum reduce_stats left in the state
+  const bool few = nfin <= kFewBlocks;
+  const double *row = blockstats + (size_t)kStats * fin_off + (size_t)tid * nfin;
+  double v[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) v[k] = tid < kStats && few && k < nfin ? row[k] : 0.0;
+  const double summed = tid < kStats && !few ? states[pidx].stats[tid] : 0.0;
+  // every load above is issued before any arithmetic on its value
+  __builtin_amdgcn_sched_barrier(0);
+  ready_s(done);
+  ready_min(in);
+#pragma unroll
+  for (int k = 0; k < 32; ++k) ready_v(v[k]);
+  ready_v(summed);
+  if (done) return;
   if (evcounts && tid == 0) {  // read: cleared for the next E step
     evcounts[pidx] = 0ull;
-    evcounts[gridDim.x + pidx] = 0ull;
+    evcounts[npairs + pidx] = 0ull;
   }
-  const int nfin = slots[pidx].nfin, fin_off = slots[pidx].fin_off;
-  double stat = 0.0;
-  if (tid < kStats) {
-    if (nfin <= kFewBlocks) {
-      // the block partials of statistic tid, in order, the loads of 32 in flight
-      const double *row = blockstats + (size_t)kStats * fin_off + (size_t)tid * nfin;
-      for (int b0 = 0; b0 < nfin; b0 += 32) {
-        double v[32];
+  double stat = summed;
+  if (tid < kStats && few) {
+    // the rest of the partials, the loads of 32 in flight
+    for (int b0 = 0;;) {
 #pragma unroll
-        for (int k = 0; k < 32; ++k) v[k] = b0 + k < nfin ? row[b0 + k] : 0.0;
+      for (int k = 0; k < 32; ++k) stat += v[k];
+      b0 += 32;
+      if (b0 >= nfin) break;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) stat += v[k];
-      }
-    } else {
-      stat = states[pidx].stats[tid];
+      for (int k = 0; k < 32; ++k) v[k] = b0 + k < nfin ? row[b0 + k] : 0.0;
     }
   }
   __shared__ double S[kStats];
   if (tid < kStats) S[tid] = stat;
   __syncthreads();
   if (tid >= 64) return;
-  mstep_wave(pidx, gridDim.x, S, in, states, traces, trace_stride, evcounts, mode);
+  mstep_wave(pidx, npairs, S, in, states, traces, trace_stride, evcounts, mode);
 }
 
 // Completes the state after the moments of Y (and X at the initial pose):
@@ -807,25 +886,31 @@ hipError_t launch_reduce_mstep(const BatchPlan &pl, const BatchDev &bd, double *
                                unsigned long long *evcounts, int mode, hipStream_t st) {
   bool many = false;
   for (const Slot &sl : pl.slots) many = many || sl.nfin > kFewBlocks;
+  const int nfin1 = pl.npairs == 1 ? pl.slots[0].nfin : 0;
   if (many)
     hipLaunchKernelGGL(reduce_stats, dim3((unsigned)(kStats * pl.npairs)), dim3(256), 0, st,
-                       bd.slots, blockstats, s);
-  hipLaunchKernelGGL(reduce_mstep, dim3((unsigned)pl.npairs), dim3(256), 0, st, bd.slots,
-                     (const double *)blockstats, s,
-                     nll_trace, trace_stride, evcounts, mode);
+                       nfin1, bd.slots, blockstats, s);
+  if (nfin1)
+    hipLaunchKernelGGL(reduce_mstep<true>, dim3(1), dim3(256), 0, st, nfin1, bd.slots,
+                       (const double *)blockstats, s, nll_trace, trace_stride, evcounts, mode);
+  else
+    hipLaunchKernelGGL(reduce_mstep<false>, dim3((unsigned)pl.npairs), dim3(256), 0, st, 0,
+                       bd.slots, (const double *)blockstats, s, nll_trace, trace_stride, evcounts,
+                       mode);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const BatchPlan &pl, const BatchDev &bd, const DevState *s,
                            const void *plan_ws, const double *partial, double *blockstats,
                            double *colS, double *colstats, hipStream_t st) {
+  const int single = pl.npairs == 1 ? 1 : 0;
   if (pl.backend == kBackendScalar)
     hipLaunchKernelGGL(estep_finalize<true>, dim3((unsigned)pl.fins), dim3(4 * kFinBlock), 0, st,
-                       bd.slots, bd.fin_slot, s, partial, 0, estep_plan_offsets(pl, plan_ws),
-                       blockstats, colS, colstats);
+                       single, bd.slots, bd.fin_slot, s, estep_plan_offsets(pl, plan_ws), partial,
+                       0, blockstats, colS, colstats);
   else
     hipLaunchKernelGGL(estep_finalize<false>, dim3((unsigned)pl.fins), dim3(kFinBlock), 0, st,
-                       bd.slots, bd.fin_slot, s, partial, pl.nsplit, (const int *)nullptr,
+                       single, bd.slots, bd.fin_slot, s, (const int *)nullptr, partial, pl.nsplit,
                        blockstats, colS, colstats);
   return hipGetLastError();
 }
