@@ -1,6 +1,7 @@
 """GPU parity of batched registration (lsgcpd_register_batch): every pair of
 a batch against the same pair registered alone, and against the FP64 oracle
-on small pairs.
+(small pairs, and a batch of scene pairs of the batch workload's kind against
+the oracle driven by its C E step).
 
 Bar: against the single-pair call, the same iterations and convergence, and
 poses and sigma^2 equal up to the grouping of the sums (rotation <= 1e-6 deg,
@@ -83,6 +84,31 @@ def test_batch_against_oracle():
         assert b.iters == o.iters
         assert O.rotation_error_deg(b.R, o.R) <= 1e-3
         assert O.translation_error(b.t, o.t) <= 1e-5 * O.bbox_diag(p.Y)
+        assert b.sigma2 == pytest.approx(o.sigma2, rel=1e-3)
+
+
+def test_batch_of_scene_pairs_against_c_oracle():
+    """Pairs of the batch workload's kind (box, sphere and plane scenes, source
+    rotations up to 60 deg, up to 10 % outliers, M and N log-uniform in
+    [1,000, 3,000]; two of these four end in a wrong local optimum, which the
+    oracle's registration reaches as well) registered in one batch, each against
+    the oracle's registration driven by the C E step with the oracle's own
+    normals: the same iterations, rotation <= 1e-3 deg, translation <= 1e-5 x
+    box diagonal."""
+    from oracle import c_oracle as CO
+    pairs = datagen.batch_pairs(4, trial=11, nmin=1000, nmax=3000)
+    k, iters = 10, 25
+    res = L.register_batch([(dev(p.X), dev(p.Y)) for p in pairs], k=k, max_iter=iters)
+    for p, b in zip(pairs, res):
+        n, kappa, _, _ = O.local_geometry(p.Y, CO.knn_indices(p.Y, k))
+        a = O.penalty_alpha(kappa, 30.0, 0.2)
+        V = O.working_volume(p.Y)
+        o = O.register(p.X, p.Y, k=k, max_iter=iters, target_normals=n, target_alpha=a, V=V,
+                       sigma2_0=CO.sigma2_init(p.X, p.Y, np.eye(3), np.zeros(3)),
+                       estep_columns=CO.register_columns_fn(p.X, p.Y, n, a, 0.1, V))
+        assert b.iters == o.iters == iters
+        assert O.rotation_error_deg(b.R, o.R) <= 1e-3, p.name
+        assert O.translation_error(b.t, o.t) <= 1e-5 * O.bbox_diag(p.Y), p.name
         assert b.sigma2 == pytest.approx(o.sigma2, rel=1e-3)
 
 
