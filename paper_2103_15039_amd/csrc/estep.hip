@@ -236,9 +236,8 @@ struct __align__(16) Item {
 };
 static_assert(sizeof(CullHdr) == 16, "the plan header is read as one 16-byte load");
 
-// The plan header of problem p in one 16-byte load: its item count decides
-// whether a block has work, its other fields the block's item, so all four
-// arrive together.
+// The plan header of problem p, read as one 16-byte vector: its item count
+// decides whether a block has work, its other fields the block's item.
 __device__ __forceinline__ CullHdr load_hdr(const CullHdr *h, int p) {
   const int4 v = reinterpret_cast<const int4 *>(h)[p];
   return CullHdr{v.x, v.y, v.z, v.w};

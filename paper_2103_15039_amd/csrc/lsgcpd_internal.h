@@ -86,11 +86,14 @@ struct DevState {
 };
 
 // Makes v ready at this point: an empty asm that takes v as an operand, so
-// the load that produces v is issued and waited for before it.  A few of
-// these before a block's exit test (its problem is done) keep the loads the
-// block needs next in the same memory round trip as the test's own load; the
+// the load that produces v is issued and waited for before it.  Before a
+// block's exit test (its problem is done) this keeps the loads the block
+// needs next in the same memory round trip as the test's own load; the
 // compiler would otherwise issue them after the test, one round trip later.
-// The "s" forms are for wave-uniform values.
+// Where several values must arrive together, the kernels put them in one such
+// asm after a scheduling barrier (__builtin_amdgcn_sched_barrier(0)), so that
+// every load is issued before any arithmetic waits on one of them.  The "s"
+// forms are for wave-uniform values.
 __device__ __forceinline__ void ready_s(int v) { asm volatile("" ::"s"(v)); }
 __device__ __forceinline__ void ready_s(long long v) { asm volatile("" ::"s"(v)); }
 __device__ __forceinline__ void ready_s(double v) { asm volatile("" ::"s"(v)); }

@@ -391,8 +391,6 @@ __device__ void finalize_block(const Slot &sl, int ps, const DevState *__restric
   }
 }
 
-// Test aid: writes P (M x N, float32) from the same per-pair exponent.
-
 // single: the batch is one problem (p = 0 without a table lookup).
 template <bool ITEMS>
 __global__ __launch_bounds__(4 * kFinBlock) void estep_finalize(
