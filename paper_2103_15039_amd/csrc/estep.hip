@@ -231,8 +231,12 @@ constexpr int kGBox = 16;
 constexpr int kRelT = 6;
 // A work item: its source group g and its tiles, positions k0 .. k0 + kn - 1
 // of the group's live-tile list (one 16-byte load for the pair kernels).
+// full: no tile of the target cloud was ruled out for the group (large
+// sigma^2); the FP64 pair kernel then takes every target of the item's tiles
+// without its per-target test.  That is exact either way: a target the test
+// would have dropped only adds exponentials that are exact zeros.
 struct __align__(16) Item {
-  int g, k0, kn, pad;
+  int g, k0, kn, full;
 };
 static_assert(sizeof(CullHdr) == 16, "the plan header is read as one 16-byte load");
 
@@ -480,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void cull_items(const Slot *__restrict__ sl
       off[g] = first;
       for (int k = 0; k < v && first + k < cap; ++k) {
         const int k0 = k * Li;
-        its[first + k] = Item{g, k0, cnt - k0 < Li ? cnt - k0 : Li, 0};
+        its[first + k] = Item{g, k0, cnt - k0 < Li ? cnt - k0 : Li, CULL && cnt == ntiles};
       }
     }
     run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
@@ -674,6 +678,8 @@ __global__ __launch_bounds__(kBlock, 5) void estep_pairs_items(
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int c = 0; c < kFeatUsed; ++c) acc[s][c] = 0.0;
+  const bool full = CULL && wi.full != 0;
+  const bool two1 = gb[6] <= gb[9];  // the group's second half holds sources
   double blo0[3], bhi0[3], blo1[3], bhi1[3];
   if constexpr (CULL)
     for (int a = 0; a < 3; ++a) {
@@ -704,8 +710,13 @@ __global__ __launch_bounds__(kBlock, 5) void estep_pairs_items(
       const TIn cur = load_tin(pts, rec, ti, Mi);
       bool on0 = false, on1 = false;
       if (lane < n1) {
-        on0 = box_live(cur.y, cur.y, cur.l, blo0, bhi0, sc);
-        on1 = box_live(cur.y, cur.y, cur.l, blo1, bhi1, sc);
+        if (full) {  // every target (half 1 only if it holds sources)
+          on0 = true;
+          on1 = two1;
+        } else {
+          on0 = box_live(cur.y, cur.y, cur.l, blo0, bhi0, sc);
+          on1 = box_live(cur.y, cur.y, cur.l, blo1, bhi1, sc);
+        }
       }
       const uint64_t m0 = __ballot(on0) & sel, m1 = __ballot(on1) & sel;
       done0 += __popcll(m0);
