@@ -204,14 +204,16 @@ __device__ __forceinline__ bool box_live(const double *lo, const double *hi, dou
 //    box_live cannot rule out (with culling off: every tile);
 //  * cull_items (one block per problem) cuts every group's list into items
 //    of L tiles, with L chosen so that there are at most about `target` items
-//    in all, and writes the item -> group map;
+//    in all, and writes one descriptor per item (group, first tile, tile
+//    count, and whether the group kept every tile);
 //  * estep_pairs_items runs one block per item: the 4 waves hold the same 128
 //    sources and take every 4th tile of the item (in a split item: every
 //    tile, and of its targets every 4th).  Per tile, one lane per target
-//    tests the target against the group box, stages its centred terms in the
-//    wave's LDS, and the wave walks the set bits of the resulting 64-bit
-//    mask.  The 4 waves' sums are added through LDS in a fixed order and the
-//    block writes one partial per source and feature.
+//    tests the target against the group box (not in an item whose group kept
+//    every tile), stages its centred terms in the wave's LDS, and the wave
+//    walks the set bits of the resulting 64-bit mask.  The 4 waves' sums are
+//    added through LDS in a fixed order and the block writes one partial per
+//    source and feature.
 // Groups near much of the target cloud get many items and isolated ones few,
 // so the blocks carry about equal work whatever the culling removes.  All
 // counts are integers and every sum runs in a fixed order, so results are
